@@ -1,0 +1,158 @@
+/*
+ * mdgemm: m-double matrix product by error-free summation on one MI355X.
+ *
+ * An m-double is an unevaluated sum of m nonoverlapping doubles (paper,
+ * Section 1).  C = A B is computed the way the paper computes m-double inner
+ * products (Section 2, Figure 1, and the convolutions of the Conclusions):
+ *
+ *   1. every row i of A and every column j of B gets a shared exponent E_i,
+ *      F_j (the largest exponent of its leading words);
+ *   2. every entry is split into S signed integer slices (digits) of beta
+ *      bits on the grid that starts at that exponent, the paper's "quarters";
+ *   3. the diagonal sums D_t = sum_{s+u=t} sum_k dA_{ik,s} dB_{kj,u},
+ *      t = 0..S-1, the paper's convolution sums s_i, run as exact slice
+ *      matrix products on the matrix cores;
+ *   4. sum_t D_t 2^(E_i + F_j - beta (t+2)) is folded exactly and rounded
+ *      once, greedily to nearest, into m nonoverlapping output words
+ *      (postponed renormalisation, Conclusions).
+ *
+ * Two slice forms:
+ *   MD_FORM_FP64: digits of up to 24 bits held in doubles, FP64 matrix-core
+ *                 products, exact while every partial sum stays below 2^53;
+ *   MD_FORM_INT8: 7-bit sign-magnitude digits in int8, INT8 matrix-core
+ *                 products with INT32 accumulation, exact while every
+ *                 partial sum stays below 2^31.
+ * S and beta are chosen per call from the target accuracy 2^-T (T = 50 m)
+ * relative to (|A||B|)_ij.  The contraction is cut into depth chunks so that
+ * every accumulation stays exact.
+ *
+ * Data layout: component planes.  Word w of entry (r, c) of a matrix X is at
+ * X[w * plane_stride + r * ld + c]; all pointers are DEVICE pointers to
+ * doubles; the words of an entry must be nonoverlapping (decreasing, with
+ * disjoint bit ranges; zero words only at the tail) and finite.
+ *
+ * Every call is ordered on `stream` (a hipStream_t; NULL = the null stream).
+ * Choosing S from the data needs the exponent spans on the host, so the
+ * call synchronises `stream` once after the exponent step unless
+ * opts->force_S is set.  Errors of argument checking are returned before
+ * any work is queued; device faults surface at the next synchronisation.
+ *
+ * All entry points are thread-safe; calls on different streams may run
+ * concurrently.  The library allocates its scratch memory with
+ * hipMallocAsync on `stream` and frees it on the same stream, unless the
+ * caller passes a workspace.
+ */
+#ifndef MDGEMM_H
+#define MDGEMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define MD_OK 0
+#define MD_EINVAL_M 1      /* m not in {2, 4, 8} */
+#define MD_EINVAL_DIM 2    /* negative size, bad leading dimension or stride, overflow */
+#define MD_ENULL 3         /* NULL data pointer with a nonzero size */
+#define MD_EALIAS 4        /* C overlaps A or B */
+#define MD_ENOMEM 5        /* scratch allocation failed, or the given workspace is too small */
+#define MD_EHIP 6          /* a HIP runtime call failed; md_last_hip_error() has the code */
+#define MD_EINVAL_OPT 7    /* unknown form or rule, or forced S / beta out of range */
+#define MD_ERANGE 8        /* no exact slice parameters exist for this size and target */
+
+/* slice forms */
+#define MD_FORM_FP64 0
+#define MD_FORM_INT8 1
+
+/* slice-count rules */
+#define MD_S_SPAN 0        /* certified by the exponent spans of A and B */
+
+/* Result of a call: the parameters the library chose. */
+typedef struct md_info {
+    int S;              /* slices per entry */
+    int beta;           /* slice width in bits */
+    int kc;             /* depth of one exact accumulation chunk */
+    int band;           /* diagonals per band of the slice contraction */
+    int span_A;         /* max over rows of A of (E_i - smallest exponent) */
+    int span_B;         /* same over the columns of B */
+    int G;              /* log2 of the certified ratio bound used by the rule */
+    int target_bits;    /* T */
+    double log2_bound;  /* certified log2 of the max relative error vs (|A||B|)_ij */
+} md_info;
+
+/* Debug dump (small shapes): every non-NULL pointer is a device buffer the
+ * caller owns; the library writes it during the call. */
+typedef struct md_debug {
+    int32_t *E;         /* [M]      shared exponents of the rows of op(A) */
+    int32_t *F;         /* [N]      shared exponents of the columns of op(B) */
+    int32_t *digits_A;  /* [S][M][K] digits of op(A) */
+    int32_t *digits_B;  /* [S][K][N] digits of op(B) */
+    int64_t *D;         /* [S][M][N] diagonal sums D_t */
+} md_debug;
+
+typedef struct md_opts {
+    int form;              /* MD_FORM_FP64 (default) or MD_FORM_INT8 */
+    int s_rule;            /* MD_S_SPAN */
+    int target_bits;       /* 0: T = 50 m */
+    int force_S;           /* > 0: use this S (and force_beta) instead of the rule */
+    int force_beta;        /* with force_S: slice width (INT8: 7; FP64: 8..24) */
+    void *workspace;       /* optional device scratch; NULL: allocate per call */
+    size_t workspace_bytes;
+    md_debug *dbg;         /* optional debug dump */
+    md_info *info;         /* optional: receives the chosen parameters */
+} md_opts;
+
+/*
+ * C = A B for m-double matrices, the plain FP64-slice form.
+ *   m: words per entry, 2, 4 or 8.
+ *   A: m planes of M x K, row-major, dense (lda = K, plane stride M K).
+ *   B: m planes of K x N, row-major, dense.
+ *   C: m planes of M x N, row-major, dense; fully overwritten; must not
+ *      overlap A or B.
+ *   stream: hipStream_t.
+ * M = 0 or N = 0 is a no-op; K = 0 writes zeros.
+ */
+int md_gemm(int m, int64_t M, int64_t N, int64_t K, const double *A, const double *B, double *C,
+            void *stream);
+
+/*
+ * C = op(A) op(B) with strides and options.
+ *   op(A) is M x K: element (i, k) at A[i*lda + k] (transA = 0) or
+ *   A[k*lda + i] (transA = 1), word w at + w*plane_stride_A.
+ *   op(B) is K x N: element (k, j) at B[k*ldb + j] (transB = 0) or
+ *   B[j*ldb + k] (transB = 1), word w at + w*plane_stride_B.
+ *   C: element (i, j) word w at C[w*plane_stride_C + i*ldc + j].
+ *   opts may be NULL (FP64 form, span rule, T = 50 m).
+ */
+int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, const double *A,
+               int64_t lda, int64_t plane_stride_A, const double *B, int64_t ldb,
+               int64_t plane_stride_B, double *C, int64_t ldc, int64_t plane_stride_C,
+               const md_opts *opts, void *stream);
+
+/*
+ * Parameter rule alone (host only, no device work): (beta, S, kc, band) for
+ * a form, contraction depth K, target T and ratio-bound exponent G.
+ * Returns MD_OK, MD_EINVAL_OPT or MD_ERANGE.
+ */
+int md_choose_params(int form, int64_t K, int T, int G, int *beta, int *S, int *kc, int *band);
+
+/* Scratch bytes a call with these sizes and parameters needs. */
+size_t md_workspace_size(int form, int64_t M, int64_t N, int64_t K, int S);
+
+/* Text of a return code (static storage). */
+const char *md_strerror(int code);
+
+/* hipError_t of the last MD_EHIP on this thread (0 if none). */
+int md_last_hip_error(void);
+
+/* Library version: major * 10000 + minor * 100 + patch. */
+int md_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MDGEMM_H */

@@ -374,6 +374,16 @@ def span_G(span_A: int, span_B: int) -> int:
 
 INT8_KGRAN = 64     # depth granule of the INT8 slice contraction
 FP64_KGRAN = 16     # depth granule of the FP64 slice contraction
+INT8_GMAX = 16      # widest band of diagonals the INT8 contraction handles
+FP64_GMAX = 16      # same, FP64
+
+
+def band_round(S: int, gmax: int):
+    """Round S up so that it splits into nb equal bands of at most gmax
+    diagonals: nb = ceil(S / gmax), band = ceil(S / nb).  Returns (S, band)."""
+    nb = -(-S // gmax)
+    band = -(-S // nb)
+    return nb * band, band
 
 
 def chunk_depth(S: int, beta: int, K: int, limit: int, gran: int) -> int:
@@ -386,8 +396,9 @@ def chunk_depth(S: int, beta: int, K: int, limit: int, gran: int) -> int:
 
 
 def choose_params(form: str, K: int, T: int, G: int):
-    """(beta, S, Kc) for a slice form.
+    """(beta, S, Kc, band) for a slice form.
 
+    S is the budget's slice count rounded up to equal bands (``band_round``).
     int8: beta = 7 (digits in [-127, 127]); every diagonal sum of a depth
     chunk Kc stays below 2^31 (INT32 accumulation exact).
     fp64: beta in [8, 24]; every diagonal sum of a chunk stays below 2^53
@@ -395,21 +406,21 @@ def choose_params(form: str, K: int, T: int, G: int):
     chunk Kc.
     """
     if form == "int8":
-        S = slice_count(7, T, G)
+        S, band = band_round(slice_count(7, T, G), INT8_GMAX)
         kc = chunk_depth(S, 7, K, 1 << 31, INT8_KGRAN)
         if kc <= 0:
             raise ValueError("no exact INT8 chunking")
-        return 7, S, kc
+        return 7, S, kc, band
     if form == "fp64":
         best = None
         for beta in range(8, 25):
-            S = slice_count(beta, T, G)
+            S, band = band_round(slice_count(beta, T, G), FP64_GMAX)
             kc = chunk_depth(S, beta, K, 1 << 53, FP64_KGRAN)
             if kc <= 0:
                 continue
             key = (S, -kc)
             if best is None or key < best[0]:
-                best = (key, (beta, S, kc))
+                best = (key, (beta, S, kc, band))
         return best[1]
     raise ValueError(form)
 

@@ -1,0 +1,222 @@
+"""m-double matrix product by error-free summation on the MI355X.
+
+Thin Python binding of ``libmdgemm.so`` (C ABI in ``include/mdgemm.h``):
+argument marshalling only; every step of the product runs in the library's
+HIP kernels.  Torch supplies device memory and the current stream.
+
+An m-double matrix is a float64 tensor of shape (m, rows, cols) on the HIP
+device, one plane per word (word 0 the leading one).
+
+    C = gemm(A, B, form="int8")          # (m, M, K) x (m, K, N) -> (m, M, N)
+    C = MDGemm.apply(A, B, "fp64")       # differentiable; C.backward(W)
+
+The backward pass of ``MDGemm`` takes dC as m-double planes and returns the
+m-double gradients dA = dC B^T and dB = A^T dC through the same error-free
+product (the adjoint of a matrix product).  Torch sees the planes as
+independent floats, so call ``C.backward(gradient=W)`` with W in m-double
+planes rather than a plane-wise torch loss.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmdgemm.so")
+
+FORM_FP64 = 0
+FORM_INT8 = 1
+_FORMS = {"fp64": FORM_FP64, "int8": FORM_INT8}
+
+ERRORS = {
+    0: "MD_OK", 1: "MD_EINVAL_M", 2: "MD_EINVAL_DIM", 3: "MD_ENULL", 4: "MD_EALIAS",
+    5: "MD_ENOMEM", 6: "MD_EHIP", 7: "MD_EINVAL_OPT", 8: "MD_ERANGE",
+}
+
+
+class MDInfo(ctypes.Structure):
+    _fields_ = [("S", ctypes.c_int), ("beta", ctypes.c_int), ("kc", ctypes.c_int),
+                ("band", ctypes.c_int), ("span_A", ctypes.c_int), ("span_B", ctypes.c_int),
+                ("G", ctypes.c_int), ("target_bits", ctypes.c_int), ("log2_bound", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class MDDebug(ctypes.Structure):
+    _fields_ = [("E", ctypes.c_void_p), ("F", ctypes.c_void_p), ("digits_A", ctypes.c_void_p),
+                ("digits_B", ctypes.c_void_p), ("D", ctypes.c_void_p)]
+
+
+class MDOpts(ctypes.Structure):
+    _fields_ = [("form", ctypes.c_int), ("s_rule", ctypes.c_int), ("target_bits", ctypes.c_int),
+                ("force_S", ctypes.c_int), ("force_beta", ctypes.c_int),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
+                ("dbg", ctypes.POINTER(MDDebug)), ("info", ctypes.POINTER(MDInfo))]
+
+
+class MDError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded C library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2606_20863_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    i64, i32, p = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p
+    L.md_gemm.argtypes = [i32, i64, i64, i64, p, p, p, p]
+    L.md_gemm.restype = i32
+    L.md_gemm_ex.argtypes = [i32, i32, i32, i64, i64, i64, p, i64, i64, p, i64, i64, p, i64, i64,
+                             ctypes.POINTER(MDOpts), p]
+    L.md_gemm_ex.restype = i32
+    L.md_choose_params.argtypes = [i32, i64, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                   ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.md_choose_params.restype = i32
+    L.md_workspace_size.argtypes = [i32, i64, i64, i64, i32]
+    L.md_workspace_size.restype = ctypes.c_size_t
+    L.md_strerror.argtypes = [i32]
+    L.md_strerror.restype = ctypes.c_char_p
+    L.md_last_hip_error.restype = i32
+    L.md_version.restype = i32
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != 0:
+        L = lib()
+        msg = L.md_strerror(rc).decode()
+        if rc == 6:
+            msg += f" (hipError {L.md_last_hip_error()})"
+        raise MDError(rc, msg)
+
+
+def choose_params(form: str, K: int, T: int, G: int):
+    """(beta, S, kc, band) the library's slice rule picks (host only)."""
+    b, s, k, bd = (ctypes.c_int() for _ in range(4))
+    _check(lib().md_choose_params(_FORMS[form], K, T, G, ctypes.byref(b), ctypes.byref(s),
+                                  ctypes.byref(k), ctypes.byref(bd)))
+    return b.value, s.value, k.value, bd.value
+
+
+def _stream_handle(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check_planes(X: torch.Tensor, name: str):
+    if X.dtype != torch.float64 or X.dim() != 3 or not X.is_cuda:
+        raise ValueError(f"{name} must be a float64 (m, rows, cols) tensor on the HIP device")
+
+
+def gemm_ex(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None, *, transA=False,
+            transB=False, form="fp64", target_bits=0, force_S=0, force_beta=0, debug=None,
+            workspace: torch.Tensor | None = None, stream=None):
+    """C = op(A) op(B) in m-double arithmetic.
+
+    A is (m, M, K) (or (m, K, M) with transA), B is (m, K, N) (or (m, N, K)
+    with transB); both contiguous per plane.  Returns (C, info dict).
+    ``debug`` may be a dict of preallocated device tensors with keys E, F,
+    digits_A, digits_B, D (see ``md_debug``).
+    """
+    _check_planes(A, "A")
+    _check_planes(B, "B")
+    A = A.contiguous()
+    B = B.contiguous()
+    m = A.shape[0]
+    if B.shape[0] != m:
+        raise ValueError("A and B have different word counts")
+    M, K = (A.shape[2], A.shape[1]) if transA else (A.shape[1], A.shape[2])
+    Kb, N = (B.shape[2], B.shape[1]) if transB else (B.shape[1], B.shape[2])
+    if Kb != K:
+        raise ValueError(f"inner sizes differ: {K} vs {Kb}")
+    if C is None:
+        C = torch.empty((m, M, N), dtype=torch.float64, device=A.device)
+    elif C.shape != (m, M, N) or not C.is_contiguous() or C.dtype != torch.float64:
+        raise ValueError("C must be a contiguous float64 (m, M, N) tensor")
+    info = MDInfo()
+    opts = MDOpts()
+    opts.form = _FORMS[form]
+    opts.target_bits = target_bits
+    opts.force_S = force_S
+    opts.force_beta = force_beta
+    opts.info = ctypes.pointer(info)
+    if workspace is not None:
+        opts.workspace = ctypes.c_void_p(workspace.data_ptr())
+        opts.workspace_bytes = workspace.numel() * workspace.element_size()
+    dbg = None
+    if debug:
+        dbg = MDDebug()
+        for key in ("E", "F", "digits_A", "digits_B", "D"):
+            if key in debug and debug[key] is not None:
+                setattr(dbg, key, debug[key].data_ptr())
+        opts.dbg = ctypes.pointer(dbg)
+    lda = A.shape[2]
+    ldb = B.shape[2]
+    rc = lib().md_gemm_ex(m, int(transA), int(transB), M, N, K, _ptr(A), lda, A.shape[1] * A.shape[2],
+                          _ptr(B), ldb, B.shape[1] * B.shape[2], _ptr(C), N, M * N,
+                          ctypes.byref(opts), _stream_handle(stream))
+    _check(rc)
+    return C, info.as_dict()
+
+
+def gemm(A: torch.Tensor, B: torch.Tensor, form: str = "fp64", stream=None) -> torch.Tensor:
+    """C = A B for m-double planes A (m, M, K) and B (m, K, N)."""
+    if form == "fp64" and stream is None:
+        _check_planes(A, "A")
+        _check_planes(B, "B")
+        A = A.contiguous()
+        B = B.contiguous()
+        m, M, K = A.shape
+        N = B.shape[2]
+        if B.shape[:2] != (m, K):
+            raise ValueError("shape mismatch")
+        C = torch.empty((m, M, N), dtype=torch.float64, device=A.device)
+        _check(lib().md_gemm(m, M, N, K, _ptr(A), _ptr(B), _ptr(C), _stream_handle(None)))
+        return C
+    return gemm_ex(A, B, form=form, stream=stream)[0]
+
+
+class MDGemm(torch.autograd.Function):
+    """C = A B with the hand-written m-double adjoint.
+
+    forward(A, B, form) -> C; backward(dC) -> (dC B^T, A^T dC, None), each an
+    m-double product through the same error-free summation.
+    """
+
+    @staticmethod
+    def forward(ctx, A, B, form="fp64"):
+        ctx.save_for_backward(A, B)
+        ctx.form = form
+        return gemm_ex(A, B, form=form)[0]
+
+    @staticmethod
+    def backward(ctx, dC):
+        A, B = ctx.saved_tensors
+        dC = dC.contiguous()
+        dA = dB = None
+        if ctx.needs_input_grad[0]:
+            dA = gemm_ex(dC, B, transB=True, form=ctx.form)[0]
+        if ctx.needs_input_grad[1]:
+            dB = gemm_ex(A, dC, transA=True, form=ctx.form)[0]
+        return dA, dB, None
+
+
+__all__ = ["gemm", "gemm_ex", "MDGemm", "choose_params", "lib", "MDError", "MDInfo"]

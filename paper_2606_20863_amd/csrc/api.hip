@@ -1,0 +1,440 @@
+// C ABI of the m-double product library: argument checking, parameter rule,
+// scratch memory and the launch sequence on the caller's stream.
+#include "../../include/mdgemm.h"
+#include "mdgemm_internal.h"
+
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <mutex>
+
+using namespace mdg;
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+int hip_fail(hipError_t e)
+{
+    g_last_hip = (int)e;
+    return MD_EHIP;
+}
+
+int ceil_log2(int64_t n)
+{
+    int b = 0;
+    while (((int64_t)1 << b) < n)
+        ++b;
+    return b;
+}
+
+// Smallest S with beta S >= T + G + ceil(log2(S + 2)) + 1.  Per product term,
+// truncating both entries to S digits and dropping the digit pairs with
+// s + u >= S errs by less than (S + 1 + 2^-(beta S)) 2^(E_i + F_j - beta S);
+// with 2^G bounding N_ij 2^(E_i + F_j) / (|A||B|)_ij this keeps the
+// method's error below 2^-(T+1) of (|A||B|)_ij, and the final rounding into
+// m words adds less than 2^-(53 m) <= 2^-(T+5) of it.
+int slice_count(int beta, int T, int G)
+{
+    int S = 1;
+    while ((int64_t)beta * S < (int64_t)T + G + ceil_log2(S + 2) + 1)
+        ++S;
+    return S;
+}
+
+// Bands of at most gmax diagonals, all of one width: S rounds up to
+// nb * ceil(S / nb) with nb = ceil(S / gmax).
+void band_round(int Smin, int gmax, int& S, int& band)
+{
+    const int nb = (Smin + gmax - 1) / gmax;
+    band = (Smin + nb - 1) / nb;
+    S = nb * band;
+}
+
+// Largest multiple of gran with S * kc * (2^beta - 1)^2 < limit, capped at K
+// rounded up to gran.
+int64_t chunk_depth(int S, int beta, int64_t K, int64_t limit, int gran)
+{
+    const int64_t d = ((int64_t)1 << beta) - 1;
+    const int64_t per = (int64_t)S * d * d;
+    int64_t kc = ((limit - 1) / per) / gran * gran;
+    const int64_t kfull = (std::max<int64_t>(K, 1) + gran - 1) / gran * gran;
+    return std::min(kc, kfull);
+}
+
+int choose(int form, int64_t K, int T, int G, int& beta, int& S, int64_t& kc, int& band)
+{
+    if (T < 1 || G < 0 || K < 0)
+        return MD_EINVAL_OPT;
+    if (form == MD_FORM_INT8) {
+        beta = 7;
+        band_round(slice_count(7, T, G), kGmaxI8, S, band);
+        kc = chunk_depth(S, 7, K, (int64_t)1 << 31, kKcI8);
+        return kc > 0 ? MD_OK : MD_ERANGE;
+    }
+    if (form == MD_FORM_FP64) {
+        bool found = false;
+        for (int b = 8; b <= 24; ++b) {
+            int s, bd;
+            band_round(slice_count(b, T, G), kGmaxF64, s, bd);
+            const int64_t k = chunk_depth(s, b, K, (int64_t)1 << 53, kKcF64);
+            if (k <= 0)
+                continue;
+            if (!found || s < S || (s == S && k > kc)) {
+                found = true;
+                beta = b;
+                S = s;
+                kc = k;
+                band = bd;
+            }
+        }
+        return found ? MD_OK : MD_ERANGE;
+    }
+    return MD_EINVAL_OPT;
+}
+
+// 32-bit columns of the exact fold: X < K 2^(beta (S+1) + 1), plus carries
+int fold_columns(int beta, int S, int64_t Kp)
+{
+    return (beta * (S + 1) + ceil_log2(std::max<int64_t>(Kp, 1)) + 2 + 31) / 32 + 3;
+}
+
+int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
+
+struct Span {
+    uintptr_t lo, hi;  // [lo, hi) in bytes; empty if lo == hi
+};
+
+Span extent(const double* p, int m, int64_t R, int64_t Cc, int64_t ld_r, int64_t ld_c, int64_t ps)
+{
+    if (R == 0 || Cc == 0)
+        return {0, 0};
+    const int64_t last = (int64_t)(m - 1) * ps + (R - 1) * ld_r + (Cc - 1) * ld_c;
+    const uintptr_t lo = (uintptr_t)p;
+    return {lo, lo + (uintptr_t)(last + 1) * sizeof(double)};
+}
+
+bool overlap(Span a, Span b) { return a.lo < a.hi && b.lo < b.hi && a.lo < b.hi && b.lo < a.hi; }
+
+bool mul_ok(int64_t a, int64_t b) { return a == 0 || b <= INT64_MAX / a; }
+
+std::mutex g_pool_mu;
+hipMemPool_t g_pool[64];
+bool g_pool_init[64];
+
+int get_pool(hipMemPool_t& pool)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_fail(e);
+    if (dev < 0 || dev >= 64)
+        return MD_EINVAL_OPT;
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    if (!g_pool_init[dev]) {
+        hipMemPoolProps props;
+        memset(&props, 0, sizeof(props));
+        props.allocType = hipMemAllocationTypePinned;
+        props.location.type = hipMemLocationTypeDevice;
+        props.location.id = dev;
+        e = hipMemPoolCreate(&g_pool[dev], &props);
+        if (e != hipSuccess)
+            return hip_fail(e);
+        uint64_t keep = UINT64_MAX;
+        e = hipMemPoolSetAttribute(g_pool[dev], hipMemPoolAttrReleaseThreshold, &keep);
+        if (e != hipSuccess)
+            return hip_fail(e);
+        g_pool_init[dev] = true;
+    }
+    pool = g_pool[dev];
+    return MD_OK;
+}
+
+// Scratch: either the caller's workspace (bump allocation) or pool memory.
+struct Scratch {
+    char* user = nullptr;
+    size_t user_bytes = 0, used = 0;
+    hipStream_t st = nullptr;
+    void* owned[4] = {nullptr, nullptr, nullptr, nullptr};
+    int nowned = 0;
+
+    int get(size_t bytes, void** out)
+    {
+        bytes = (bytes + 255) / 256 * 256;
+        if (user) {
+            if (used + bytes > user_bytes)
+                return MD_ENOMEM;
+            *out = user + used;
+            used += bytes;
+            return MD_OK;
+        }
+        hipMemPool_t pool;
+        int rc = get_pool(pool);
+        if (rc)
+            return rc;
+        hipError_t e = hipMallocFromPoolAsync(out, std::max<size_t>(bytes, 256), pool, st);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return MD_ENOMEM;
+        }
+        owned[nowned++] = *out;
+        return MD_OK;
+    }
+    ~Scratch()
+    {
+        for (int i = 0; i < nowned; ++i)
+            (void)hipFreeAsync(owned[i], st);
+    }
+};
+
+size_t digits_bytes(int form, int64_t R, int64_t K, int S)
+{
+    const int64_t Rp = round_up(std::max<int64_t>(R, 1), kTile);
+    if (form == MD_FORM_INT8)
+        return (size_t)S * Rp * round_up(std::max<int64_t>(K, 1), kKcI8);
+    return (size_t)S * Rp * round_up(std::max<int64_t>(K, 1), kKcF64) * sizeof(double);
+}
+
+size_t small_bytes(int64_t M, int64_t N)
+{
+    return (size_t)(3 * round_up(M + 64, 64) + 3 * round_up(N + 64, 64) + 64) * sizeof(int32_t) + 7 * 256;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* md_strerror(int code)
+{
+    switch (code) {
+    case MD_OK: return "success";
+    case MD_EINVAL_M: return "m must be 2, 4 or 8";
+    case MD_EINVAL_DIM: return "invalid size, leading dimension or plane stride";
+    case MD_ENULL: return "NULL data pointer";
+    case MD_EALIAS: return "C overlaps A or B";
+    case MD_ENOMEM: return "scratch allocation failed or workspace too small";
+    case MD_EHIP: return "HIP runtime error (see md_last_hip_error)";
+    case MD_EINVAL_OPT: return "invalid option";
+    case MD_ERANGE: return "no exact slice parameters for this size and target";
+    default: return "unknown error";
+    }
+}
+
+int md_last_hip_error(void) { return g_last_hip; }
+
+int md_version(void) { return 100; }
+
+int md_choose_params(int form, int64_t K, int T, int G, int* beta, int* S, int* kc, int* band)
+{
+    int b = 0, s = 0, bd = 0;
+    int64_t k = 0;
+    const int rc = choose(form, K, T, G, b, s, k, bd);
+    if (rc == MD_OK) {
+        if (beta) *beta = b;
+        if (S) *S = s;
+        if (kc) *kc = (int)std::min<int64_t>(k, INT_MAX);
+        if (band) *band = bd;
+    }
+    return rc;
+}
+
+size_t md_workspace_size(int form, int64_t M, int64_t N, int64_t K, int S)
+{
+    return small_bytes(M, N) + digits_bytes(form, M, K, S) + digits_bytes(form, N, K, S) + 1024;
+}
+
+int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, const double* A,
+               int64_t lda, int64_t plane_stride_A, const double* B, int64_t ldb,
+               int64_t plane_stride_B, double* C, int64_t ldc, int64_t plane_stride_C,
+               const md_opts* opts, void* stream)
+{
+    g_last_hip = 0;
+    if (m != 2 && m != 4 && m != 8)
+        return MD_EINVAL_M;
+    if (M < 0 || N < 0 || K < 0)
+        return MD_EINVAL_DIM;
+    md_opts o;
+    memset(&o, 0, sizeof(o));
+    if (opts)
+        o = *opts;
+    if (o.form != MD_FORM_FP64 && o.form != MD_FORM_INT8)
+        return MD_EINVAL_OPT;
+    if (o.s_rule != MD_S_SPAN)
+        return MD_EINVAL_OPT;
+    if (M == 0 || N == 0)
+        return MD_OK;
+    if (!C || (K > 0 && (!A || !B)))
+        return MD_ENULL;
+    // leading dimensions and plane strides
+    if (ldc < N || plane_stride_C < 1)
+        return MD_EINVAL_DIM;
+    if (K > 0) {
+        if (lda < (transA ? M : K) || ldb < (transB ? K : N) || plane_stride_A < 1 || plane_stride_B < 1)
+            return MD_EINVAL_DIM;
+    }
+    if (!mul_ok(M, std::max<int64_t>(ldc, 1)) || !mul_ok(std::max<int64_t>(M, K), std::max<int64_t>(lda, 1)) ||
+        !mul_ok(std::max<int64_t>(K, N), std::max<int64_t>(ldb, 1)) || M > (INT64_C(1) << 40) ||
+        N > (INT64_C(1) << 40) || K > (INT64_C(1) << 40))
+        return MD_EINVAL_DIM;
+    const Span sc = extent(C, m, M, N, ldc, 1, plane_stride_C);
+    if (K > 0) {
+        const Span sa = transA ? extent(A, m, K, M, lda, 1, plane_stride_A) : extent(A, m, M, K, lda, 1, plane_stride_A);
+        const Span sb = transB ? extent(B, m, N, K, ldb, 1, plane_stride_B) : extent(B, m, K, N, ldb, 1, plane_stride_B);
+        if (overlap(sc, sa) || overlap(sc, sb))
+            return MD_EALIAS;
+    }
+    const int T = o.target_bits > 0 ? o.target_bits : 50 * m;
+    if (o.force_S < 0 || o.force_S > 512 || (o.force_S > 0 && (o.force_beta < 1 || o.force_beta > 24)) ||
+        (o.force_S > 0 && o.form == MD_FORM_INT8 && o.force_beta != 7))
+        return MD_EINVAL_OPT;
+
+    hipStream_t st = (hipStream_t)stream;
+    if (K == 0) {
+        hipError_t e = launch_fill_zero(C, m, M, N, ldc, plane_stride_C, st);
+        if (e != hipSuccess)
+            return hip_fail(e);
+        if (o.info) {
+            memset(o.info, 0, sizeof(*o.info));
+            o.info->target_bits = T;
+            o.info->log2_bound = -1.0 / 0.0;
+        }
+        return MD_OK;
+    }
+
+    Operand opA{A, plane_stride_A, transA ? 1 : lda, transA ? lda : 1, M, K};
+    Operand opB{B, plane_stride_B, transB ? ldb : 1, transB ? 1 : ldb, N, K};
+
+    Scratch scr;
+    scr.st = st;
+    if (o.workspace) {
+        scr.user = (char*)o.workspace;
+        scr.user_bytes = o.workspace_bytes;
+    }
+    int32_t *hiA, *loA, *hiB, *loB, *E, *F, *stats;
+    {
+        void* p;
+        int rc = scr.get(small_bytes(M, N), &p);
+        if (rc)
+            return rc;
+        int32_t* q = (int32_t*)p;
+        const int64_t Ma = round_up(M + 64, 64), Na = round_up(N + 64, 64);
+        hiA = q; q += Ma;
+        loA = q; q += Ma;
+        E = q; q += Ma;
+        hiB = q; q += Na;
+        loB = q; q += Na;
+        F = q; q += Na;
+        stats = q;
+    }
+    md_debug* dbg = o.dbg;
+    hipError_t e;
+    if ((e = launch_exp_init(hiA, loA, M, stats, st)) != hipSuccess) return hip_fail(e);
+    if ((e = launch_exp_init(hiB, loB, N, nullptr, st)) != hipSuccess) return hip_fail(e);
+    if ((e = launch_exp_partial(opA, hiA, loA, st)) != hipSuccess) return hip_fail(e);
+    if ((e = launch_exp_partial(opB, hiB, loB, st)) != hipSuccess) return hip_fail(e);
+    if ((e = launch_exp_final(hiA, loA, M, E, stats, dbg ? dbg->E : nullptr, st)) != hipSuccess) return hip_fail(e);
+    if ((e = launch_exp_final(hiB, loB, N, F, stats + 1, dbg ? dbg->F : nullptr, st)) != hipSuccess) return hip_fail(e);
+
+    int spans[2] = {0, 0};
+    int beta, S, band;
+    int64_t kc;
+    int G = 0;
+    if (o.force_S > 0) {
+        beta = o.force_beta;
+        const int gmax = o.form == MD_FORM_INT8 ? kGmaxI8 : kGmaxF64;
+        int s2;
+        band_round(o.force_S, gmax, s2, band);
+        if (s2 != o.force_S)
+            return MD_EINVAL_OPT;   // forced S must split into equal bands
+        S = o.force_S;
+        kc = chunk_depth(S, beta, K, o.form == MD_FORM_INT8 ? ((int64_t)1 << 31) : ((int64_t)1 << 53),
+                         o.form == MD_FORM_INT8 ? kKcI8 : kKcF64);
+        if (kc <= 0)
+            return MD_ERANGE;
+    } else {
+        if ((e = hipMemcpyAsync(spans, stats, sizeof(spans), hipMemcpyDeviceToHost, st)) != hipSuccess)
+            return hip_fail(e);
+        if ((e = hipStreamSynchronize(st)) != hipSuccess)
+            return hip_fail(e);
+        G = spans[0] + spans[1] + 2;
+        const int rc = choose(o.form, K, T, G, beta, S, kc, band);
+        if (rc)
+            return rc;
+    }
+    const int kcg = o.form == MD_FORM_INT8 ? kKcI8 : kKcF64;
+    const int64_t nkc = (K + kcg - 1) / kcg;
+    const int64_t Mp = round_up(M, kTile), Np = round_up(N, kTile);
+    const int ncol = fold_columns(beta, S, nkc * kcg);
+    if ((size_t)4 * ncol * 256 * sizeof(int64_t) > 160 * 1024)
+        return MD_ERANGE;
+
+    void *dA, *dB;
+    int rc = scr.get(digits_bytes(o.form, M, K, S), &dA);
+    if (rc)
+        return rc;
+    rc = scr.get(digits_bytes(o.form, N, K, S), &dB);
+    if (rc)
+        return rc;
+
+    if (o.form == MD_FORM_INT8) {
+        if ((e = launch_split_i8(opA, m, E, S, Mp / kRowBlock, nkc, (int8_t*)dA, dbg ? dbg->digits_A : nullptr, st)) != hipSuccess)
+            return hip_fail(e);
+        if ((e = launch_split_i8(opB, m, F, S, Np / kRowBlock, nkc, (int8_t*)dB, dbg ? dbg->digits_B : nullptr, st)) != hipSuccess)
+            return hip_fail(e);
+    } else {
+        if ((e = launch_split_f64(opA, m, E, S, beta, Mp / kRowBlock, nkc, (double*)dA, dbg ? dbg->digits_A : nullptr, st)) != hipSuccess)
+            return hip_fail(e);
+        if ((e = launch_split_f64(opB, m, F, S, beta, Np / kRowBlock, nkc, (double*)dB, dbg ? dbg->digits_B : nullptr, st)) != hipSuccess)
+            return hip_fail(e);
+    }
+    if (dbg && dbg->D) {
+        if ((e = launch_fill_zero((double*)dbg->D, S, M, N, N, M * N, st)) != hipSuccess)
+            return hip_fail(e);
+    }
+    GemmArgs ga;
+    ga.A = dA;
+    ga.B = dB;
+    ga.E = E;
+    ga.F = F;
+    ga.C = C;
+    ga.ldc = ldc;
+    ga.psc = plane_stride_C;
+    ga.M = M;
+    ga.N = N;
+    ga.nkc = nkc;
+    ga.kcc = std::max<int64_t>(kc / kcg, 1);
+    ga.S = S;
+    ga.beta = beta;
+    ga.band = band;
+    ga.nbands = S / band;
+    ga.m = m;
+    ga.ncol = ncol;
+    ga.dbgD = dbg ? dbg->D : nullptr;
+    e = o.form == MD_FORM_INT8 ? launch_gemm_i8(ga, st) : launch_gemm_f64(ga, st);
+    if (e != hipSuccess)
+        return hip_fail(e);
+
+    if (o.info) {
+        md_info* in = o.info;
+        in->S = S;
+        in->beta = beta;
+        in->kc = (int)std::min<int64_t>(kc, INT_MAX);
+        in->band = band;
+        in->span_A = spans[0];
+        in->span_B = spans[1];
+        in->G = G;
+        in->target_bits = T;
+        // certified bound of the method plus the final rounding
+        const double lb = (double)(G - beta * S) + __builtin_log2((double)S + 2.0);
+        in->log2_bound = o.force_S > 0 ? 0.0 : __builtin_log2(__builtin_exp2(lb) + __builtin_exp2(-53.0 * m + 0.1));
+    }
+    return MD_OK;
+}
+
+int md_gemm(int m, int64_t M, int64_t N, int64_t K, const double* A, const double* B, double* C,
+            void* stream)
+{
+    return md_gemm_ex(m, 0, 0, M, N, K, A, K, M * K, B, N, K * N, C, N, M * N, nullptr, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,72 @@
+// Internal interfaces of the m-double product library (not installed).
+//
+// Tiled slice layout ("fragments").  An operand op(X) has R rows (rows of A,
+// or columns of B) and depth K.  Rows are grouped in blocks of 16, depth in
+// chunks of KC (64 for INT8, 16 for FP64).  For row block rb, depth chunk kc
+// and slice s, one fragment holds the 16 x KC digits in the order one
+// wavefront hands them to the matrix cores:
+//
+//   INT8 (v_mfma_i32_16x16x64_i8): 64 lanes x 16 bytes; lane l holds row
+//     rb*16 + l%16, depth kc*64 + 16*(l/16) + b in byte b.
+//   FP64 (v_mfma_f64_16x16x4f64, four steps): 64 lanes x 4 doubles; lane l
+//     holds row rb*16 + l%16, depth kc*16 + 4*q + l/16 in double q, and step q
+//     of the matrix-core product uses double q of both operands.
+//
+// Fragment (rb, kc, s) starts at element ((rb * nkc + kc) * S + s) * 64 lanes,
+// so the S slices of one depth chunk are adjacent.  Rows beyond R and depth
+// beyond K hold zero digits.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mdg {
+
+constexpr int kRowBlock = 16;   // rows per fragment
+constexpr int kKcI8 = 64;       // depth per INT8 fragment
+constexpr int kKcF64 = 16;      // depth per FP64 fragment
+constexpr int kTile = 32;       // rows and columns per workgroup (2 x 2 waves)
+constexpr int kGmaxI8 = 16;     // widest band of diagonals, INT8 form
+constexpr int kGmaxF64 = 16;    // widest band of diagonals, FP64 form
+
+// element (r, k), word w of an operand: p[w * ps + r * sr + k * sk]
+struct Operand {
+    const double* p;
+    int64_t ps, sr, sk;
+    int64_t R, K;
+};
+
+struct GemmArgs {
+    const void* A;          // tiled digits of op(A)
+    const void* B;          // tiled digits of op(B)^T (rows = columns of op(B))
+    const int32_t* E;       // [M]
+    const int32_t* F;       // [N]
+    double* C;
+    int64_t ldc, psc;
+    int64_t M, N;
+    int64_t nkc;            // depth chunks
+    int64_t kcc;            // depth chunks per exact accumulation chunk
+    int S, beta, band, nbands, m;
+    int ncol;               // 32-bit columns of the exact fold accumulator
+    int64_t* dbgD;          // optional [S][M][N]
+};
+
+hipError_t launch_fill_zero(double* C, int m, int64_t M, int64_t N, int64_t ldc, int64_t psc,
+                            hipStream_t st);
+
+// stats[0..1]: span maxima of A and B (reset by launch_exp_init)
+hipError_t launch_exp_init(int32_t* hi, int32_t* lo, int64_t R, int32_t* stats, hipStream_t st);
+hipError_t launch_exp_partial(const Operand& op, int32_t* hi, int32_t* lo, hipStream_t st);
+hipError_t launch_exp_final(const int32_t* hi, const int32_t* lo, int64_t R, int32_t* E,
+                            int32_t* span_max, int32_t* dbgE, hipStream_t st);
+
+hipError_t launch_split_i8(const Operand& op, int m, const int32_t* E, int S, int64_t nrb,
+                           int64_t nkc, int8_t* out, int32_t* dbg, hipStream_t st);
+hipError_t launch_split_f64(const Operand& op, int m, const int32_t* E, int S, int beta,
+                            int64_t nrb, int64_t nkc, double* out, int32_t* dbg, hipStream_t st);
+
+hipError_t launch_gemm_i8(const GemmArgs& a, hipStream_t st);
+hipError_t launch_gemm_f64(const GemmArgs& a, hipStream_t st);
+
+}  // namespace mdg

@@ -1,0 +1,350 @@
+// Exponent alignment and split of m-double operands into integer slices.
+//
+// Shared exponent (the paper assumes one exponent for all doubles, Section
+// 2; here one per row of A and per column of B): E_r is the largest frexp
+// exponent (2^(e-1) <= |x| < 2^e) of the leading words of row r, zero words
+// skipped, and 0 for an all-zero row.  Nonoverlapping words keep every
+// entry of the row below 2^E_r in magnitude.
+//
+// Split (the paper's quarters, Section 2 and Figure 1, with beta bits in
+// place of 13): digit s of an entry is
+//   d_s = sum_w sgn(w) * (floor(|w| * 2^(beta (s+1) - E_r)) mod 2^beta),
+// i.e. each word is cut on the beta-bit grid that starts at 2^E_r and
+// truncated toward zero below 2^(E_r - beta S).  Because the words' bits are
+// disjoint, |d_s| <= 2^beta - 1 (INT8: beta = 7 fits int8).
+//
+// The split works a limb at a time: a limb is a run of D = floor(63/beta)
+// digits, W = D beta bits wide.  For limb j the positive words and the
+// negative words are each gathered into one W-bit integer (their bits are
+// disjoint, so OR adds them), and digit D j + i is the difference of the
+// i-th beta-bit fields of the two.
+#include "mdgemm_internal.h"
+
+#include <climits>
+
+namespace mdg {
+namespace {
+
+__device__ __forceinline__ int frexp_exponent(double x)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    const int eb = (int)((b >> 52) & 0x7ff);
+    if (eb)
+        return eb - 1022;
+    const uint64_t f = b & ((1ull << 52) - 1);
+    return (64 - __clzll((long long)f)) - 1074;
+}
+
+// |x| = mant * 2^ex with mant < 2^53; returns true if x < 0
+__device__ __forceinline__ bool decode(double x, uint64_t& mant, int& ex)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    const int eb = (int)((b >> 52) & 0x7ff);
+    const uint64_t f = b & ((1ull << 52) - 1);
+    mant = eb ? (f | (1ull << 52)) : f;
+    ex = eb ? eb - 1075 : -1074;
+    return (b >> 63) != 0;
+}
+
+// floor(mant * 2^sh) mod 2^W, W <= 63
+__device__ __forceinline__ uint64_t field(uint64_t mant, int sh, uint64_t wmask)
+{
+    uint64_t v;
+    if (sh >= 0)
+        v = sh >= 63 ? 0 : (mant << sh);
+    else
+        v = sh <= -64 ? 0 : (mant >> (-sh));
+    return v & wmask;
+}
+
+__global__ void k_fill_zero(double* C, int m, int64_t M, int64_t N, int64_t ldc, int64_t psc)
+{
+    const int64_t n = (int64_t)m * M * N;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t w = e / (M * N), r = e % (M * N);
+        C[w * psc + (r / N) * ldc + (r % N)] = 0.0;
+    }
+}
+
+__global__ void k_exp_init(int32_t* hi, int32_t* lo, int64_t R, int32_t* stats)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < R) {
+        hi[r] = INT_MIN;
+        lo[r] = INT_MAX;
+    }
+    if (r < 2 && stats)
+        stats[r] = 0;
+}
+
+// Block: 16 rows x 1024 depth, 256 threads; each row's 16 threads reduce
+// through shuffles-free LDS and one pair of atomics per row.
+constexpr int kExpRows = 16, kExpDepth = 1024;
+
+__global__ __launch_bounds__(256) void k_exp_partial(Operand op, int32_t* hi, int32_t* lo,
+                                                     int rows_fast)
+{
+    __shared__ int s_hi[256], s_lo[256];
+    const int t = threadIdx.x;
+    const int tr = rows_fast ? (t & 15) : (t >> 4);
+    const int tk = rows_fast ? (t >> 4) : (t & 15);
+    const int64_t r = (int64_t)blockIdx.x * kExpRows + tr;
+    const int64_t k0 = (int64_t)blockIdx.y * kExpDepth;
+    int h = INT_MIN, l = INT_MAX;
+    if (r < op.R) {
+        const double* p = op.p + r * op.sr;
+        const int64_t kend = min(k0 + (int64_t)kExpDepth, op.K);
+        for (int64_t k = k0 + tk; k < kend; k += 16) {
+            const double x = p[k * op.sk];
+            if (x != 0.0) {
+                const int e = frexp_exponent(x);
+                h = max(h, e);
+                l = min(l, e);
+            }
+        }
+    }
+    s_hi[t] = h;
+    s_lo[t] = l;
+    __syncthreads();
+    if (tk == 0 && r < op.R) {
+        for (int q = 1; q < 16; ++q) {
+            const int o = rows_fast ? (t + 16 * q) : (t + q);
+            h = max(h, s_hi[o]);
+            l = min(l, s_lo[o]);
+        }
+        if (h != INT_MIN) {
+            atomicMax(hi + r, h);
+            atomicMin(lo + r, l);
+        }
+    }
+}
+
+__global__ void k_exp_final(const int32_t* hi, const int32_t* lo, int64_t R, int32_t* E,
+                            int32_t* span_max, int32_t* dbgE)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R)
+        return;
+    const int h = hi[r];
+    const int e = h == INT_MIN ? 0 : h;
+    const int span = h == INT_MIN ? 0 : h - lo[r];
+    E[r] = e;
+    if (dbgE)
+        dbgE[r] = e;
+    atomicMax(span_max, span);
+}
+
+// Gather limb j (digits [D j, D j + D)) of the positive and the negative
+// words of one entry.
+template <int MW>
+__device__ __forceinline__ void limb_pair(const uint64_t (&mant)[MW], const int (&sh0)[MW],
+                                          const bool (&neg)[MW], int shift, uint64_t wmask,
+                                          uint64_t& P, uint64_t& N)
+{
+    P = 0;
+    N = 0;
+#pragma unroll
+    for (int w = 0; w < MW; ++w) {
+        const uint64_t v = field(mant[w], sh0[w] + shift, wmask);
+        if (neg[w])
+            N |= v;
+        else
+            P |= v;
+    }
+}
+
+// INT8 split: one block of 256 threads writes one fragment (1 KB); thread T
+// writes bytes [4T, 4T+4): lane T/4 of the fragment, depth bytes 4 (T%4).. .
+template <int MW>
+__global__ __launch_bounds__(256) void k_split_i8(Operand op, const int32_t* E, int S, int64_t nkc,
+                                                  int8_t* out, int32_t* dbg)
+{
+    constexpr int beta = 7, D = 9, W = 63;
+    const int T = threadIdx.x;
+    const int64_t rb = blockIdx.y, kc = blockIdx.x;
+    const int L = T >> 2;                     // fragment lane
+    const int64_t r = rb * kRowBlock + (L & 15);
+    const int64_t kbase = kc * kKcI8 + 16 * (L >> 4) + 4 * (T & 3);
+    const bool row_ok = r < op.R;
+    const int Er = row_ok ? E[r] : 0;
+
+    uint64_t mant[4][MW];
+    int sh0[4][MW];
+    bool neg[4][MW];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t k = kbase + q;
+        const bool ok = row_ok && k < op.K;
+#pragma unroll
+        for (int w = 0; w < MW; ++w) {
+            const double x = ok ? op.p[w * op.ps + r * op.sr + k * op.sk] : 0.0;
+            int ex;
+            neg[q][w] = decode(x, mant[q][w], ex);
+            sh0[q][w] = ex - Er;
+        }
+    }
+    const uint64_t wmask = (1ull << W) - 1;
+    uint32_t* o32 = reinterpret_cast<uint32_t*>(out) + ((rb * nkc + kc) * (int64_t)S) * 256 + T;
+    const int nl = (S + D - 1) / D;
+    for (int j = 0; j < nl; ++j) {
+        uint64_t P[4], N[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            limb_pair<MW>(mant[q], sh0[q], neg[q], W * (j + 1), wmask, P[q], N[q]);
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const int s = D * j + i;
+            if (s >= S)
+                break;
+            const int rs = W - beta * (i + 1);
+            uint32_t packed = 0;
+            int dv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                dv[q] = (int)((P[q] >> rs) & 127) - (int)((N[q] >> rs) & 127);
+                packed |= ((uint32_t)(dv[q] & 0xff)) << (8 * q);
+            }
+            o32[(int64_t)s * 256] = packed;
+            if (dbg && row_ok) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (kbase + q < op.K)
+                        dbg[((int64_t)s * op.R + r) * op.K + kbase + q] = dv[q];
+            }
+        }
+    }
+}
+
+// FP64 split: one wave writes one fragment (64 lanes x 4 doubles); lane l
+// holds row l%16, depth 4q + l/16.
+template <int MW>
+__global__ __launch_bounds__(256) void k_split_f64(Operand op, const int32_t* E, int S, int beta,
+                                                   int64_t nrb, int64_t nkc, double* out,
+                                                   int32_t* dbg)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t frag = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (frag >= nrb * nkc)
+        return;
+    const int64_t rb = frag / nkc, kc = frag % nkc;
+    const int64_t r = rb * kRowBlock + (lane & 15);
+    const bool row_ok = r < op.R;
+    const int Er = row_ok ? E[r] : 0;
+    const int D = 63 / beta, W = D * beta;
+
+    uint64_t mant[4][MW];
+    int sh0[4][MW];
+    bool neg[4][MW];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t k = kc * kKcF64 + 4 * q + (lane >> 4);
+        const bool ok = row_ok && k < op.K;
+#pragma unroll
+        for (int w = 0; w < MW; ++w) {
+            const double x = ok ? op.p[w * op.ps + r * op.sr + k * op.sk] : 0.0;
+            int ex;
+            neg[q][w] = decode(x, mant[q][w], ex);
+            sh0[q][w] = ex - Er;
+        }
+    }
+    const uint64_t wmask = (1ull << W) - 1, dmask = (1ull << beta) - 1;
+    double* o = out + ((rb * nkc + kc) * (int64_t)S) * 256 + lane * 4;
+    const int nl = (S + D - 1) / D;
+    for (int j = 0; j < nl; ++j) {
+        uint64_t P[4], N[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            limb_pair<MW>(mant[q], sh0[q], neg[q], W * (j + 1), wmask, P[q], N[q]);
+        for (int i = 0; i < D; ++i) {
+            const int s = D * j + i;
+            if (s >= S)
+                break;
+            const int rs = W - beta * (i + 1);
+            double dv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                dv[q] = (double)((int64_t)((P[q] >> rs) & dmask) - (int64_t)((N[q] >> rs) & dmask));
+            double4 v;
+            v.x = dv[0];
+            v.y = dv[1];
+            v.z = dv[2];
+            v.w = dv[3];
+            *reinterpret_cast<double4*>(o + (int64_t)s * 256) = v;
+            if (dbg && row_ok) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t k = kc * kKcF64 + 4 * q + (lane >> 4);
+                    if (k < op.K)
+                        dbg[((int64_t)s * op.R + r) * op.K + k] = (int32_t)dv[q];
+                }
+            }
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_fill_zero(double* C, int m, int64_t M, int64_t N, int64_t ldc, int64_t psc,
+                            hipStream_t st)
+{
+    const int64_t n = (int64_t)m * M * N;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st,
+                       C, m, M, N, ldc, psc);
+    return hipGetLastError();
+}
+
+hipError_t launch_exp_init(int32_t* hi, int32_t* lo, int64_t R, int32_t* stats, hipStream_t st)
+{
+    const int64_t blocks = std::max<int64_t>((R + 255) / 256, 1);
+    hipLaunchKernelGGL(k_exp_init, dim3((unsigned)blocks), dim3(256), 0, st, hi, lo, R, stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_exp_partial(const Operand& op, int32_t* hi, int32_t* lo, hipStream_t st)
+{
+    const int rows_fast = (op.sr == 1 && op.sk != 1) ? 1 : 0;
+    dim3 grid((unsigned)((op.R + kExpRows - 1) / kExpRows),
+              (unsigned)((op.K + kExpDepth - 1) / kExpDepth));
+    hipLaunchKernelGGL(k_exp_partial, grid, dim3(256), 0, st, op, hi, lo, rows_fast);
+    return hipGetLastError();
+}
+
+hipError_t launch_exp_final(const int32_t* hi, const int32_t* lo, int64_t R, int32_t* E,
+                            int32_t* span_max, int32_t* dbgE, hipStream_t st)
+{
+    const int64_t blocks = std::max<int64_t>((R + 255) / 256, 1);
+    hipLaunchKernelGGL(k_exp_final, dim3((unsigned)blocks), dim3(256), 0, st, hi, lo, R, E,
+                       span_max, dbgE);
+    return hipGetLastError();
+}
+
+hipError_t launch_split_i8(const Operand& op, int m, const int32_t* E, int S, int64_t nrb,
+                           int64_t nkc, int8_t* out, int32_t* dbg, hipStream_t st)
+{
+    dim3 grid((unsigned)nkc, (unsigned)nrb);
+    switch (m) {
+    case 2: hipLaunchKernelGGL(k_split_i8<2>, grid, dim3(256), 0, st, op, E, S, nkc, out, dbg); break;
+    case 4: hipLaunchKernelGGL(k_split_i8<4>, grid, dim3(256), 0, st, op, E, S, nkc, out, dbg); break;
+    case 8: hipLaunchKernelGGL(k_split_i8<8>, grid, dim3(256), 0, st, op, E, S, nkc, out, dbg); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_split_f64(const Operand& op, int m, const int32_t* E, int S, int beta,
+                            int64_t nrb, int64_t nkc, double* out, int32_t* dbg, hipStream_t st)
+{
+    const int64_t blocks = (nrb * nkc + 3) / 4;
+    dim3 grid((unsigned)blocks);
+    switch (m) {
+    case 2: hipLaunchKernelGGL(k_split_f64<2>, grid, dim3(256), 0, st, op, E, S, beta, nrb, nkc, out, dbg); break;
+    case 4: hipLaunchKernelGGL(k_split_f64<4>, grid, dim3(256), 0, st, op, E, S, beta, nrb, nkc, out, dbg); break;
+    case 8: hipLaunchKernelGGL(k_split_f64<8>, grid, dim3(256), 0, st, op, E, S, beta, nrb, nkc, out, dbg); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mdg

@@ -1,0 +1,321 @@
+// Slice contraction, exact fold and renormalisation (one fused kernel).
+//
+// For every output entry the kernel forms the diagonal sums
+//   D_t = sum_{s+u=t} sum_k dA_{ik,s} dB_{kj,u},  t = 0..S-1,
+// the paper's convolution sums s_i (Section 2; the Conclusions recast them
+// as matrix products, which here run on the matrix cores), adds
+//   X = sum_t D_t 2^(beta (S-1-t))
+// exactly in a multi-word integer, and rounds C~ = X 2^(E_i + F_j - beta(S+1))
+// greedily to nearest into m words (one renormalisation per entry, the
+// paper's postponed renormalisation).
+//
+// Work split: a workgroup of 4 waves owns a 32 x 32 block of C, each wave a
+// 16 x 16 tile.  Diagonals are processed in bands of G consecutive t; for a
+// band starting at t0 (a multiple of G) the wave keeps G accumulators and a
+// sliding window of G B-fragments: at step s it multiplies A_s with
+// B_{t0+g-s} into accumulator g, so each A fragment is loaded once per band
+// and each B fragment enters the window once.  The window slot of B_u is
+// u mod G, which the fully unrolled steps resolve at compile time.
+//
+// Exactness: INT8 products accumulate in INT32 and FP64 products in FP64;
+// the host chooses the depth chunk kcc so that every diagonal sum of a chunk
+// stays below 2^31 (INT8) or 2^53 (FP64).  After each chunk the accumulators
+// are added into the exact fold.
+//
+// The fold lives in LDS: per wave, per output, ncol signed 64-bit columns
+// with weights 2^(32 q) (carry-save; normalised once at the end).
+#include "mdgemm_internal.h"
+
+namespace mdg {
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+struct FormI8 {
+    typedef v4i frag;
+    typedef v4i acc;
+    static __device__ __forceinline__ acc mma(const frag& a, const frag& b, const acc& c)
+    {
+        return __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ acc zero() { return acc{0, 0, 0, 0}; }
+    static __device__ __forceinline__ int64_t value(const acc& c, int o) { return (int64_t)c[o]; }
+    // accumulator element o of lane l is row 4 (l/16) + o, column l%16
+    static __device__ __forceinline__ int row(int lane, int o) { return 4 * (lane >> 4) + o; }
+};
+
+struct FormF64 {
+    typedef v4d frag;   // four depth steps of 4
+    typedef v4d acc;
+    static __device__ __forceinline__ acc mma(const frag& a, const frag& b, acc c)
+    {
+        c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1], b[1], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[2], b[2], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[3], b[3], c, 0, 0, 0);
+        return c;
+    }
+    static __device__ __forceinline__ acc zero() { return acc{0.0, 0.0, 0.0, 0.0}; }
+    // exact: an integer of magnitude below 2^53
+    static __device__ __forceinline__ int64_t value(const acc& c, int o) { return (int64_t)c[o]; }
+    // accumulator element o of lane l is row 4 o + l/16, column l%16
+    static __device__ __forceinline__ int row(int lane, int o) { return 4 * o + (lane >> 4); }
+};
+
+// One depth chunk of one band: diagonals t0..t0+G-1, t0 a multiple of G.
+// A and B point at slice 0 of the chunk (plus the lane); slice s is at +64 s.
+template <class Form, int G>
+__device__ __forceinline__ void band_chunk(typename Form::acc (&acc)[G],
+                                           const typename Form::frag* __restrict__ A,
+                                           const typename Form::frag* __restrict__ B, int t0)
+{
+    typedef typename Form::frag Frag;
+    Frag win[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+        win[g] = B[(t0 + g) * 64];
+    // steps s = 0 .. t0-1: every diagonal of the band has a partner
+    for (int s0 = 0; s0 < t0; s0 += G) {
+#pragma unroll
+        for (int r = 0; r < G; ++r) {
+            const int s = s0 + r;
+            if (r > 0 || s0 > 0)
+                win[(G - r) % G] = B[(t0 - s) * 64];
+            const Frag a = A[s * 64];
+#pragma unroll
+            for (int g = G - 1; g >= 0; --g)
+                acc[g] = Form::mma(a, win[(g - r + G) % G], acc[g]);
+        }
+    }
+    // step s = t0: B_0 enters
+    if (t0 > 0)
+        win[0] = B[0];
+    {
+        const Frag a = A[t0 * 64];
+#pragma unroll
+        for (int g = G - 1; g >= 0; --g)
+            acc[g] = Form::mma(a, win[g], acc[g]);
+    }
+    // steps s = t0 + p: only diagonals g >= p have a partner
+#pragma unroll
+    for (int p = 1; p < G; ++p) {
+        const Frag a = A[(t0 + p) * 64];
+#pragma unroll
+        for (int g = G - 1; g >= p; --g)
+            acc[g] = Form::mma(a, win[g - p], acc[g]);
+    }
+}
+
+// column q of output o of this lane: cols[q * 256 + o * 64]
+__device__ __forceinline__ void col_add(int64_t* cols, int o, int q, int64_t v)
+{
+    cols[q * 256 + o * 64] += v;
+}
+
+// X += v * 2^p exactly (carry-save), |v| < 2^63
+__device__ __forceinline__ void fold_add(int64_t* cols, int o, int64_t v, int p)
+{
+    const int q = p >> 5, r = p & 31;
+    const int64_t lo = v & 0xffffffffLL;    // in [0, 2^32)
+    const int64_t hi = v >> 32;             // |hi| < 2^31
+    const int64_t x = lo << r;              // < 2^63
+    const int64_t y = hi << r;              // |y| < 2^62
+    col_add(cols, o, q, x & 0xffffffffLL);
+    col_add(cols, o, q + 1, (x >> 32) + (y & 0xffffffffLL));
+    col_add(cols, o, q + 2, y >> 32);
+}
+
+__device__ __forceinline__ uint32_t limb(const int64_t* c, int q, int ncol)
+{
+    return q < ncol ? (uint32_t)c[q * 256] : 0u;
+}
+
+// 64 bits of the (nonnegative, normalised) integer starting at bit pos
+__device__ __forceinline__ uint64_t window64(const int64_t* c, int pos, int ncol)
+{
+    const int q = pos >> 5, r = pos & 31;
+    const uint64_t lo = (uint64_t)limb(c, q, ncol) | ((uint64_t)limb(c, q + 1, ncol) << 32);
+    const uint64_t hi = limb(c, q + 2, ncol);
+    return r ? ((lo >> r) | (hi << (64 - r))) : lo;
+}
+
+// Greedy round-to-nearest of X 2^scale into m words; c is one output's
+// column set (stride 256), consumed.
+__device__ void renormalise(int64_t* c, int ncol, int scale, int m, double* out, int64_t psc,
+                            bool write)
+{
+    // carry propagation: 32-bit limbs, the top one signed
+    int64_t carry = 0;
+    for (int q = 0; q < ncol; ++q) {
+        int64_t v = c[q * 256] + carry;
+        if (q < ncol - 1) {
+            carry = v >> 32;
+            v -= carry * 4294967296LL;
+        }
+        c[q * 256] = v;
+    }
+    const bool neg = c[(ncol - 1) * 256] < 0;
+    if (neg) {
+        carry = 0;
+        for (int q = 0; q < ncol; ++q) {
+            int64_t v = -c[q * 256] + carry;
+            if (q < ncol - 1) {
+                carry = v >> 32;
+                v -= carry * 4294967296LL;
+            }
+            c[q * 256] = v;
+        }
+    }
+    double sgn = neg ? -1.0 : 1.0;
+    const int umin = -1074 - scale;
+    for (int t = 0; t < m; ++t) {
+        int top = -1;
+        for (int q = ncol - 1; q >= 0; --q) {
+            const uint32_t v = (uint32_t)c[q * 256];
+            if (v) {
+                top = 32 * q + 31 - __clz((int)v);
+                break;
+            }
+        }
+        double w = 0.0;
+        if (top >= 0) {
+            int unit = max(top - 52, umin);
+            if (unit < 0)
+                unit = 0;
+            uint64_t n = window64(c, unit, ncol);
+            int rnd = 0, sticky = 0;
+            if (unit > 0) {
+                const int rb = unit - 1;
+                rnd = (int)((limb(c, rb >> 5, ncol) >> (rb & 31)) & 1u);
+                const int qs = rb >> 5;
+                for (int q = 0; q < qs && !sticky; ++q)
+                    sticky = limb(c, q, ncol) != 0;
+                if (!sticky && (rb & 31))
+                    sticky = (limb(c, qs, ncol) & ((1u << (rb & 31)) - 1u)) != 0;
+            }
+            const bool up = rnd && (sticky || (n & 1));
+            if (up)
+                n += 1;
+            w = sgn * ldexp((double)n, unit + scale);
+            // remainder: clear the bits at and above unit
+            const int qu = unit >> 5;
+            for (int q = qu + 1; q < ncol; ++q)
+                c[q * 256] = 0;
+            if (qu < ncol)
+                c[qu * 256] = (int64_t)(limb(c, qu, ncol) & ((unit & 31) ? ((1u << (unit & 31)) - 1u) : 0u));
+            if (up) {
+                // |remainder| = 2^unit - low, and its sign flips
+                uint64_t cy = 1;
+                const int qe = (unit + 31) >> 5;
+                for (int q = 0; q < qe && q < ncol; ++q) {
+                    const uint64_t v = (uint64_t)(~limb(c, q, ncol)) + cy;
+                    c[q * 256] = (int64_t)(v & 0xffffffffull);
+                    cy = v >> 32;
+                }
+                if ((unit & 31) && qe - 1 < ncol)
+                    c[(qe - 1) * 256] &= (int64_t)((1u << (unit & 31)) - 1u);
+                sgn = -sgn;
+            }
+        }
+        if (write)
+            out[t * psc] = w;
+    }
+}
+
+template <class Form, int G>
+__global__ __launch_bounds__(256, 1) void k_slice_gemm(GemmArgs a)
+{
+    typedef typename Form::frag Frag;
+    typedef typename Form::acc Acc;
+    extern __shared__ int64_t lds[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t rb = (int64_t)blockIdx.y * 2 + (wave >> 1);
+    const int64_t cb = (int64_t)blockIdx.x * 2 + (wave & 1);
+    int64_t* cols = lds + (int64_t)wave * a.ncol * 256 + lane;
+    for (int q = 0; q < a.ncol; ++q)
+#pragma unroll
+        for (int o = 0; o < 4; ++o)
+            cols[q * 256 + o * 64] = 0;
+
+    const int64_t fstride = (int64_t)a.S * 64;   // fragments of one depth chunk
+    const Frag* Ab = (const Frag*)a.A + rb * a.nkc * fstride + lane;
+    const Frag* Bb = (const Frag*)a.B + cb * a.nkc * fstride + lane;
+
+    for (int b = 0; b < a.nbands; ++b) {
+        const int t0 = b * G;
+        for (int64_t c0 = 0; c0 < a.nkc; c0 += a.kcc) {
+            Acc acc[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+                acc[g] = Form::zero();
+            const int64_t c1 = min(c0 + a.kcc, a.nkc);
+            for (int64_t kc = c0; kc < c1; ++kc)
+                band_chunk<Form, G>(acc, Ab + kc * fstride, Bb + kc * fstride, t0);
+            // exact fold of this chunk's diagonal sums
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int t = t0 + g;
+                const int p = a.beta * (a.S - 1 - t);
+#pragma unroll
+                for (int o = 0; o < 4; ++o) {
+                    const int64_t v = Form::value(acc[g], o);
+                    fold_add(cols, o, v, p);
+                    if (a.dbgD) {
+                        const int64_t i = rb * 16 + Form::row(lane, o), j = cb * 16 + (lane & 15);
+                        if (i < a.M && j < a.N)
+                            a.dbgD[((int64_t)t * a.M + i) * a.N + j] += v;
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+        const int64_t i = rb * 16 + Form::row(lane, o), j = cb * 16 + (lane & 15);
+        const bool ok = i < a.M && j < a.N;
+        const int scale = ok ? a.E[i] + a.F[j] - a.beta * (a.S + 1) : 0;
+        renormalise(cols + o * 64, a.ncol, scale, a.m, ok ? a.C + i * a.ldc + j : nullptr, a.psc, ok);
+    }
+}
+
+template <class Form, int G>
+hipError_t launch_one(const GemmArgs& a, hipStream_t st)
+{
+    const size_t lds = (size_t)4 * a.ncol * 256 * sizeof(int64_t);
+    hipError_t e = hipFuncSetAttribute((const void*)k_slice_gemm<Form, G>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess)
+        return e;
+    dim3 grid((unsigned)((a.N + kTile - 1) / kTile), (unsigned)((a.M + kTile - 1) / kTile));
+    hipLaunchKernelGGL((k_slice_gemm<Form, G>), grid, dim3(256), lds, st, a);
+    return hipGetLastError();
+}
+
+template <class Form, int G>
+struct Dispatch {
+    static hipError_t run(const GemmArgs& a, hipStream_t st)
+    {
+        if (a.band == G)
+            return launch_one<Form, G>(a, st);
+        return Dispatch<Form, G - 1>::run(a, st);
+    }
+};
+template <class Form>
+struct Dispatch<Form, 0> {
+    static hipError_t run(const GemmArgs&, hipStream_t) { return hipErrorInvalidValue; }
+};
+
+}  // namespace
+
+hipError_t launch_gemm_i8(const GemmArgs& a, hipStream_t st)
+{
+    return Dispatch<FormI8, kGmaxI8>::run(a, st);
+}
+
+hipError_t launch_gemm_f64(const GemmArgs& a, hipStream_t st)
+{
+    return Dispatch<FormF64, kGmaxF64>::run(a, st);
+}
+
+}  // namespace mdg

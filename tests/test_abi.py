@@ -1,0 +1,95 @@
+"""The C ABI without a GPU: the library loads, exports every declared entry
+point, validates arguments before touching the device, and its parameter
+rule agrees with the oracle's (written independently)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2606_20863_amd as md
+from oracle import exact as ox
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mdgemm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(md_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = md.lib()
+    names = declared_functions()
+    assert "md_gemm" in names and "md_gemm_ex" in names
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_version_and_strerror():
+    L = md.lib()
+    assert L.md_version() >= 100
+    for code in range(9):
+        assert len(L.md_strerror(code)) > 0
+    assert L.md_strerror(12345) == b"unknown error"
+
+
+def test_argument_errors_before_device_work():
+    L = md.lib()
+    p = ctypes.c_void_p(0x1000)
+    # m outside {2, 4, 8}
+    assert L.md_gemm(3, 4, 4, 4, p, p, p, None) == 1
+    # negative sizes
+    assert L.md_gemm(2, -1, 4, 4, p, p, p, None) == 2
+    # empty output: no-op success, even with NULL pointers
+    assert L.md_gemm(2, 0, 4, 4, None, None, None, None) == 0
+    assert L.md_gemm(2, 4, 0, 4, None, None, None, None) == 0
+    # NULL data pointers
+    assert L.md_gemm(2, 4, 4, 4, None, p, p, None) == 3
+    # C overlapping A
+    a = ctypes.c_void_p(0x100000)
+    c = ctypes.c_void_p(0x100000 + 8)
+    b = ctypes.c_void_p(0x900000)
+    assert L.md_gemm(2, 4, 4, 4, a, b, c, None) == 4
+    # bad leading dimension
+    opts = md.MDOpts()
+    assert L.md_gemm_ex(2, 0, 0, 4, 4, 4, a, 3, 16, b, 4, 16, ctypes.c_void_p(0x500000), 4, 16,
+                        ctypes.byref(opts), None) == 2
+    # unknown form
+    opts.form = 9
+    assert L.md_gemm_ex(2, 0, 0, 4, 4, 4, a, 4, 16, b, 4, 16, ctypes.c_void_p(0x500000), 4, 16,
+                        ctypes.byref(opts), None) == 7
+    # forced INT8 slices must be 7 bits wide
+    opts.form = 1
+    opts.force_S = 8
+    opts.force_beta = 9
+    assert L.md_gemm_ex(2, 0, 0, 4, 4, 4, a, 4, 16, b, 4, 16, ctypes.c_void_p(0x500000), 4, 16,
+                        ctypes.byref(opts), None) == 7
+
+
+@pytest.mark.parametrize("form", ["int8", "fp64"])
+@pytest.mark.parametrize("K", [1, 64, 100, 1024, 2048, 4096, 100000])
+@pytest.mark.parametrize("T,G", [(100, 2), (100, 40), (200, 3), (200, 44), (400, 9), (400, 34)])
+def test_parameter_rule_matches_oracle(form, K, T, G):
+    try:
+        ref = ox.choose_params(form, K, T, G)
+    except ValueError:
+        ref = None
+    try:
+        got = md.choose_params(form, K, T, G)
+    except md.MDError as e:
+        assert ref is None, e
+        return
+    assert got == ref
+
+
+def test_parameter_rule_exactness_and_budget():
+    for form, limit in (("int8", 2 ** 31), ("fp64", 2 ** 53)):
+        for K in (64, 1000, 4096):
+            for T, G in ((100, 2), (200, 44), (400, 34)):
+                beta, S, kc, band = md.choose_params(form, K, T, G)
+                assert S * kc * (2 ** beta - 1) ** 2 < limit
+                assert S % band == 0 and band <= 16
+                assert beta * S >= T + G + ox.ceil_log2(S + 2) + 1

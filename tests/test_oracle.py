@@ -275,7 +275,7 @@ def test_budget_rule_meets_target(name, form):
     _, sA = ox.row_exponents(A[0])
     _, sB = ox.row_exponents(B[0].T)
     G = ox.span_G(max(sA), max(sB))
-    beta, S, kc = ox.choose_params(form, 24, T, G)
+    beta, S, kc, band = ox.choose_params(form, 24, T, G)
     worst, res = _max_err(A, B, beta, S)
     assert worst <= -T
     for i in range(6):
