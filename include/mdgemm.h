@@ -89,7 +89,7 @@ typedef struct md_debug {
     int32_t *E;         /* [M]      shared exponents of the rows of op(A) */
     int32_t *F;         /* [N]      shared exponents of the columns of op(B) */
     int32_t *digits_A;  /* [S][M][K] digits of op(A) */
-    int32_t *digits_B;  /* [S][K][N] digits of op(B) */
+    int32_t *digits_B;  /* [S][N][K] digits of op(B), by column */
     int64_t *D;         /* [S][M][N] diagonal sums D_t */
 } md_debug;
 
@@ -103,6 +103,8 @@ typedef struct md_opts {
     size_t workspace_bytes;
     md_debug *dbg;         /* optional debug dump */
     md_info *info;         /* optional: receives the chosen parameters */
+    void *ev_gemm_begin;   /* optional hipEvent_t pair (caller-owned), recorded on */
+    void *ev_gemm_end;     /*   `stream` right before / after the slice contraction */
 } md_opts;
 
 /*

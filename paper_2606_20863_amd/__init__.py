@@ -54,7 +54,8 @@ class MDOpts(ctypes.Structure):
     _fields_ = [("form", ctypes.c_int), ("s_rule", ctypes.c_int), ("target_bits", ctypes.c_int),
                 ("force_S", ctypes.c_int), ("force_beta", ctypes.c_int),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
-                ("dbg", ctypes.POINTER(MDDebug)), ("info", ctypes.POINTER(MDInfo))]
+                ("dbg", ctypes.POINTER(MDDebug)), ("info", ctypes.POINTER(MDInfo)),
+                ("ev_gemm_begin", ctypes.c_void_p), ("ev_gemm_end", ctypes.c_void_p)]
 
 
 class MDError(RuntimeError):
@@ -128,13 +129,14 @@ def _check_planes(X: torch.Tensor, name: str):
 
 def gemm_ex(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None, *, transA=False,
             transB=False, form="fp64", target_bits=0, force_S=0, force_beta=0, debug=None,
-            workspace: torch.Tensor | None = None, stream=None):
+            workspace: torch.Tensor | None = None, events=None, stream=None):
     """C = op(A) op(B) in m-double arithmetic.
 
     A is (m, M, K) (or (m, K, M) with transA), B is (m, K, N) (or (m, N, K)
     with transB); both contiguous per plane.  Returns (C, info dict).
     ``debug`` may be a dict of preallocated device tensors with keys E, F,
-    digits_A, digits_B, D (see ``md_debug``).
+    digits_A, digits_B, D (see ``md_debug``).  ``events`` may be a pair of
+    raw hipEvent_t handles recorded around the slice contraction.
     """
     _check_planes(A, "A")
     _check_planes(B, "B")
@@ -161,6 +163,9 @@ def gemm_ex(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None, *, 
     if workspace is not None:
         opts.workspace = ctypes.c_void_p(workspace.data_ptr())
         opts.workspace_bytes = workspace.numel() * workspace.element_size()
+    if events is not None:
+        opts.ev_gemm_begin = ctypes.c_void_p(events[0])
+        opts.ev_gemm_end = ctypes.c_void_p(events[1])
     dbg = None
     if debug:
         dbg = MDDebug()

@@ -410,8 +410,12 @@ int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, c
     ga.m = m;
     ga.ncol = ncol;
     ga.dbgD = dbg ? dbg->D : nullptr;
+    if (o.ev_gemm_begin && (e = hipEventRecord((hipEvent_t)o.ev_gemm_begin, st)) != hipSuccess)
+        return hip_fail(e);
     e = o.form == MD_FORM_INT8 ? launch_gemm_i8(ga, st) : launch_gemm_f64(ga, st);
     if (e != hipSuccess)
+        return hip_fail(e);
+    if (o.ev_gemm_end && (e = hipEventRecord((hipEvent_t)o.ev_gemm_end, st)) != hipSuccess)
         return hip_fail(e);
 
     if (o.info) {
