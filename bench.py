@@ -62,6 +62,7 @@ def run_form(md, torch, A, B, form, steps, warmup):
     t0 = time.perf_counter()
     for i in range(steps):
         C, info = md.gemm_ex(A, B, form=form, events=evs[i])
+    info["rule"] = "rho" if info["G"] != info["G_span"] or info["G_rho"] >= 0 else "span"
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kern = [elapsed_ms(hip, e) for e in evs]
@@ -162,7 +163,7 @@ def main():
         "config": {"workload": f"{WORKLOAD}: quad-double (m=4) C = A B, M=N=K=4096, leading words "
                                "U(-1,1), trailing words 2^-53 U(-1,1)",
                    "M": M, "N": N, "K": K, "m": m, "target_bits": info8["target_bits"],
-                   "s_rule": "span"},
+                   "s_rule": info8.get("rule", "rho")},
         "int8_form": {"S": S8, "beta": info8["beta"], "kc": info8["kc"], "band": info8["band"],
                       "ms_per_call": round(ms8, 4), "gemm_kernel_ms": round(kern8, 4),
                       "effective_gflops": round(eff8, 3),

@@ -67,8 +67,13 @@ extern "C" {
 #define MD_FORM_FP64 0
 #define MD_FORM_INT8 1
 
-/* slice-count rules */
-#define MD_S_SPAN 0        /* certified by the exponent spans of A and B */
+/* slice-count rules: both bound 2^G >= max_ij N_ij 2^(E_i+F_j) / (|A||B|)_ij,
+ * N_ij the number of k with a_ik b_kj != 0; S is the smallest count with
+ * beta S >= T + G + ceil(log2(S+2)) + 1 (rounded up to equal bands).  The
+ * certificates assume strongly nonoverlapping words, |w_{t+1}| <= ulp(w_t)/2. */
+#define MD_S_RHO 0         /* default: the smaller of the span bound and a magnitude bound
+                              from one extra INT8 product of 7-bit leading-word magnitudes */
+#define MD_S_SPAN 1        /* span bound only: G = span_A + span_B + 2 */
 
 /* Result of a call: the parameters the library chose. */
 typedef struct md_info {
@@ -79,6 +84,8 @@ typedef struct md_info {
     int span_A;         /* max over rows of A of (E_i - smallest exponent) */
     int span_B;         /* same over the columns of B */
     int G;              /* log2 of the certified ratio bound used by the rule */
+    int G_span;         /* span bound: span_A + span_B + 2 */
+    int G_rho;          /* magnitude bound (-1: not computed or not certifiable) */
     int target_bits;    /* T */
     double log2_bound;  /* certified log2 of the max relative error vs (|A||B|)_ij */
 } md_info;
@@ -95,7 +102,7 @@ typedef struct md_debug {
 
 typedef struct md_opts {
     int form;              /* MD_FORM_FP64 (default) or MD_FORM_INT8 */
-    int s_rule;            /* MD_S_SPAN */
+    int s_rule;            /* MD_S_RHO (default) or MD_S_SPAN */
     int target_bits;       /* 0: T = 50 m */
     int force_S;           /* > 0: use this S (and force_beta) instead of the rule */
     int force_beta;        /* with force_S: slice width (INT8: 7; FP64: 8..24) */
@@ -127,7 +134,7 @@ int md_gemm(int m, int64_t M, int64_t N, int64_t K, const double *A, const doubl
  *   op(B) is K x N: element (k, j) at B[k*ldb + j] (transB = 0) or
  *   B[j*ldb + k] (transB = 1), word w at + w*plane_stride_B.
  *   C: element (i, j) word w at C[w*plane_stride_C + i*ldc + j].
- *   opts may be NULL (FP64 form, span rule, T = 50 m).
+ *   opts may be NULL (FP64 form, MD_S_RHO rule, T = 50 m).
  */
 int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, const double *A,
                int64_t lda, int64_t plane_stride_A, const double *B, int64_t ldb,

@@ -372,6 +372,39 @@ def span_G(span_A: int, span_B: int) -> int:
     return span_A + span_B + 2
 
 
+def rho_G(A: np.ndarray, B: np.ndarray):
+    """Magnitude certificate for the ratio N_ij 2^(E_i+F_j) / (|A||B|)_ij.
+
+    q_ik = floor(|a_ik^(0)| 2^(7 - E_i)) and likewise for the columns of B;
+    strongly nonoverlapping words give |a_ik| >= (1 - 2^-52) q_ik 2^(E_i-7),
+    hence the ratio is at most K 2^14 / ((1 - 2^-51) min_ij P_ij) with
+    P = q_A q_B.  Returns (min P, G): G the smallest g >= 0 with
+    min P * 2^g >= K 2^14 + 1, or None when min P = 0.
+    """
+    K = A.shape[2]
+    E, _ = row_exponents(A[0])
+    F, _ = row_exponents(B[0].T)
+    qa = np.zeros(A.shape[1:], dtype=np.int64)
+    qb = np.zeros(B.shape[1:], dtype=np.int64)
+    for i in range(A.shape[1]):
+        for k in range(K):
+            x = Fraction(abs(float(A[0, i, k]))) * Fraction(2) ** (7 - E[i])
+            qa[i, k] = x.numerator // x.denominator
+    for k in range(K):
+        for j in range(B.shape[2]):
+            x = Fraction(abs(float(B[0, k, j]))) * Fraction(2) ** (7 - F[j])
+            qb[k, j] = x.numerator // x.denominator
+    P = qa @ qb
+    minP = int(P.min())
+    if minP == 0:
+        return 0, None
+    target = K * (1 << 14) + 1
+    g = 0
+    while (minP << g) < target:
+        g += 1
+    return minP, g
+
+
 INT8_KGRAN = 64     # depth granule of the INT8 slice contraction
 FP64_KGRAN = 16     # depth granule of the FP64 slice contraction
 INT8_GMAX = 16      # widest band of diagonals the INT8 contraction handles

@@ -29,6 +29,7 @@ LIB_PATH = os.path.join(HERE, "libmdgemm.so")
 FORM_FP64 = 0
 FORM_INT8 = 1
 _FORMS = {"fp64": FORM_FP64, "int8": FORM_INT8}
+_RULES = {"rho": 0, "span": 1}
 
 ERRORS = {
     0: "MD_OK", 1: "MD_EINVAL_M", 2: "MD_EINVAL_DIM", 3: "MD_ENULL", 4: "MD_EALIAS",
@@ -39,7 +40,8 @@ ERRORS = {
 class MDInfo(ctypes.Structure):
     _fields_ = [("S", ctypes.c_int), ("beta", ctypes.c_int), ("kc", ctypes.c_int),
                 ("band", ctypes.c_int), ("span_A", ctypes.c_int), ("span_B", ctypes.c_int),
-                ("G", ctypes.c_int), ("target_bits", ctypes.c_int), ("log2_bound", ctypes.c_double)]
+                ("G", ctypes.c_int), ("G_span", ctypes.c_int), ("G_rho", ctypes.c_int),
+                ("target_bits", ctypes.c_int), ("log2_bound", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -128,8 +130,8 @@ def _check_planes(X: torch.Tensor, name: str):
 
 
 def gemm_ex(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None, *, transA=False,
-            transB=False, form="fp64", target_bits=0, force_S=0, force_beta=0, debug=None,
-            workspace: torch.Tensor | None = None, events=None, stream=None):
+            transB=False, form="fp64", rule="rho", target_bits=0, force_S=0, force_beta=0,
+            debug=None, workspace: torch.Tensor | None = None, events=None, stream=None):
     """C = op(A) op(B) in m-double arithmetic.
 
     A is (m, M, K) (or (m, K, M) with transA), B is (m, K, N) (or (m, N, K)
@@ -156,6 +158,7 @@ def gemm_ex(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None, *, 
     info = MDInfo()
     opts = MDOpts()
     opts.form = _FORMS[form]
+    opts.s_rule = _RULES[rule]
     opts.target_bits = target_bits
     opts.force_S = force_S
     opts.force_beta = force_beta

@@ -101,6 +101,22 @@ int fold_columns(int beta, int S, int64_t Kp)
 
 int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 
+// Magnitude certificate.  With q = floor(|a^(0)| 2^(7-E_i)) and strongly
+// nonoverlapping words, |a_ik||b_kj| >= (1 - 2^-51) 2^(E_i+F_j-14) qA_ik qB_kj,
+// so N_ij 2^(E_i+F_j) / (|A||B|)_ij <= K 2^14 / ((1 - 2^-51) minP).  Returns the
+// smallest G >= 0 with minP 2^G >= K 2^14 + 1 (which covers the 1 - 2^-51
+// factor for K < 2^36), or -1 when minP is 0 (no certificate).
+int rho_exponent(uint64_t minP, int64_t K)
+{
+    if (minP == 0 || minP == ~0ull)
+        return -1;
+    const unsigned __int128 target = ((unsigned __int128)K << 14) + 1;
+    int g = 0;
+    while (((unsigned __int128)minP << g) < target)
+        ++g;
+    return g;
+}
+
 struct Span {
     uintptr_t lo, hi;  // [lo, hi) in bytes; empty if lo == hi
 };
@@ -155,7 +171,7 @@ struct Scratch {
     char* user = nullptr;
     size_t user_bytes = 0, used = 0;
     hipStream_t st = nullptr;
-    void* owned[4] = {nullptr, nullptr, nullptr, nullptr};
+    void* owned[8] = {};
     int nowned = 0;
 
     int get(size_t bytes, void** out)
@@ -175,6 +191,10 @@ struct Scratch {
         hipError_t e = hipMallocFromPoolAsync(out, std::max<size_t>(bytes, 256), pool, st);
         if (e != hipSuccess) {
             (void)hipGetLastError();
+            return MD_ENOMEM;
+        }
+        if (nowned == 8) {
+            (void)hipFreeAsync(*out, st);
             return MD_ENOMEM;
         }
         owned[nowned++] = *out;
@@ -240,7 +260,8 @@ int md_choose_params(int form, int64_t K, int T, int G, int* beta, int* S, int* 
 
 size_t md_workspace_size(int form, int64_t M, int64_t N, int64_t K, int S)
 {
-    return small_bytes(M, N) + digits_bytes(form, M, K, S) + digits_bytes(form, N, K, S) + 1024;
+    return small_bytes(M, N) + digits_bytes(MD_FORM_INT8, M, K, 1) + digits_bytes(MD_FORM_INT8, N, K, 1) +
+           digits_bytes(form, M, K, S) + digits_bytes(form, N, K, S) + 4096;
 }
 
 int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, const double* A,
@@ -259,7 +280,7 @@ int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, c
         o = *opts;
     if (o.form != MD_FORM_FP64 && o.form != MD_FORM_INT8)
         return MD_EINVAL_OPT;
-    if (o.s_rule != MD_S_SPAN)
+    if (o.s_rule != MD_S_SPAN && o.s_rule != MD_S_RHO)
         return MD_EINVAL_OPT;
     if (M == 0 || N == 0)
         return MD_OK;
@@ -335,10 +356,29 @@ int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, c
     if ((e = launch_exp_final(hiA, loA, M, E, stats, dbg ? dbg->E : nullptr, st)) != hipSuccess) return hip_fail(e);
     if ((e = launch_exp_final(hiB, loB, N, F, stats + 1, dbg ? dbg->F : nullptr, st)) != hipSuccess) return hip_fail(e);
 
-    int spans[2] = {0, 0};
+    int32_t spans[4] = {0, 0, 0, 0};   // span_A, span_B, minimum magnitude product (uint64)
     int beta, S, band;
     int64_t kc;
-    int G = 0;
+    int G = 0, G_span = 0, G_rho = -1;
+    const bool use_rho = o.force_S == 0 && o.s_rule == MD_S_RHO;
+    if (use_rho) {
+        // magnitude certificate: min_ij sum_k qA_ik qB_kj, q the 7-bit
+        // leading-word magnitudes on the shared-exponent grid
+        const int64_t nkm = (K + kKcI8 - 1) / kKcI8;
+        void *qA, *qB;
+        int rc = scr.get(digits_bytes(MD_FORM_INT8, M, K, 1), &qA);
+        if (rc)
+            return rc;
+        rc = scr.get(digits_bytes(MD_FORM_INT8, N, K, 1), &qB);
+        if (rc)
+            return rc;
+        if ((e = launch_split_mag(opA, E, round_up(M, kTile) / kRowBlock, nkm, (int8_t*)qA, st)) != hipSuccess)
+            return hip_fail(e);
+        if ((e = launch_split_mag(opB, F, round_up(N, kTile) / kRowBlock, nkm, (int8_t*)qB, st)) != hipSuccess)
+            return hip_fail(e);
+        if ((e = launch_mag_min(qA, qB, M, N, nkm, (unsigned long long*)(stats + 2), st)) != hipSuccess)
+            return hip_fail(e);
+    }
     if (o.force_S > 0) {
         beta = o.force_beta;
         const int gmax = o.form == MD_FORM_INT8 ? kGmaxI8 : kGmaxF64;
@@ -356,7 +396,15 @@ int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, c
             return hip_fail(e);
         if ((e = hipStreamSynchronize(st)) != hipSuccess)
             return hip_fail(e);
-        G = spans[0] + spans[1] + 2;
+        G_span = spans[0] + spans[1] + 2;
+        G = G_span;
+        if (use_rho) {
+            uint64_t minP;
+            memcpy(&minP, spans + 2, sizeof(minP));
+            G_rho = rho_exponent(minP, K);
+            if (G_rho >= 0 && G_rho < G)
+                G = G_rho;
+        }
         const int rc = choose(o.form, K, T, G, beta, S, kc, band);
         if (rc)
             return rc;
@@ -427,6 +475,8 @@ int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, c
         in->span_A = spans[0];
         in->span_B = spans[1];
         in->G = G;
+        in->G_span = G_span;
+        in->G_rho = G_rho;
         in->target_bits = T;
         // certified bound of the method plus the final rounding
         const double lb = (double)(G - beta * S) + __builtin_log2((double)S + 2.0);

@@ -63,10 +63,17 @@ hipError_t launch_exp_final(const int32_t* hi, const int32_t* lo, int64_t R, int
 
 hipError_t launch_split_i8(const Operand& op, int m, const int32_t* E, int S, int64_t nrb,
                            int64_t nkc, int8_t* out, int32_t* dbg, hipStream_t st);
+// one INT8 slice of leading-word magnitudes (ratio certificate)
+hipError_t launch_split_mag(const Operand& op, const int32_t* E, int64_t nrb, int64_t nkc,
+                            int8_t* out, hipStream_t st);
 hipError_t launch_split_f64(const Operand& op, int m, const int32_t* E, int S, int beta,
                             int64_t nrb, int64_t nkc, double* out, int32_t* dbg, hipStream_t st);
 
 hipError_t launch_gemm_i8(const GemmArgs& a, hipStream_t st);
+// minP[0] = min over (i < M, j < N) of sum_k qA_ik qB_kj (must start at
+// UINT64_MAX); qA, qB from launch_split_mag, nkc depth fragments each.
+hipError_t launch_mag_min(const void* qA, const void* qB, int64_t M, int64_t N, int64_t nkc,
+                          unsigned long long* minP, hipStream_t st);
 hipError_t launch_gemm_f64(const GemmArgs& a, hipStream_t st);
 
 }  // namespace mdg

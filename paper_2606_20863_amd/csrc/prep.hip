@@ -67,6 +67,8 @@ __global__ void k_fill_zero(double* C, int m, int64_t M, int64_t N, int64_t ldc,
     }
 }
 
+// stats: [0] span max of A, [1] span max of B, [2..3] (as one uint64) the
+// minimum magnitude product, started at its largest value
 __global__ void k_exp_init(int32_t* hi, int32_t* lo, int64_t R, int32_t* stats)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -76,6 +78,8 @@ __global__ void k_exp_init(int32_t* hi, int32_t* lo, int64_t R, int32_t* stats)
     }
     if (r < 2 && stats)
         stats[r] = 0;
+    if (r == 0 && stats)
+        *reinterpret_cast<unsigned long long*>(stats + 2) = ~0ull;
 }
 
 // Block: 16 rows x 1024 depth, 256 threads; each row's 16 threads reduce
@@ -216,6 +220,33 @@ __global__ __launch_bounds__(256) void k_split_i8(Operand op, const int32_t* E, 
     }
 }
 
+// Magnitude digits for the ratio certificate: q = floor(|a^(0)| 2^(7 - E_r)),
+// in [0, 127] because |a^(0)| < 2^E_r; one slice in INT8 fragment order.
+// Nonoverlapping words give |a| >= |a^(0)| (1 - 2^-52) >= q 2^(E_r - 7) (1 - 2^-52).
+__global__ __launch_bounds__(256) void k_split_mag(Operand op, const int32_t* E, int64_t nkc,
+                                                   int8_t* out)
+{
+    const int T = threadIdx.x;
+    const int64_t rb = blockIdx.y, kc = blockIdx.x;
+    const int L = T >> 2;
+    const int64_t r = rb * kRowBlock + (L & 15);
+    const int64_t kbase = kc * kKcI8 + 16 * (L >> 4) + 4 * (T & 3);
+    const bool row_ok = r < op.R;
+    const int Er = row_ok ? E[r] : 0;
+    uint32_t packed = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t k = kbase + q;
+        const double x = (row_ok && k < op.K) ? op.p[r * op.sr + k * op.sk] : 0.0;
+        uint64_t mant;
+        int ex;
+        decode(x, mant, ex);
+        const uint64_t v = field(mant, ex + 7 - Er, 127);
+        packed |= (uint32_t)v << (8 * q);
+    }
+    reinterpret_cast<uint32_t*>(out)[(rb * nkc + kc) * 256 + T] = packed;
+}
+
 // FP64 split: one wave writes one fragment (64 lanes x 4 doubles); lane l
 // holds row l%16, depth 4q + l/16.
 template <int MW>
@@ -330,6 +361,14 @@ hipError_t launch_split_i8(const Operand& op, int m, const int32_t* E, int S, in
     case 8: hipLaunchKernelGGL(k_split_i8<8>, grid, dim3(256), 0, st, op, E, S, nkc, out, dbg); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_split_mag(const Operand& op, const int32_t* E, int64_t nrb, int64_t nkc,
+                            int8_t* out, hipStream_t st)
+{
+    dim3 grid((unsigned)nkc, (unsigned)nrb);
+    hipLaunchKernelGGL(k_split_mag, grid, dim3(256), 0, st, op, E, nkc, out);
     return hipGetLastError();
 }
 

@@ -306,7 +306,85 @@ struct Dispatch<Form, 0> {
     static hipError_t run(const GemmArgs&, hipStream_t) { return hipErrorInvalidValue; }
 };
 
+// min over the outputs of P_ij = sum_k qA_ik qB_kj: a wave computes a 64 x 64
+// block (4 x 4 fragments), a workgroup 128 x 128.  Each 16 x 16 fragment sum
+// of one depth fragment is below 64 * 127^2 < 2^20, so INT32 holds 2^11
+// depth fragments exactly; longer depths are carried into int64.
+__global__ __launch_bounds__(256) void k_mag_min(const v4i* __restrict__ qA,
+                                                 const v4i* __restrict__ qB, int64_t M, int64_t N,
+                                                 int64_t nkc, unsigned long long* minP)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t rb0 = ((int64_t)blockIdx.y * 2 + (wave >> 1)) * 4;
+    const int64_t cb0 = ((int64_t)blockIdx.x * 2 + (wave & 1)) * 4;
+    const int64_t nrb = (M + 15) / 16, ncb = (N + 15) / 16;
+    v4i acc[4][4];
+    int64_t tot[4][4][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+            acc[x][y] = v4i{0, 0, 0, 0};
+#pragma unroll
+            for (int o = 0; o < 4; ++o)
+                tot[x][y][o] = 0;
+        }
+    for (int64_t kc = 0; kc < nkc; ++kc) {
+        v4i a[4], b[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+            const int64_t rb = min(rb0 + x, nrb - 1);
+            const int64_t cb = min(cb0 + x, ncb - 1);
+            a[x] = qA[(rb * nkc + kc) * 64 + lane];
+            b[x] = qB[(cb * nkc + kc) * 64 + lane];
+        }
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y)
+                acc[x][y] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[x], b[y], acc[x][y], 0, 0, 0);
+        if ((kc & 2047) == 2047 || kc == nkc - 1) {
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y) {
+#pragma unroll
+                    for (int o = 0; o < 4; ++o)
+                        tot[x][y][o] += acc[x][y][o];
+                    acc[x][y] = v4i{0, 0, 0, 0};
+                }
+        }
+    }
+    unsigned long long best = ~0ull;
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+#pragma unroll
+            for (int o = 0; o < 4; ++o) {
+                const int64_t i = (rb0 + x) * 16 + FormI8::row(lane, o);
+                const int64_t j = (cb0 + y) * 16 + (lane & 15);
+                if (i < M && j < N && (unsigned long long)tot[x][y][o] < best)
+                    best = (unsigned long long)tot[x][y][o];
+            }
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(best, off);
+        best = o < best ? o : best;
+    }
+    if (lane == 0 && best != ~0ull)
+        atomicMin(minP, best);
+}
+
 }  // namespace
+
+hipError_t launch_mag_min(const void* qA, const void* qB, int64_t M, int64_t N, int64_t nkc,
+                          unsigned long long* minP, hipStream_t st)
+{
+    dim3 grid((unsigned)((N + 127) / 128), (unsigned)((M + 127) / 128));
+    hipLaunchKernelGGL(k_mag_min, grid, dim3(256), 0, st, (const v4i*)qA, (const v4i*)qB, M, N,
+                       nkc, minP);
+    return hipGetLastError();
+}
 
 hipError_t launch_gemm_i8(const GemmArgs& a, hipStream_t st)
 {

@@ -91,21 +91,29 @@ def test_bitexact_transposed_operands(transA, transB, form, S, beta):
     check_against_oracle(A, B, got, beta, S)
 
 
+@pytest.mark.parametrize("rule", ["rho", "span"])
 @pytest.mark.parametrize("form", ["int8", "fp64"])
 @pytest.mark.parametrize("name", ["dd64", "qd1024", "od1024"])
-def test_rule_and_bound_small(form, name):
+def test_rule_and_bound_small(form, name, rule):
     """Default parameters: the library's rule equals the oracle's, the
     output equals the oracle's method layer bit for bit, and every entry is
     within 2^-T of (|A||B|)_ij of the exact product."""
     _, m, _, _, _, _, _ = mdinputs.WORKLOADS[name]
     A, B = mdinputs.workload(name, M=48, N=40, K=72)
-    C, info = md.gemm_ex(dev(A), dev(B), form=form)
+    C, info = md.gemm_ex(dev(A), dev(B), form=form, rule=rule)
     C = host(C)
     T = ox.TARGET_BITS[m]
     E, sA = ox.row_exponents(A[0])
     F, sB = ox.row_exponents(B[0].T)
-    G = ox.span_G(max(sA), max(sB))
-    assert (info["span_A"], info["span_B"], info["G"]) == (max(sA), max(sB), G)
+    G_span = ox.span_G(max(sA), max(sB))
+    assert (info["span_A"], info["span_B"], info["G_span"]) == (max(sA), max(sB), G_span)
+    G = G_span
+    if rule == "rho":
+        _, G_rho = ox.rho_G(A, B)
+        assert info["G_rho"] == (-1 if G_rho is None else G_rho)
+        if G_rho is not None:
+            G = min(G_span, G_rho)
+    assert info["G"] == G
     beta, S, kc, band = ox.choose_params(form, 72, T, G)
     assert (info["beta"], info["S"], info["kc"], info["band"]) == (beta, S, kc, band)
     ref = ox.method_product(A, B, beta, S)
@@ -118,6 +126,17 @@ def test_rule_and_bound_small(form, name):
     for i in range(0, 48, 7):
         for j in range(0, 40, 5):
             assert ox.is_nonoverlapping(C[:, i, j], strong=True)
+
+
+def test_rho_certificate_falls_back_to_span():
+    """A zero magnitude product (disjoint supports) leaves only the span
+    certificate; the product is then exactly zero where it must be."""
+    A, B = mdinputs.workload("dd64", M=16, N=16, K=64)
+    A[:, :, 32:] = 0.0
+    B[:, :32, :] = 0.0
+    C, info = md.gemm_ex(dev(A), dev(B), form="int8")
+    assert info["G_rho"] == -1 and info["G"] == info["G_span"]
+    assert np.all(host(C) == 0.0)
 
 
 def test_dd64_workload_both_forms_full():
