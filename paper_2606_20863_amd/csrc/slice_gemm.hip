@@ -35,6 +35,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 struct FormI8 {
     typedef v4i frag;
     typedef v4i acc;
+    static constexpr bool kPipelined = true;
     static __device__ __forceinline__ acc mma(const frag& a, const frag& b, const acc& c)
     {
         return __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c, 0, 0, 0);
@@ -48,6 +49,7 @@ struct FormI8 {
 struct FormF64 {
     typedef v4d frag;   // four depth steps of 4
     typedef v4d acc;
+    static constexpr bool kPipelined = false;
     static __device__ __forceinline__ acc mma(const frag& a, const frag& b, acc c)
     {
         c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], c, 0, 0, 0);
@@ -104,6 +106,113 @@ __device__ __forceinline__ void band_chunk(typename Form::acc (&acc)[G],
 #pragma unroll
         for (int g = G - 1; g >= p; --g)
             acc[g] = Form::mma(a, win[g - p], acc[g]);
+    }
+}
+
+// Software-pipelined run of depth chunks [c0, c1) for one band (t0 a
+// multiple of G, P < G).  A step s of a chunk uses A_s and, for 1 <= s <= t0,
+// the entering fragment B_{t0-s}; both are loaded P steps ahead into a small
+// ring (pa, pb), across chunk boundaries.  The next chunk's window is loaded
+// one fragment per tail step into the slot whose last use was the step
+// before.  Scheduling barriers keep each step's loads ahead of its matrix
+// instructions.  Loads past the last chunk re-read the current chunk.
+template <class Form, int G, int P>
+__device__ __forceinline__ void band_run(typename Form::acc (&acc)[G],
+                                         const typename Form::frag* __restrict__ A,
+                                         const typename Form::frag* __restrict__ B,
+                                         int64_t fstride, int64_t c0, int64_t c1, int t0)
+{
+    static_assert(P >= 1 && P < G, "prefetch distance must be below the band width");
+    typedef typename Form::frag Frag;
+    const Frag* Ak = A + c0 * fstride;
+    const Frag* Bk = B + c0 * fstride;
+    Frag win[G], pa[P], pb[P];
+#pragma unroll
+    for (int g = G - 1; g >= 0; --g)
+        win[g] = Bk[(t0 + g) * 64];
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        pa[q] = Ak[q * 64];
+        pb[q] = (q >= 1 && q <= t0) ? Bk[(t0 - q) * 64] : pa[q];
+    }
+    for (int64_t kc = c0; kc < c1; ++kc) {
+        const bool more = kc + 1 < c1;
+        const Frag* An = more ? Ak + fstride : Ak;
+        const Frag* Bn = more ? Bk + fstride : Bk;
+        // steps s = 0 .. t0-1
+        for (int s0 = 0; s0 < t0; s0 += G) {
+#pragma unroll
+            for (int r = 0; r < G; ++r) {
+                const int s = s0 + r;
+                const Frag a = pa[0];
+                const Frag b = pb[0];
+#pragma unroll
+                for (int q = 0; q + 1 < P; ++q) {
+                    pa[q] = pa[q + 1];
+                    pb[q] = pb[q + 1];
+                }
+                pa[P - 1] = Ak[(s + P) * 64];
+                if (s + P <= t0)
+                    pb[P - 1] = Bk[(t0 - s - P) * 64];
+                if (r > 0 || s0 > 0)
+                    win[(G - r) % G] = b;
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int g = G - 1; g >= 0; --g)
+                    acc[g] = Form::mma(a, win[(g - r + G) % G], acc[g]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        // step s = t0: B_0 enters; slot 0 of the next window is free after it
+        Frag nwin[G];
+        {
+            const Frag a = pa[0];
+            const Frag b = pb[0];
+#pragma unroll
+            for (int q = 0; q + 1 < P; ++q) {
+                pa[q] = pa[q + 1];
+                pb[q] = pb[q + 1];
+            }
+            pa[P - 1] = Ak[(t0 + P) * 64];
+            if (t0 > 0)
+                win[0] = b;
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int g = G - 1; g >= 0; --g)
+                acc[g] = Form::mma(a, win[g], acc[g]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // tail steps s = t0 + p, p = 1 .. G-1: diagonals g >= p
+#pragma unroll
+        for (int p = 1; p < G; ++p) {
+            const Frag a = pa[0];
+#pragma unroll
+            for (int q = 0; q + 1 < P; ++q) {
+                pa[q] = pa[q + 1];
+                pb[q] = pb[q + 1];
+            }
+            const int nq = p + P - G;       // step of the next chunk, if >= 0
+            if (nq < 0) {
+                pa[P - 1] = Ak[(t0 + p + P) * 64];
+            } else {
+                pa[P - 1] = An[nq * 64];
+                if (nq >= 1 && nq <= t0)
+                    pb[P - 1] = Bn[(t0 - nq) * 64];
+            }
+            // slot G-p was last read at step t0 + p - 1
+            nwin[G - p] = Bn[(t0 + G - p) * 64];
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int g = G - 1; g >= p; --g)
+                acc[g] = Form::mma(a, win[g - p], acc[g]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        nwin[0] = Bn[t0 * 64];
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+            win[g] = nwin[g];
+        Ak = An;
+        Bk = Bn;
     }
 }
 
@@ -250,8 +359,12 @@ __global__ __launch_bounds__(256, 1) void k_slice_gemm(GemmArgs a)
             for (int g = 0; g < G; ++g)
                 acc[g] = Form::zero();
             const int64_t c1 = min(c0 + a.kcc, a.nkc);
-            for (int64_t kc = c0; kc < c1; ++kc)
-                band_chunk<Form, G>(acc, Ab + kc * fstride, Bb + kc * fstride, t0);
+            if constexpr (Form::kPipelined && G > 3) {
+                band_run<Form, G, 3>(acc, Ab, Bb, fstride, c0, c1, t0);
+            } else {
+                for (int64_t kc = c0; kc < c1; ++kc)
+                    band_chunk<Form, G>(acc, Ab + kc * fstride, Bb + kc * fstride, t0);
+            }
             // exact fold of this chunk's diagonal sums
 #pragma unroll
             for (int g = 0; g < G; ++g) {
