@@ -176,7 +176,7 @@ def main():
                       "max_log2_err_sampled": round(err64, 2),
                       "certified_log2_bound": round(info64["log2_bound"], 2)},
         "int8_over_fp64": round(eff8 / eff64, 3),
-        "roofline": {"bound": "mfma", "kernel": "k_slice_gemm<FormI8> (INT8 slice contraction)",
+        "roofline": {"bound": "mfma", "kernel": f"k_tri_i8<{S8}> (INT8 slice contraction)" if info8["band"] == S8 else "k_slice_gemm<FormI8> (INT8 slice contraction)",
                      "achieved": round(ach8, 3), "peak": PEAK_INT8_TOPS, "unit": "TFLOP/s",
                      "frac": round(ach8 / PEAK_INT8_TOPS, 4), "traffic": None,
                      "work_per_launch": f"2*M*N*K*S(S+1)/2 = {ops8:.4e} int8 ops"},

@@ -409,11 +409,15 @@ INT8_KGRAN = 64     # depth granule of the INT8 slice contraction
 FP64_KGRAN = 16     # depth granule of the FP64 slice contraction
 INT8_GMAX = 16      # widest band of diagonals the INT8 contraction handles
 FP64_GMAX = 16      # same, FP64
+INT8_SINGLE = 32    # INT8: up to this many diagonals form one band
 
 
-def band_round(S: int, gmax: int):
+def band_round(S: int, gmax: int, single: int = 0):
     """Round S up so that it splits into nb equal bands of at most gmax
-    diagonals: nb = ceil(S / gmax), band = ceil(S / nb).  Returns (S, band)."""
+    diagonals: nb = ceil(S / gmax), band = ceil(S / nb); S <= single stays
+    one band.  Returns (S, band)."""
+    if S <= single:
+        return S, S
     nb = -(-S // gmax)
     band = -(-S // nb)
     return nb * band, band
@@ -439,7 +443,7 @@ def choose_params(form: str, K: int, T: int, G: int):
     chunk Kc.
     """
     if form == "int8":
-        S, band = band_round(slice_count(7, T, G), INT8_GMAX)
+        S, band = band_round(slice_count(7, T, G), INT8_GMAX, INT8_SINGLE)
         kc = chunk_depth(S, 7, K, 1 << 31, INT8_KGRAN)
         if kc <= 0:
             raise ValueError("no exact INT8 chunking")

@@ -43,9 +43,14 @@ int slice_count(int beta, int T, int G)
 }
 
 // Bands of at most gmax diagonals, all of one width: S rounds up to
-// nb * ceil(S / nb) with nb = ceil(S / gmax).
-void band_round(int Smin, int gmax, int& S, int& band)
+// nb * ceil(S / nb) with nb = ceil(S / gmax); S <= single stays one band
+// (INT8 contracts up to kTriMaxI8 diagonals at once).
+void band_round(int Smin, int gmax, int single, int& S, int& band)
 {
+    if (Smin <= single) {
+        S = band = Smin;
+        return;
+    }
     const int nb = (Smin + gmax - 1) / gmax;
     band = (Smin + nb - 1) / nb;
     S = nb * band;
@@ -68,7 +73,7 @@ int choose(int form, int64_t K, int T, int G, int& beta, int& S, int64_t& kc, in
         return MD_EINVAL_OPT;
     if (form == MD_FORM_INT8) {
         beta = 7;
-        band_round(slice_count(7, T, G), kGmaxI8, S, band);
+        band_round(slice_count(7, T, G), kGmaxI8, kTriMaxI8, S, band);
         kc = chunk_depth(S, 7, K, (int64_t)1 << 31, kKcI8);
         return kc > 0 ? MD_OK : MD_ERANGE;
     }
@@ -76,7 +81,7 @@ int choose(int form, int64_t K, int T, int G, int& beta, int& S, int64_t& kc, in
         bool found = false;
         for (int b = 8; b <= 24; ++b) {
             int s, bd;
-            band_round(slice_count(b, T, G), kGmaxF64, s, bd);
+            band_round(slice_count(b, T, G), kGmaxF64, 0, s, bd);
             const int64_t k = chunk_depth(s, b, K, (int64_t)1 << 53, kKcF64);
             if (k <= 0)
                 continue;
@@ -382,8 +387,9 @@ int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, c
     if (o.force_S > 0) {
         beta = o.force_beta;
         const int gmax = o.form == MD_FORM_INT8 ? kGmaxI8 : kGmaxF64;
+        const int single = o.form == MD_FORM_INT8 ? kTriMaxI8 : 0;
         int s2;
-        band_round(o.force_S, gmax, s2, band);
+        band_round(o.force_S, gmax, single, s2, band);
         if (s2 != o.force_S)
             return MD_EINVAL_OPT;   // forced S must split into equal bands
         S = o.force_S;

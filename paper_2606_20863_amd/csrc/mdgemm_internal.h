@@ -27,7 +27,8 @@ constexpr int kRowBlock = 16;   // rows per fragment
 constexpr int kKcI8 = 64;       // depth per INT8 fragment
 constexpr int kKcF64 = 16;      // depth per FP64 fragment
 constexpr int kTile = 32;       // rows and columns per workgroup (2 x 2 waves)
-constexpr int kGmaxI8 = 16;     // widest band of diagonals, INT8 form
+constexpr int kTriMaxI8 = 32;   // INT8: up to this many diagonals in one band (whole triangle)
+constexpr int kGmaxI8 = 16;     // INT8: widest band when S needs several bands
 constexpr int kGmaxF64 = 16;    // widest band of diagonals, FP64 form
 
 // element (r, k), word w of an operand: p[w * ps + r * sr + k * sk]

@@ -109,6 +109,30 @@ __device__ __forceinline__ void band_chunk(typename Form::acc (&acc)[G],
     }
 }
 
+// Buffer-resource loads of INT8 fragments: one descriptor per wave spans the
+// wave's row block of fragments; the lane's 16 bytes sit at lane * 16 and the
+// fragment at a scalar byte offset, so no per-load address registers are
+// needed.  Offsets past the descriptor's range read zeros.
+struct FragStream {
+    __amdgpu_buffer_rsrc_t rsrc;
+    int voff;
+    __device__ __forceinline__ v4i operator()(uint32_t soff) const
+    {
+        return __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff, (int)soff, 0);
+    }
+};
+
+__device__ __forceinline__ FragStream frag_stream(const void* base, uint64_t bytes, int lane)
+{
+    FragStream f;
+    // word 3 of a raw (untyped) buffer descriptor on gfx9-class targets
+    f.rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0,
+                                               (int)(bytes > 0xffffffffull ? 0xffffffffu : bytes),
+                                               0x00020000);
+    f.voff = lane * 16;
+    return f;
+}
+
 // Software-pipelined run of depth chunks [c0, c1) for one band (t0 a
 // multiple of G, P < G).  A step s of a chunk uses A_s and, for 1 <= s <= t0,
 // the entering fragment B_{t0-s}; both are loaded P steps ahead into a small
@@ -163,8 +187,7 @@ __device__ __forceinline__ void band_run(typename Form::acc (&acc)[G],
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
-        // step s = t0: B_0 enters; slot 0 of the next window is free after it
-        Frag nwin[G];
+        // step s = t0: B_0 enters
         {
             const Frag a = pa[0];
             const Frag b = pb[0];
@@ -183,6 +206,7 @@ __device__ __forceinline__ void band_run(typename Form::acc (&acc)[G],
             __builtin_amdgcn_sched_barrier(0);
         }
         // tail steps s = t0 + p, p = 1 .. G-1: diagonals g >= p
+        Frag nwin[G];
 #pragma unroll
         for (int p = 1; p < G; ++p) {
             const Frag a = pa[0];
@@ -213,6 +237,52 @@ __device__ __forceinline__ void band_run(typename Form::acc (&acc)[G],
             win[g] = nwin[g];
         Ak = An;
         Bk = Bn;
+    }
+}
+
+// Whole triangle of one depth-chunk run [c0, c1): all S diagonals at once
+// (INT8, S <= 32).  The window holds B_0 .. B_{S-1} of the chunk; step p
+// multiplies A_p with B_{g-p} into diagonal g for g >= p.  A is streamed P
+// steps ahead; the next chunk's B_{S-p} is loaded at step p into the slot
+// read for the last time at step p-1.  Fragment (kc, s) of a stream is at
+// byte (kc S + s) 1024.
+template <int S, int P>
+__device__ __forceinline__ void tri_run_i8(v4i (&acc)[S], const FragStream& LA,
+                                           const FragStream& LB, int64_t c0, int64_t c1)
+{
+    static_assert(P >= 1 && P <= S, "prefetch distance");
+    constexpr uint32_t F = 1024, CS = (uint32_t)S * F;
+    uint32_t ck = (uint32_t)c0 * CS;
+    v4i win[S], pa[P];
+#pragma unroll
+    for (int g = S - 1; g >= 0; --g)
+        win[g] = LB(ck + g * F);
+#pragma unroll
+    for (int q = 0; q < P; ++q)
+        pa[q] = LA(ck + q * F);
+    for (int64_t kc = c0; kc < c1; ++kc) {
+        const uint32_t cn = kc + 1 < c1 ? ck + CS : ck;
+        v4i nwin[S];
+#pragma unroll
+        for (int p = 0; p < S; ++p) {
+            const v4i a = pa[0];
+#pragma unroll
+            for (int q = 0; q + 1 < P; ++q)
+                pa[q] = pa[q + 1];
+            pa[P - 1] = (p + P < S) ? LA(ck + (p + P) * F) : LA(cn + (p + P - S) * F);
+            if (p >= 1)
+                nwin[S - p] = LB(cn + (S - p) * F);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int g = S - 1; g >= p; --g)
+                acc[g] = FormI8::mma(a, win[g - p], acc[g]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        nwin[0] = LB(cn);
+#pragma unroll
+        for (int g = 0; g < S; ++g)
+            win[g] = nwin[g];
+        ck = cn;
     }
 }
 
@@ -332,24 +402,75 @@ __device__ void renormalise(int64_t* c, int ncol, int scale, int m, double* out,
     }
 }
 
-template <class Form, int G>
+// Wave geometry shared by the contraction kernels: 4 waves, a 2 x 2 grid of
+// 16 x 16 output tiles per workgroup.
+struct WaveTile {
+    int lane, wave;
+    int64_t rb, cb;     // row block of op(A), column block of op(B)
+    int64_t* cols;      // this lane's fold columns: cols[q * 256 + o * 64]
+
+    __device__ __forceinline__ WaveTile(const GemmArgs& a, int64_t* lds)
+    {
+        lane = threadIdx.x & 63;
+        wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
+        rb = (int64_t)blockIdx.y * 2 + (wave >> 1);
+        cb = (int64_t)blockIdx.x * 2 + (wave & 1);
+        cols = lds + (int64_t)wave * a.ncol * 256 + lane;
+        for (int q = 0; q < a.ncol; ++q)
+#pragma unroll
+            for (int o = 0; o < 4; ++o)
+                cols[q * 256 + o * 64] = 0;
+    }
+};
+
+// Exact fold of one depth chunk's diagonal sums t0 .. t0+G-1.  DBG kernels
+// also add them into the debug buffer (a separate instantiation, so that the
+// production kernels carry no debug addressing).
+template <class Form, int G, bool DBG>
+__device__ __forceinline__ void fold_chunk(const typename Form::acc (&acc)[G], int t0,
+                                           const GemmArgs& a, const WaveTile& w)
+{
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int t = t0 + g;
+        const int p = a.beta * (a.S - 1 - t);
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            const int64_t v = Form::value(acc[g], o);
+            fold_add(w.cols, o, v, p);
+            if constexpr (DBG) {
+                const int64_t i = w.rb * 16 + Form::row(w.lane, o), j = w.cb * 16 + (w.lane & 15);
+                if (i < a.M && j < a.N)
+                    a.dbgD[((int64_t)t * a.M + i) * a.N + j] += v;
+            }
+        }
+    }
+}
+
+template <class Form>
+__device__ __forceinline__ void write_outputs(const GemmArgs& a, const WaveTile& w)
+{
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+        const int64_t i = w.rb * 16 + Form::row(w.lane, o), j = w.cb * 16 + (w.lane & 15);
+        const bool ok = i < a.M && j < a.N;
+        const int scale = ok ? a.E[i] + a.F[j] - a.beta * (a.S + 1) : 0;
+        renormalise(w.cols + o * 64, a.ncol, scale, a.m, ok ? a.C + i * a.ldc + j : nullptr, a.psc,
+                    ok);
+    }
+}
+
+// Banded contraction: S = nbands * G diagonals, G at a time.
+template <class Form, int G, bool DBG>
 __global__ __launch_bounds__(256, 1) void k_slice_gemm(GemmArgs a)
 {
     typedef typename Form::frag Frag;
     typedef typename Form::acc Acc;
     extern __shared__ int64_t lds[];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t rb = (int64_t)blockIdx.y * 2 + (wave >> 1);
-    const int64_t cb = (int64_t)blockIdx.x * 2 + (wave & 1);
-    int64_t* cols = lds + (int64_t)wave * a.ncol * 256 + lane;
-    for (int q = 0; q < a.ncol; ++q)
-#pragma unroll
-        for (int o = 0; o < 4; ++o)
-            cols[q * 256 + o * 64] = 0;
-
+    const WaveTile w(a, lds);
     const int64_t fstride = (int64_t)a.S * 64;   // fragments of one depth chunk
-    const Frag* Ab = (const Frag*)a.A + rb * a.nkc * fstride + lane;
-    const Frag* Bb = (const Frag*)a.B + cb * a.nkc * fstride + lane;
+    const Frag* Ab = (const Frag*)a.A + w.rb * a.nkc * fstride + w.lane;
+    const Frag* Bb = (const Frag*)a.B + w.cb * a.nkc * fstride + w.lane;
 
     for (int b = 0; b < a.nbands; ++b) {
         const int t0 = b * G;
@@ -365,43 +486,42 @@ __global__ __launch_bounds__(256, 1) void k_slice_gemm(GemmArgs a)
                 for (int64_t kc = c0; kc < c1; ++kc)
                     band_chunk<Form, G>(acc, Ab + kc * fstride, Bb + kc * fstride, t0);
             }
-            // exact fold of this chunk's diagonal sums
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-                const int t = t0 + g;
-                const int p = a.beta * (a.S - 1 - t);
-#pragma unroll
-                for (int o = 0; o < 4; ++o) {
-                    const int64_t v = Form::value(acc[g], o);
-                    fold_add(cols, o, v, p);
-                    if (a.dbgD) {
-                        const int64_t i = rb * 16 + Form::row(lane, o), j = cb * 16 + (lane & 15);
-                        if (i < a.M && j < a.N)
-                            a.dbgD[((int64_t)t * a.M + i) * a.N + j] += v;
-                    }
-                }
-            }
+            fold_chunk<Form, G, DBG>(acc, t0, a, w);
         }
     }
-#pragma unroll
-    for (int o = 0; o < 4; ++o) {
-        const int64_t i = rb * 16 + Form::row(lane, o), j = cb * 16 + (lane & 15);
-        const bool ok = i < a.M && j < a.N;
-        const int scale = ok ? a.E[i] + a.F[j] - a.beta * (a.S + 1) : 0;
-        renormalise(cols + o * 64, a.ncol, scale, a.m, ok ? a.C + i * a.ldc + j : nullptr, a.psc, ok);
-    }
+    write_outputs<Form>(a, w);
 }
 
-template <class Form, int G>
-hipError_t launch_one(const GemmArgs& a, hipStream_t st)
+// Whole-triangle INT8 contraction, S <= 32 diagonals in one band.
+template <int S, bool DBG>
+__global__ __launch_bounds__(256, 1) void k_tri_i8(GemmArgs a)
+{
+    extern __shared__ int64_t lds[];
+    const WaveTile w(a, lds);
+    const uint64_t bytes = (uint64_t)a.nkc * S * 1024;   // one row block of fragments
+    const FragStream LA = frag_stream((const char*)a.A + w.rb * bytes, bytes, w.lane);
+    const FragStream LB = frag_stream((const char*)a.B + w.cb * bytes, bytes, w.lane);
+    for (int64_t c0 = 0; c0 < a.nkc; c0 += a.kcc) {
+        v4i acc[S];
+#pragma unroll
+        for (int g = 0; g < S; ++g)
+            acc[g] = FormI8::zero();
+        tri_run_i8<S, (S < 3 ? S : 3)>(acc, LA, LB, c0, min(c0 + a.kcc, a.nkc));
+        fold_chunk<FormI8, S, DBG>(acc, 0, a, w);
+    }
+    write_outputs<FormI8>(a, w);
+}
+
+template <class Kernel>
+hipError_t launch_kernel(Kernel k, const GemmArgs& a, hipStream_t st)
 {
     const size_t lds = (size_t)4 * a.ncol * 256 * sizeof(int64_t);
-    hipError_t e = hipFuncSetAttribute((const void*)k_slice_gemm<Form, G>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
     if (e != hipSuccess)
         return e;
     dim3 grid((unsigned)((a.N + kTile - 1) / kTile), (unsigned)((a.M + kTile - 1) / kTile));
-    hipLaunchKernelGGL((k_slice_gemm<Form, G>), grid, dim3(256), lds, st, a);
+    hipLaunchKernelGGL(k, grid, dim3(256), lds, st, a);
     return hipGetLastError();
 }
 
@@ -410,12 +530,28 @@ struct Dispatch {
     static hipError_t run(const GemmArgs& a, hipStream_t st)
     {
         if (a.band == G)
-            return launch_one<Form, G>(a, st);
+            return a.dbgD ? launch_kernel(k_slice_gemm<Form, G, true>, a, st)
+                          : launch_kernel(k_slice_gemm<Form, G, false>, a, st);
         return Dispatch<Form, G - 1>::run(a, st);
     }
 };
 template <class Form>
 struct Dispatch<Form, 0> {
+    static hipError_t run(const GemmArgs&, hipStream_t) { return hipErrorInvalidValue; }
+};
+
+template <int S>
+struct DispatchTri {
+    static hipError_t run(const GemmArgs& a, hipStream_t st)
+    {
+        if (a.S == S)
+            return a.dbgD ? launch_kernel(k_tri_i8<S, true>, a, st)
+                          : launch_kernel(k_tri_i8<S, false>, a, st);
+        return DispatchTri<S - 1>::run(a, st);
+    }
+};
+template <>
+struct DispatchTri<0> {
     static hipError_t run(const GemmArgs&, hipStream_t) { return hipErrorInvalidValue; }
 };
 
@@ -501,6 +637,8 @@ hipError_t launch_mag_min(const void* qA, const void* qB, int64_t M, int64_t N, 
 
 hipError_t launch_gemm_i8(const GemmArgs& a, hipStream_t st)
 {
+    if (a.nbands == 1 && a.S <= kTriMaxI8)
+        return DispatchTri<kTriMaxI8>::run(a, st);
     return Dispatch<FormI8, kGmaxI8>::run(a, st);
 }
 
