@@ -242,46 +242,74 @@ __device__ __forceinline__ void band_run(typename Form::acc (&acc)[G],
 
 // Whole triangle of one depth-chunk run [c0, c1): all S diagonals at once
 // (INT8, S <= 32).  The window holds B_0 .. B_{S-1} of the chunk; step p
-// multiplies A_p with B_{g-p} into diagonal g for g >= p.  A is streamed P
-// steps ahead; the next chunk's B_{S-p} is loaded at step p into the slot
-// read for the last time at step p-1.  Fragment (kc, s) of a stream is at
-// byte (kc S + s) 1024.
-template <int S, int P>
+// multiplies A_p with B_{g-p} into diagonal g for g >= p, so B_{S-p} is read
+// for the last time at step p-1 and its slot takes the next chunk's B_{S-p}
+// at step p (B_0 after the last step).  Step p carries S - p matrix
+// instructions, so A loads are scheduled by work, not by steps: A_q is
+// issued at the latest step that leaves at least kLead instructions before
+// its use (tri_issue_step); the next chunk's first A fragments are issued
+// inside this chunk.  Fragment (kc, s) of a stream is at byte (kc S + s) 1024.
+constexpr int kLead = 48;
+
+// Step (0 .. S-1 of this chunk) at which A of position q is issued, where
+// q = 0 .. S-1 are this chunk's steps and q = S .. S+1 the next chunk's
+// steps 0 and 1; -1: issued before the chunk starts (prologue or the end of
+// the previous chunk; only for q < S).  Work between issue at step l and use at position q is the sum of
+// the instructions of steps l .. q-1 (steps of the next chunk count S - (q-S)).
+constexpr int tri_work(int S, int p) { return p < S ? S - p : S - (p - S); }
+constexpr int tri_issue_step(int S, int q)
+{
+    int w = 0;
+    for (int l = q - 1; l >= 0; --l) {
+        w += tri_work(S, l);
+        if (w >= kLead)
+            return l < S ? l : S - 1;
+    }
+    return q < S ? -1 : 0;   // the next chunk's A cannot precede this chunk
+}
+
+template <int S>
 __device__ __forceinline__ void tri_run_i8(v4i (&acc)[S], const FragStream& LA,
                                            const FragStream& LB, int64_t c0, int64_t c1)
 {
-    static_assert(P >= 1 && P <= S, "prefetch distance");
     constexpr uint32_t F = 1024, CS = (uint32_t)S * F;
     uint32_t ck = (uint32_t)c0 * CS;
-    v4i win[S], pa[P];
+    v4i win[S], ar[S + 2];
 #pragma unroll
     for (int g = S - 1; g >= 0; --g)
         win[g] = LB(ck + g * F);
+    // A of this first chunk issued "before" it: positions with no issue step
 #pragma unroll
-    for (int q = 0; q < P; ++q)
-        pa[q] = LA(ck + q * F);
+    for (int q = 0; q < S; ++q)
+        if (tri_issue_step(S, q) < 0)
+            ar[q] = LA(ck + q * F);
     for (int64_t kc = c0; kc < c1; ++kc) {
         const uint32_t cn = kc + 1 < c1 ? ck + CS : ck;
-        v4i nwin[S];
 #pragma unroll
         for (int p = 0; p < S; ++p) {
-            const v4i a = pa[0];
+            // issue the A loads scheduled at this step
 #pragma unroll
-            for (int q = 0; q + 1 < P; ++q)
-                pa[q] = pa[q + 1];
-            pa[P - 1] = (p + P < S) ? LA(ck + (p + P) * F) : LA(cn + (p + P - S) * F);
+            for (int q = p + 1; q < S + 2; ++q)
+                if (tri_issue_step(S, q) == p)
+                    ar[q] = q < S ? LA(ck + q * F) : LA(cn + (q - S) * F);
             if (p >= 1)
-                nwin[S - p] = LB(cn + (S - p) * F);
+                win[S - p] = LB(cn + (S - p) * F);
             __builtin_amdgcn_sched_barrier(0);
+            const v4i a = ar[p];
 #pragma unroll
             for (int g = S - 1; g >= p; --g)
                 acc[g] = FormI8::mma(a, win[g - p], acc[g]);
             __builtin_amdgcn_sched_barrier(0);
         }
-        nwin[0] = LB(cn);
+        win[0] = LB(cn);
+        // the next chunk's steps 0 and 1 were issued here; steps >= 2 whose
+        // issue step is "before the chunk" cannot exist for S >= 3
+        ar[0] = ar[S];
+        ar[1] = ar[S + 1];
 #pragma unroll
-        for (int g = 0; g < S; ++g)
-            win[g] = nwin[g];
+        for (int q = 2; q < S; ++q)
+            if (tri_issue_step(S, q) < 0)
+                ar[q] = LA(cn + q * F);
         ck = cn;
     }
 }
@@ -402,6 +430,29 @@ __device__ void renormalise(int64_t* c, int ncol, int scale, int m, double* out,
     }
 }
 
+// Workgroup -> 32 x 32 output tile.  Workgroups are dispatched round-robin
+// over the 8 XCDs (each with its own L2), so linear id L runs on XCD L % 8.
+// The mapping gives XCD x the contiguous range x T/8 .. (x+1) T/8 - 1 of a
+// grouped order in which runs of kGroupRows tile rows advance column by
+// column: the workgroups resident on one XCD at a time then cover a compact
+// block of tiles and share their A row panels and B column panels in L2.
+constexpr int kXcds = 8, kGroupRows = 4;
+
+__device__ __forceinline__ void tile_of_workgroup(int64_t gx, int64_t gy, int64_t& ty, int64_t& tx)
+{
+    const int64_t T = gx * gy;
+    int64_t L = blockIdx.x;
+    if (T % kXcds == 0)
+        L = (L % kXcds) * (T / kXcds) + L / kXcds;
+    const int64_t per_group = (int64_t)kGroupRows * gx;
+    const int64_t group = L / per_group;
+    const int64_t first = group * kGroupRows;
+    const int64_t rows = min((int64_t)kGroupRows, gy - first);
+    const int64_t r = L % per_group;
+    ty = first + r % rows;
+    tx = r / rows;
+}
+
 // Wave geometry shared by the contraction kernels: 4 waves, a 2 x 2 grid of
 // 16 x 16 output tiles per workgroup.
 struct WaveTile {
@@ -413,8 +464,10 @@ struct WaveTile {
     {
         lane = threadIdx.x & 63;
         wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
-        rb = (int64_t)blockIdx.y * 2 + (wave >> 1);
-        cb = (int64_t)blockIdx.x * 2 + (wave & 1);
+        int64_t ty, tx;
+        tile_of_workgroup((a.N + kTile - 1) / kTile, (a.M + kTile - 1) / kTile, ty, tx);
+        rb = ty * 2 + (wave >> 1);
+        cb = tx * 2 + (wave & 1);
         cols = lds + (int64_t)wave * a.ncol * 256 + lane;
         for (int q = 0; q < a.ncol; ++q)
 #pragma unroll
@@ -506,7 +559,7 @@ __global__ __launch_bounds__(256, 1) void k_tri_i8(GemmArgs a)
 #pragma unroll
         for (int g = 0; g < S; ++g)
             acc[g] = FormI8::zero();
-        tri_run_i8<S, (S < 3 ? S : 3)>(acc, LA, LB, c0, min(c0 + a.kcc, a.nkc));
+        tri_run_i8<S>(acc, LA, LB, c0, min(c0 + a.kcc, a.nkc));
         fold_chunk<FormI8, S, DBG>(acc, 0, a, w);
     }
     write_outputs<FormI8>(a, w);
@@ -520,8 +573,8 @@ hipError_t launch_kernel(Kernel k, const GemmArgs& a, hipStream_t st)
                                        (int)lds);
     if (e != hipSuccess)
         return e;
-    dim3 grid((unsigned)((a.N + kTile - 1) / kTile), (unsigned)((a.M + kTile - 1) / kTile));
-    hipLaunchKernelGGL(k, grid, dim3(256), lds, st, a);
+    const int64_t tiles = ((a.N + kTile - 1) / kTile) * ((a.M + kTile - 1) / kTile);
+    hipLaunchKernelGGL(k, dim3((unsigned)tiles), dim3(256), lds, st, a);
     return hipGetLastError();
 }
 
