@@ -32,6 +32,33 @@ PEAK_INT8_TOPS = 5000.0      # MI355X dense INT8 matrix peak, TOP/s
 PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 matrix peak, TFLOP/s
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of the INT8 slice contraction from the committed
+    counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by its reading
+    for a plain 1 GiB copy); None when the summary is missing, covers another
+    kernel, or the kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_tri_i8_qd4096_traffic.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("|", " ", "#")):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    csrc = os.path.join(ROOT, "paper_2606_20863_amd", "csrc")
+    blob = b"".join(open(os.path.join(csrc, f), "rb").read()
+                    for f in ("slice_gemm.hip", "mdgemm_internal.h"))
+    fp = hashlib.sha256(blob).hexdigest()[:16]
+    want = vals.get("Kernel source fingerprint", "").split("=")[-1].strip()
+    if fp != want or kernel != vals.get("kernel"):
+        return None
+    copy = float(vals["copy_bytes"])
+    fetch = float(vals["fetch_kib"]) * 1024 * copy / (float(vals["copy_fetch_kib"]) * 1024)
+    write = float(vals["write_kib"]) * 1024 * copy / (float(vals["copy_write_kib"]) * 1024)
+    return fetch + write
+
+
 def hip_events(n):
     hip = ctypes.CDLL("libamdhip64.so.7")
     hip.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
@@ -160,6 +187,11 @@ def main():
     ach8 = ops8 / (kern8 * 1e-3) / 1e12
     ach64 = ops64 / (kern64 * 1e-3) / 1e12
 
+    kname8 = (f"k_tri_i8<{S8}, false>" if info8["band"] == S8
+              else f"k_slice_gemm<FormI8, {info8['band']}, false>")
+    traffic8 = measured_traffic(kname8)
+    traffic8 = None if traffic8 is None else int(traffic8)
+
     C8h = C8.cpu().numpy()
     C64h = C64.cpu().numpy()
     err8 = accuracy_sample(Ah, Bh, C8h)
@@ -194,10 +226,11 @@ def main():
                       "max_log2_err_sampled": round(err64, 2),
                       "certified_log2_bound": round(info64["log2_bound"], 2)},
         "int8_over_fp64": round(eff8 / eff64, 3),
-        "roofline": {"bound": "mfma", "kernel": f"k_tri_i8<{S8}> (INT8 slice contraction)" if info8["band"] == S8 else "k_slice_gemm<FormI8> (INT8 slice contraction)",
+        "roofline": {"bound": "mfma", "kernel": kname8,
                      "achieved": round(ach8, 3), "peak": PEAK_INT8_TOPS, "unit": "TFLOP/s",
-                     "frac": round(ach8 / PEAK_INT8_TOPS, 4), "traffic": None,
-                     "work_per_launch": f"2*M*N*K*S(S+1)/2 = {ops8:.4e} int8 ops"},
+                     "frac": round(ach8 / PEAK_INT8_TOPS, 4), "traffic": traffic8,
+                     "work_per_launch": f"2*M*N*K*S(S+1)/2 = {ops8:.4e} int8 ops (unit: int8 TOP/s)",
+                     "algorithmic_bytes_per_launch": int(2 * S8 * M * K + 8 * m * M * N)},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(Ah, Bh, K)
