@@ -46,9 +46,9 @@ def measured_traffic(kernel: str):
         if ":" in line and not line.startswith(("|", " ", "#")):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    csrc = os.path.join(ROOT, "paper_2606_20863_amd", "csrc")
-    blob = b"".join(open(os.path.join(csrc, f), "rb").read()
-                    for f in ("slice_gemm.hip", "mdgemm_internal.h"))
+    pkg = os.path.join(ROOT, "paper_2606_20863_amd")
+    blob = b"".join(open(os.path.join(pkg, f), "rb").read()
+                    for f in ("csrc/slice_gemm.hip", "csrc/mdgemm_internal.h", "build.py"))
     fp = hashlib.sha256(blob).hexdigest()[:16]
     want = vals.get("Kernel source fingerprint", "").split("=")[-1].strip()
     if fp != want or kernel != vals.get("kernel"):

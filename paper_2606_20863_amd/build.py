@@ -23,6 +23,9 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",
     # no packed FP32 instructions in any HIP code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core accumulators in VGPRs, operand fragments free to use AGPRs:
+    # keeps the contraction loops free of accumulator copies
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
 ]
 
 
