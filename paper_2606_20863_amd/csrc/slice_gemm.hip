@@ -22,8 +22,10 @@
 // stays below 2^31 (INT8) or 2^53 (FP64).  After each chunk the accumulators
 // are added into the exact fold.
 //
-// The fold lives in LDS: per wave, per output, ncol signed 64-bit columns
-// with weights 2^(32 q) (carry-save; normalised once at the end).
+// The banded kernels keep the fold in LDS: per wave, per output, ncol signed
+// 64-bit columns with weights 2^(32 q) (carry-save; normalised once at the
+// end).  The whole-triangle INT8 kernel, whose bit positions are all known at
+// compile time, keeps it in registers and renormalises there.
 #include "mdgemm_internal.h"
 
 namespace mdg {
@@ -460,7 +462,7 @@ struct WaveTile {
     int64_t rb, cb;     // row block of op(A), column block of op(B)
     int64_t* cols;      // this lane's fold columns: cols[q * 256 + o * 64]
 
-    __device__ __forceinline__ WaveTile(const GemmArgs& a, int64_t* lds)
+    __device__ __forceinline__ WaveTile(const GemmArgs& a)
     {
         lane = threadIdx.x & 63;
         wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
@@ -468,6 +470,12 @@ struct WaveTile {
         tile_of_workgroup((a.N + kTile - 1) / kTile, (a.M + kTile - 1) / kTile, ty, tx);
         rb = ty * 2 + (wave >> 1);
         cb = tx * 2 + (wave & 1);
+        cols = nullptr;
+    }
+
+    // zeroed LDS fold columns (the banded kernels)
+    __device__ __forceinline__ void init_cols(const GemmArgs& a, int64_t* lds)
+    {
         cols = lds + (int64_t)wave * a.ncol * 256 + lane;
         for (int q = 0; q < a.ncol; ++q)
 #pragma unroll
@@ -520,7 +528,8 @@ __global__ __launch_bounds__(256, 1) void k_slice_gemm(GemmArgs a)
     typedef typename Form::frag Frag;
     typedef typename Form::acc Acc;
     extern __shared__ int64_t lds[];
-    const WaveTile w(a, lds);
+    WaveTile w(a);
+    w.init_cols(a, lds);
     const int64_t fstride = (int64_t)a.S * 64;   // fragments of one depth chunk
     const Frag* Ab = (const Frag*)a.A + w.rb * a.nkc * fstride + w.lane;
     const Frag* Bb = (const Frag*)a.B + w.cb * a.nkc * fstride + w.lane;
@@ -545,34 +554,196 @@ __global__ __launch_bounds__(256, 1) void k_slice_gemm(GemmArgs a)
     write_outputs<Form>(a, w);
 }
 
+// Register-resident fold of the whole-triangle kernel.  There beta = 7 and
+// the band starts at t = 0, so diagonal t lands at bit 7 e, e = S-1-t, which
+// is column e / 4 (weight 2^(28 (e / 4))) shifted left by the static amount
+// 7 (e mod 4).  One depth chunk adds less than 2^31 (1 + 2^7 + 2^14 + 2^21)
+// < 2^53 to a column; after every chunk the columns are carried back to 28
+// bits.  The top column takes only carries and is the signed one.
+template <int S>
+struct Tri {
+    static constexpr int kCols = (S + 3) / 4 + 1;
+    // 32-bit limbs of the magnitude: kCols-1 columns of 28 bits, a top one
+    // below 2^64
+    static constexpr int kLimbs = (28 * (kCols - 1) + 64 + 31) / 32;
+};
+
+template <int NC>
+__device__ __forceinline__ void carry28(int64_t (&x)[NC])
+{
+#pragma unroll
+    for (int j = 0; j + 1 < NC; ++j) {
+        x[j + 1] += x[j] >> 28;
+        x[j] &= 0xfffffffLL;
+    }
+}
+
+template <int S, bool DBG>
+__device__ __forceinline__ void tri_fold(const v4i (&acc)[S], int64_t (&x)[4][Tri<S>::kCols],
+                                         const GemmArgs& a, const WaveTile& w)
+{
+#pragma unroll
+    for (int g = 0; g < S; ++g) {
+        const int e = S - 1 - g;
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            x[o][e >> 2] += (int64_t)acc[g][o] * ((int64_t)1 << (7 * (e & 3)));
+            if constexpr (DBG) {
+                const int64_t i = w.rb * 16 + FormI8::row(w.lane, o), j = w.cb * 16 + (w.lane & 15);
+                if (i < a.M && j < a.N)
+                    a.dbgD[((int64_t)g * a.M + i) * a.N + j] += acc[g][o];
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 0; o < 4; ++o)
+        carry28(x[o]);
+}
+
+// Limb k of the integer whose limb 0 is zero and limbs 1..NL are L[0..NL-1]
+// (bits of X shifted up by 32, so that bit unit-1 >= -1 of X has a place).
+template <int NL>
+__device__ __forceinline__ uint32_t shifted_limb(const uint32_t (&L)[NL], int k)
+{
+    return (k >= 1 && k <= NL) ? L[k - 1] : 0u;
+}
+
+// One greedy round-to-nearest step on (-1)^neg X 2^scale, X >= 0 held in
+// 32-bit limbs L: returns the word RN(X 2^scale) (with sign) and leaves the
+// remainder in L and its sign in sgn.  The same steps as the LDS version,
+// with every limb index static (data-dependent positions become selects)
+// and no branches, so that the steps of several outputs interleave.
+template <int NL>
+__device__ __forceinline__ double rn_step(uint32_t (&L)[NL], double& sgn, int umin, int scale)
+{
+    int top = -1;
+#pragma unroll
+    for (int k = 0; k < NL; ++k)
+        top = L[k] ? 32 * k + 31 - __clz((int)L[k]) : top;
+    const int unit = max(max(top - 52, umin), 0);
+    // 64 bits of X from bit unit-1: the round bit, then the 53-bit
+    // significand; sticky: any bit below unit-1
+    const int P = unit + 31, q = P >> 5, r = P & 31;
+    uint32_t l0 = 0, l1 = 0, l2 = 0, st = 0;
+#pragma unroll
+    for (int k = 0; k <= NL; ++k) {
+        const uint32_t v = shifted_limb(L, k);
+        st |= k < q ? v : (k == q ? v & ((1u << r) - 1u) : 0u);
+        l0 = k == q ? v : l0;
+        l1 = k == q ? shifted_limb(L, k + 1) : l1;
+        l2 = k == q ? shifted_limb(L, k + 2) : l2;
+    }
+    const uint64_t lo = (uint64_t)l0 | ((uint64_t)l1 << 32);
+    const uint64_t win = r ? ((lo >> r) | ((uint64_t)l2 << (64 - r))) : lo;
+    uint64_t n = win >> 1;
+    const bool up = (win & 1) && (st || (n & 1));
+    n += up;
+    const double w = top >= 0 ? sgn * ldexp((double)n, unit + scale) : 0.0;
+    // remainder: the bits below unit; rounded up, 2^unit minus them with the
+    // sign flipped
+    uint64_t cy = 1;
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int b = unit - 32 * k;
+        const uint32_t keep = b >= 32 ? ~0u : (b <= 0 ? 0u : (1u << b) - 1u);
+        const uint64_t v = (uint64_t)(~L[k]) + cy;
+        cy = v >> 32;
+        L[k] = (up ? (uint32_t)v : L[k]) & keep;
+    }
+    sgn = up ? -sgn : sgn;
+    return w;
+}
+
+// Magnitude limbs of the carried columns; returns the sign.
+template <int NC, int NL>
+__device__ __forceinline__ bool to_limbs(int64_t (&x)[NC], uint32_t (&L)[NL])
+{
+    const bool neg = x[NC - 1] < 0;
+#pragma unroll
+    for (int j = 0; j < NC; ++j)
+        x[j] = neg ? -x[j] : x[j];
+    carry28(x);
+#pragma unroll
+    for (int k = 0; k < NL; ++k)
+        L[k] = 0;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+        const uint64_t v = (uint64_t)x[j];
+        const int b = 28 * j, k = b >> 5, r = b & 31;
+        L[k] |= (uint32_t)(v << r);
+        if (k + 1 < NL)
+            L[k + 1] |= (uint32_t)(r ? v >> (32 - r) : v >> 32);
+        if (k + 2 < NL && r)
+            L[k + 2] |= (uint32_t)(v >> (64 - r));
+    }
+    return neg;
+}
+
+// Greedy renormalisation of the lane's four outputs, their steps interleaved.
+template <int S>
+__device__ __forceinline__ void tri_outputs(int64_t (&x)[4][Tri<S>::kCols], const GemmArgs& a,
+                                            const WaveTile& w)
+{
+    constexpr int NL = Tri<S>::kLimbs;
+    uint32_t L[4][NL];
+    double sgn[4], *out[4];
+    int scale[4], umin[4];
+    bool ok[4];
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+        const int64_t i = w.rb * 16 + FormI8::row(w.lane, o), j = w.cb * 16 + (w.lane & 15);
+        ok[o] = i < a.M && j < a.N;
+        scale[o] = ok[o] ? a.E[i] + a.F[j] - 7 * (S + 1) : 0;
+        umin[o] = -1074 - scale[o];
+        out[o] = a.C + (ok[o] ? i * a.ldc + j : 0);
+        sgn[o] = to_limbs(x[o], L[o]) ? -1.0 : 1.0;
+    }
+    for (int t = 0; t < a.m; ++t) {
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            const double wv = rn_step(L[o], sgn[o], umin[o], scale[o]);
+            if (ok[o])
+                out[o][t * a.psc] = wv;
+        }
+    }
+}
+
 // Whole-triangle INT8 contraction, S <= 32 diagonals in one band.
 template <int S, bool DBG>
 __global__ __launch_bounds__(256, 1) void k_tri_i8(GemmArgs a)
 {
-    extern __shared__ int64_t lds[];
-    const WaveTile w(a, lds);
+    const WaveTile w(a);
     const uint64_t bytes = (uint64_t)a.nkc * S * 1024;   // one row block of fragments
     const FragStream LA = frag_stream((const char*)a.A + w.rb * bytes, bytes, w.lane);
     const FragStream LB = frag_stream((const char*)a.B + w.cb * bytes, bytes, w.lane);
+    int64_t x[4][Tri<S>::kCols];
+#pragma unroll
+    for (int o = 0; o < 4; ++o)
+#pragma unroll
+        for (int j = 0; j < Tri<S>::kCols; ++j)
+            x[o][j] = 0;
     for (int64_t c0 = 0; c0 < a.nkc; c0 += a.kcc) {
         v4i acc[S];
 #pragma unroll
         for (int g = 0; g < S; ++g)
             acc[g] = FormI8::zero();
         tri_run_i8<S>(acc, LA, LB, c0, min(c0 + a.kcc, a.nkc));
-        fold_chunk<FormI8, S, DBG>(acc, 0, a, w);
+        tri_fold<S, DBG>(acc, x, a, w);
     }
-    write_outputs<FormI8>(a, w);
+    tri_outputs<S>(x, a, w);
 }
 
+// lds_fold: the kernel keeps its fold columns in LDS (4 waves x ncol x 256)
 template <class Kernel>
-hipError_t launch_kernel(Kernel k, const GemmArgs& a, hipStream_t st)
+hipError_t launch_kernel(Kernel k, const GemmArgs& a, hipStream_t st, bool lds_fold = true)
 {
-    const size_t lds = (size_t)4 * a.ncol * 256 * sizeof(int64_t);
-    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
-    if (e != hipSuccess)
-        return e;
+    const size_t lds = lds_fold ? (size_t)4 * a.ncol * 256 * sizeof(int64_t) : 0;
+    if (lds) {
+        const hipError_t e = hipFuncSetAttribute(
+            (const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess)
+            return e;
+    }
     const int64_t tiles = ((a.N + kTile - 1) / kTile) * ((a.M + kTile - 1) / kTile);
     hipLaunchKernelGGL(k, dim3((unsigned)tiles), dim3(256), lds, st, a);
     return hipGetLastError();
@@ -598,8 +769,8 @@ struct DispatchTri {
     static hipError_t run(const GemmArgs& a, hipStream_t st)
     {
         if (a.S == S)
-            return a.dbgD ? launch_kernel(k_tri_i8<S, true>, a, st)
-                          : launch_kernel(k_tri_i8<S, false>, a, st);
+            return a.dbgD ? launch_kernel(k_tri_i8<S, true>, a, st, false)
+                          : launch_kernel(k_tri_i8<S, false>, a, st, false);
         return DispatchTri<S - 1>::run(a, st);
     }
 };
@@ -690,7 +861,9 @@ hipError_t launch_mag_min(const void* qA, const void* qB, int64_t M, int64_t N, 
 
 hipError_t launch_gemm_i8(const GemmArgs& a, hipStream_t st)
 {
-    if (a.nbands == 1 && a.S <= kTriMaxI8)
+    // the triangle kernel's register fold holds |X| / 2^(28 ceil(S/4)) < K 2^9
+    // in its signed top column
+    if (a.nbands == 1 && a.S <= kTriMaxI8 && a.nkc * kKcI8 < ((int64_t)1 << 48))
         return DispatchTri<kTriMaxI8>::run(a, st);
     return Dispatch<FormI8, kGmaxI8>::run(a, st);
 }
