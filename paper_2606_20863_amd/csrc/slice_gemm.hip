@@ -243,75 +243,84 @@ __device__ __forceinline__ void band_run(typename Form::acc (&acc)[G],
 }
 
 // Whole triangle of one depth-chunk run [c0, c1): all S diagonals at once
-// (INT8, S <= 32).  The window holds B_0 .. B_{S-1} of the chunk; step p
-// multiplies A_p with B_{g-p} into diagonal g for g >= p, so B_{S-p} is read
-// for the last time at step p-1 and its slot takes the next chunk's B_{S-p}
-// at step p (B_0 after the last step).  Step p carries S - p matrix
-// instructions, so A loads are scheduled by work, not by steps: A_q is
-// issued at the latest step that leaves at least kLead instructions before
-// its use (tri_issue_step); the next chunk's first A fragments are issued
-// inside this chunk.  Fragment (kc, s) of a stream is at byte (kc S + s) 1024.
-constexpr int kLead = 48;
+// (INT8, S <= 32), for R row blocks of op(A) against one column block of
+// op(B).  The window holds B_0 .. B_{S-1} of the chunk; step p multiplies
+// A_p of every row block with B_{g-p} into diagonal g for g >= p (g
+// descending), so B_{S-p} is read for the last time at step p-1 and its slot
+// takes the next chunk's B_{S-p} at step p (B_0 after the last step).
+// Fragment (kc, s) of a stream is at byte (kc S + s) 1024.
+//
+// Step p carries R (S - p) matrix instructions, so A loads are scheduled by
+// work, not by steps: A_q is issued at the latest step that leaves at least
+// LA instructions before its use (tri_issue_a); the next chunk's first A
+// fragments are issued inside this chunk.
+constexpr int tri_work(int S, int R, int p) { return R * (p < S ? S - p : S - (p - S)); }
 
 // Step (0 .. S-1 of this chunk) at which A of position q is issued, where
 // q = 0 .. S-1 are this chunk's steps and q = S .. S+1 the next chunk's
 // steps 0 and 1; -1: issued before the chunk starts (prologue or the end of
-// the previous chunk; only for q < S).  Work between issue at step l and use at position q is the sum of
-// the instructions of steps l .. q-1 (steps of the next chunk count S - (q-S)).
-constexpr int tri_work(int S, int p) { return p < S ? S - p : S - (p - S); }
-constexpr int tri_issue_step(int S, int q)
+// the previous chunk; only for q < S).
+constexpr int tri_issue_a(int S, int R, int LA, int q)
 {
     int w = 0;
     for (int l = q - 1; l >= 0; --l) {
-        w += tri_work(S, l);
-        if (w >= kLead)
+        w += tri_work(S, R, l);
+        if (w >= LA)
             return l < S ? l : S - 1;
     }
     return q < S ? -1 : 0;   // the next chunk's A cannot precede this chunk
 }
 
-template <int S>
-__device__ __forceinline__ void tri_run_i8(v4i (&acc)[S], const FragStream& LA,
-                                           const FragStream& LB, int64_t c0, int64_t c1)
+template <int S, int R, int LA>
+__device__ __forceinline__ void tri_run_i8(v4i (&acc)[R][S], const FragStream (&LDA)[R],
+                                           const FragStream& LDB, int64_t c0, int64_t c1)
 {
     constexpr uint32_t F = 1024, CS = (uint32_t)S * F;
     uint32_t ck = (uint32_t)c0 * CS;
-    v4i win[S], ar[S + 2];
+    v4i win[S], ar[R][S + 2];
 #pragma unroll
     for (int g = S - 1; g >= 0; --g)
-        win[g] = LB(ck + g * F);
+        win[g] = LDB(ck + g * F);
     // A of this first chunk issued "before" it: positions with no issue step
 #pragma unroll
     for (int q = 0; q < S; ++q)
-        if (tri_issue_step(S, q) < 0)
-            ar[q] = LA(ck + q * F);
+        if (tri_issue_a(S, R, LA, q) < 0)
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                ar[r][q] = LDA[r](ck + q * F);
     for (int64_t kc = c0; kc < c1; ++kc) {
         const uint32_t cn = kc + 1 < c1 ? ck + CS : ck;
 #pragma unroll
         for (int p = 0; p < S; ++p) {
-            // issue the A loads scheduled at this step
+            // issue the loads scheduled at this step
 #pragma unroll
             for (int q = p + 1; q < S + 2; ++q)
-                if (tri_issue_step(S, q) == p)
-                    ar[q] = q < S ? LA(ck + q * F) : LA(cn + (q - S) * F);
+                if (tri_issue_a(S, R, LA, q) == p)
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        ar[r][q] = q < S ? LDA[r](ck + q * F) : LDA[r](cn + (q - S) * F);
             if (p >= 1)
-                win[S - p] = LB(cn + (S - p) * F);
+                win[S - p] = LDB(cn + (S - p) * F);
             __builtin_amdgcn_sched_barrier(0);
-            const v4i a = ar[p];
 #pragma unroll
             for (int g = S - 1; g >= p; --g)
-                acc[g] = FormI8::mma(a, win[g - p], acc[g]);
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    acc[r][g] = FormI8::mma(ar[r][p], win[g - p], acc[r][g]);
             __builtin_amdgcn_sched_barrier(0);
         }
-        win[0] = LB(cn);
-        // the next chunk's steps 0 and 1 were issued here; steps >= 2 whose
-        // issue step is "before the chunk" cannot exist for S >= 3
-        ar[0] = ar[S];
-        ar[1] = ar[S + 1];
+        win[0] = LDB(cn);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            ar[r][0] = ar[r][S];
+            ar[r][1] = ar[r][S + 1];
+        }
 #pragma unroll
         for (int q = 2; q < S; ++q)
-            if (tri_issue_step(S, q) < 0)
-                ar[q] = LA(cn + q * F);
+            if (tri_issue_a(S, R, LA, q) < 0)
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    ar[r][q] = LDA[r](cn + q * F);
         ck = cn;
     }
 }
@@ -462,13 +471,14 @@ struct WaveTile {
     int64_t rb, cb;     // row block of op(A), column block of op(B)
     int64_t* cols;      // this lane's fold columns: cols[q * 256 + o * 64]
 
-    __device__ __forceinline__ WaveTile(const GemmArgs& a)
+    // R row blocks per wave (rb .. rb+R-1): a 32 R x 32 workgroup tile
+    __device__ __forceinline__ WaveTile(const GemmArgs& a, int R)
     {
         lane = threadIdx.x & 63;
         wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
         int64_t ty, tx;
-        tile_of_workgroup((a.N + kTile - 1) / kTile, (a.M + kTile - 1) / kTile, ty, tx);
-        rb = ty * 2 + (wave >> 1);
+        tile_of_workgroup((a.N + kTile - 1) / kTile, (a.M + kTile * R - 1) / (kTile * R), ty, tx);
+        rb = (ty * 2 + (wave >> 1)) * R;
         cb = tx * 2 + (wave & 1);
         cols = nullptr;
     }
@@ -528,7 +538,7 @@ __global__ __launch_bounds__(256, 1) void k_slice_gemm(GemmArgs a)
     typedef typename Form::frag Frag;
     typedef typename Form::acc Acc;
     extern __shared__ int64_t lds[];
-    WaveTile w(a);
+    WaveTile w(a, 1);
     w.init_cols(a, lds);
     const int64_t fstride = (int64_t)a.S * 64;   // fragments of one depth chunk
     const Frag* Ab = (const Frag*)a.A + w.rb * a.nkc * fstride + w.lane;
@@ -578,26 +588,29 @@ __device__ __forceinline__ void carry28(int64_t (&x)[NC])
     }
 }
 
-template <int S, bool DBG>
-__device__ __forceinline__ void tri_fold(const v4i (&acc)[S], int64_t (&x)[4][Tri<S>::kCols],
-                                         const GemmArgs& a, const WaveTile& w)
+// x[4 r + o]: output o of the lane in row block rb0 + r
+template <int S, int R, bool DBG>
+__device__ __forceinline__ void tri_fold(const v4i (&acc)[R][S], int64_t (&x)[4 * R][Tri<S>::kCols],
+                                         const GemmArgs& a, int64_t rb0, int64_t cb, int lane)
 {
 #pragma unroll
     for (int g = 0; g < S; ++g) {
         const int e = S - 1 - g;
 #pragma unroll
-        for (int o = 0; o < 4; ++o) {
-            x[o][e >> 2] += (int64_t)acc[g][o] * ((int64_t)1 << (7 * (e & 3)));
-            if constexpr (DBG) {
-                const int64_t i = w.rb * 16 + FormI8::row(w.lane, o), j = w.cb * 16 + (w.lane & 15);
-                if (i < a.M && j < a.N)
-                    a.dbgD[((int64_t)g * a.M + i) * a.N + j] += acc[g][o];
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int o = 0; o < 4; ++o) {
+                x[4 * r + o][e >> 2] += (int64_t)acc[r][g][o] * ((int64_t)1 << (7 * (e & 3)));
+                if constexpr (DBG) {
+                    const int64_t i = (rb0 + r) * 16 + FormI8::row(lane, o), j = cb * 16 + (lane & 15);
+                    if (i < a.M && j < a.N)
+                        a.dbgD[((int64_t)g * a.M + i) * a.N + j] += acc[r][g][o];
+                }
             }
-        }
     }
 #pragma unroll
-    for (int o = 0; o < 4; ++o)
-        carry28(x[o]);
+    for (int n = 0; n < 4 * R; ++n)
+        carry28(x[n]);
 }
 
 // Limb k of the integer whose limb 0 is zero and limbs 1..NL are L[0..NL-1]
@@ -679,42 +692,46 @@ __device__ __forceinline__ bool to_limbs(int64_t (&x)[NC], uint32_t (&L)[NL])
     return neg;
 }
 
-// Greedy renormalisation of the lane's four outputs, their steps interleaved.
-template <int S>
-__device__ __forceinline__ void tri_outputs(int64_t (&x)[4][Tri<S>::kCols], const GemmArgs& a,
-                                            const WaveTile& w)
+// Greedy renormalisation of the lane's 4 R outputs, their steps interleaved.
+template <int S, int R>
+__device__ __forceinline__ void tri_outputs(int64_t (&x)[4 * R][Tri<S>::kCols], const GemmArgs& a,
+                                            int64_t rb0, int64_t cb, int lane)
 {
-    constexpr int NL = Tri<S>::kLimbs;
-    uint32_t L[4][NL];
-    double sgn[4], *out[4];
-    int scale[4], umin[4];
-    bool ok[4];
+    constexpr int NL = Tri<S>::kLimbs, NO = 4 * R;
+    uint32_t L[NO][NL];
+    double sgn[NO], *out[NO];
+    int scale[NO], umin[NO];
+    bool ok[NO];
 #pragma unroll
-    for (int o = 0; o < 4; ++o) {
-        const int64_t i = w.rb * 16 + FormI8::row(w.lane, o), j = w.cb * 16 + (w.lane & 15);
-        ok[o] = i < a.M && j < a.N;
-        scale[o] = ok[o] ? a.E[i] + a.F[j] - 7 * (S + 1) : 0;
-        umin[o] = -1074 - scale[o];
-        out[o] = a.C + (ok[o] ? i * a.ldc + j : 0);
-        sgn[o] = to_limbs(x[o], L[o]) ? -1.0 : 1.0;
+    for (int n = 0; n < NO; ++n) {
+        const int64_t i = (rb0 + n / 4) * 16 + FormI8::row(lane, n % 4), j = cb * 16 + (lane & 15);
+        ok[n] = i < a.M && j < a.N;
+        scale[n] = ok[n] ? a.E[i] + a.F[j] - 7 * (S + 1) : 0;
+        umin[n] = -1074 - scale[n];
+        out[n] = a.C + (ok[n] ? i * a.ldc + j : 0);
+        sgn[n] = to_limbs(x[n], L[n]) ? -1.0 : 1.0;
     }
     for (int t = 0; t < a.m; ++t) {
 #pragma unroll
-        for (int o = 0; o < 4; ++o) {
-            const double wv = rn_step(L[o], sgn[o], umin[o], scale[o]);
-            if (ok[o])
-                out[o][t * a.psc] = wv;
+        for (int n = 0; n < NO; ++n) {
+            const double wv = rn_step(L[n], sgn[n], umin[n], scale[n]);
+            if (ok[n])
+                out[n][t * a.psc] = wv;
         }
     }
 }
 
-// Whole-triangle INT8 contraction, S <= 32 diagonals in one band.
+// Load lead of the triangle kernels' A fragments, in matrix instructions.
+constexpr int kLeadA = 48;
+
+// Whole-triangle INT8 contraction, S <= 32 diagonals in one band, one row
+// block per wave (32 x 32 workgroup tile), any number of exactness chunks.
 template <int S, bool DBG>
 __global__ __launch_bounds__(256, 1) void k_tri_i8(GemmArgs a)
 {
-    const WaveTile w(a);
+    const WaveTile w(a, 1);
     const uint64_t bytes = (uint64_t)a.nkc * S * 1024;   // one row block of fragments
-    const FragStream LA = frag_stream((const char*)a.A + w.rb * bytes, bytes, w.lane);
+    const FragStream LA[1] = {frag_stream((const char*)a.A + w.rb * bytes, bytes, w.lane)};
     const FragStream LB = frag_stream((const char*)a.B + w.cb * bytes, bytes, w.lane);
     int64_t x[4][Tri<S>::kCols];
 #pragma unroll
@@ -723,19 +740,54 @@ __global__ __launch_bounds__(256, 1) void k_tri_i8(GemmArgs a)
         for (int j = 0; j < Tri<S>::kCols; ++j)
             x[o][j] = 0;
     for (int64_t c0 = 0; c0 < a.nkc; c0 += a.kcc) {
-        v4i acc[S];
+        v4i acc[1][S];
 #pragma unroll
         for (int g = 0; g < S; ++g)
-            acc[g] = FormI8::zero();
-        tri_run_i8<S>(acc, LA, LB, c0, min(c0 + a.kcc, a.nkc));
-        tri_fold<S, DBG>(acc, x, a, w);
+            acc[0][g] = FormI8::zero();
+        tri_run_i8<S, 1, kLeadA>(acc, LA, LB, c0, min(c0 + a.kcc, a.nkc));
+        tri_fold<S, 1, DBG>(acc, x, a, w.rb, w.cb, w.lane);
     }
-    tri_outputs<S>(x, a, w);
+    tri_outputs<S, 1>(x, a, w.rb, w.cb, w.lane);
+}
+
+// The same with two row blocks per wave (64 x 32 workgroup tile), which
+// share the B window: half the B loads per matrix instruction.  The whole
+// depth is one exactness chunk, so the fold columns exist only after the
+// contraction.  A row block past the digit array (M padded to 32 rows) reads
+// through an empty descriptor: zeros.
+template <int S>
+__global__ __launch_bounds__(256, 1) void k_tri2_i8(GemmArgs a)
+{
+    const WaveTile w(a, 2);
+    const uint64_t bytes = (uint64_t)a.nkc * S * 1024;
+    const int64_t nrb = 2 * ((a.M + kTile - 1) / kTile);
+    FragStream LA[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+        LA[r] = frag_stream((const char*)a.A + (w.rb + r) * bytes, w.rb + r < nrb ? bytes : 0,
+                            w.lane);
+    const FragStream LB = frag_stream((const char*)a.B + w.cb * bytes, bytes, w.lane);
+    v4i acc[2][S];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int g = 0; g < S; ++g)
+            acc[r][g] = FormI8::zero();
+    tri_run_i8<S, 2, kLeadA>(acc, LA, LB, 0, a.nkc);
+    int64_t x[8][Tri<S>::kCols];
+#pragma unroll
+    for (int n = 0; n < 8; ++n)
+#pragma unroll
+        for (int j = 0; j < Tri<S>::kCols; ++j)
+            x[n][j] = 0;
+    tri_fold<S, 2, false>(acc, x, a, w.rb, w.cb, w.lane);
+    tri_outputs<S, 2>(x, a, w.rb, w.cb, w.lane);
 }
 
 // lds_fold: the kernel keeps its fold columns in LDS (4 waves x ncol x 256)
 template <class Kernel>
-hipError_t launch_kernel(Kernel k, const GemmArgs& a, hipStream_t st, bool lds_fold = true)
+hipError_t launch_kernel(Kernel k, const GemmArgs& a, hipStream_t st, bool lds_fold = true,
+                         int tile_rows = kTile)
 {
     const size_t lds = lds_fold ? (size_t)4 * a.ncol * 256 * sizeof(int64_t) : 0;
     if (lds) {
@@ -744,7 +796,7 @@ hipError_t launch_kernel(Kernel k, const GemmArgs& a, hipStream_t st, bool lds_f
         if (e != hipSuccess)
             return e;
     }
-    const int64_t tiles = ((a.N + kTile - 1) / kTile) * ((a.M + kTile - 1) / kTile);
+    const int64_t tiles = ((a.N + kTile - 1) / kTile) * ((a.M + tile_rows - 1) / tile_rows);
     hipLaunchKernelGGL(k, dim3((unsigned)tiles), dim3(256), lds, st, a);
     return hipGetLastError();
 }
@@ -776,6 +828,20 @@ struct DispatchTri {
 };
 template <>
 struct DispatchTri<0> {
+    static hipError_t run(const GemmArgs&, hipStream_t) { return hipErrorInvalidValue; }
+};
+
+template <int S>
+struct DispatchTri2 {
+    static hipError_t run(const GemmArgs& a, hipStream_t st)
+    {
+        if (a.S == S)
+            return launch_kernel(k_tri2_i8<S>, a, st, false, 2 * kTile);
+        return DispatchTri2<S - 1>::run(a, st);
+    }
+};
+template <>
+struct DispatchTri2<0> {
     static hipError_t run(const GemmArgs&, hipStream_t) { return hipErrorInvalidValue; }
 };
 
@@ -863,8 +929,12 @@ hipError_t launch_gemm_i8(const GemmArgs& a, hipStream_t st)
 {
     // the triangle kernel's register fold holds |X| / 2^(28 ceil(S/4)) < K 2^9
     // in its signed top column
-    if (a.nbands == 1 && a.S <= kTriMaxI8 && a.nkc * kKcI8 < ((int64_t)1 << 48))
+    if (a.nbands == 1 && a.S <= kTriMaxI8 && a.nkc * kKcI8 < ((int64_t)1 << 48)) {
+        // one exactness chunk: two row blocks per wave (no debug dump there)
+        if (a.kcc >= a.nkc && !a.dbgD)
+            return DispatchTri2<kTriMaxI8>::run(a, st);
         return DispatchTri<kTriMaxI8>::run(a, st);
+    }
     return Dispatch<FormI8, kGmaxI8>::run(a, st);
 }
 
