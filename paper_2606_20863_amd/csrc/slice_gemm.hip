@@ -845,10 +845,85 @@ struct DispatchTri2<0> {
     static hipError_t run(const GemmArgs&, hipStream_t) { return hipErrorInvalidValue; }
 };
 
-// min over the outputs of P_ij = sum_k qA_ik qB_kj: a wave computes a 64 x 64
-// block (4 x 4 fragments), a workgroup 128 x 128.  Each 16 x 16 fragment sum
-// of one depth fragment is below 64 * 127^2 < 2^20, so INT32 holds 2^11
-// depth fragments exactly; longer depths are carried into int64.
+// min over the outputs of P_ij = sum_k qA_ik qB_kj, depth up to 2^11 depth
+// fragments (INT32 exact: one fragment adds below 64 * 127^2 < 2^20): a wave
+// computes a 64 x 64 block (4 x 4 fragments), a workgroup 128 x 128.  The
+// fragments of the next kMagDepth depth steps are in flight while the
+// current one multiplies.  Row or column blocks past the padded arrays read
+// through empty descriptors (zeros; those outputs are not counted).
+constexpr int kMagDepth = 4;
+
+__global__ __launch_bounds__(256) void k_mag_min_short(const v4i* __restrict__ qA,
+                                                       const v4i* __restrict__ qB, int64_t M,
+                                                       int64_t N, int64_t nkc,
+                                                       unsigned long long* minP)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t rb0 = ((int64_t)blockIdx.y * 2 + (wave >> 1)) * 4;
+    const int64_t cb0 = ((int64_t)blockIdx.x * 2 + (wave & 1)) * 4;
+    const int64_t nrb = 2 * ((M + kTile - 1) / kTile), ncb = 2 * ((N + kTile - 1) / kTile);
+    const uint64_t bytes = (uint64_t)nkc * 1024;
+    FragStream SA[4], SB[4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+        SA[x] = frag_stream((const char*)qA + (rb0 + x) * bytes, rb0 + x < nrb ? bytes : 0, lane);
+        SB[x] = frag_stream((const char*)qB + (cb0 + x) * bytes, cb0 + x < ncb ? bytes : 0, lane);
+    }
+    v4i acc[4][4], pa[kMagDepth][4], pb[kMagDepth][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+            acc[x][y] = v4i{0, 0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < kMagDepth; ++d)
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+            pa[d][x] = SA[x](d * 1024u);
+            pb[d][x] = SB[x](d * 1024u);
+        }
+    for (int64_t kc = 0; kc < nkc; kc += kMagDepth) {
+#pragma unroll
+        for (int d = 0; d < kMagDepth; ++d) {
+            // depth steps past nkc read zeros and add nothing
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y)
+                    acc[x][y] = __builtin_amdgcn_mfma_i32_16x16x64_i8(pa[d][x], pb[d][y], acc[x][y],
+                                                                      0, 0, 0);
+            const uint32_t nxt = (uint32_t)(kc + d + kMagDepth) * 1024u;
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                pa[d][x] = SA[x](nxt);
+                pb[d][x] = SB[x](nxt);
+            }
+        }
+    }
+    unsigned long long best = ~0ull;
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+#pragma unroll
+            for (int o = 0; o < 4; ++o) {
+                const int64_t i = (rb0 + x) * 16 + FormI8::row(lane, o);
+                const int64_t j = (cb0 + y) * 16 + (lane & 15);
+                const unsigned long long v = (unsigned long long)(uint32_t)acc[x][y][o];
+                if (i < M && j < N && v < best)
+                    best = v;
+            }
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(best, off);
+        best = o < best ? o : best;
+    }
+    if (lane == 0 && best != ~0ull)
+        atomicMin(minP, best);
+}
+
+// The same for longer depths (not pipelined): partial sums carried into
+// int64 every 2^11 depth fragments.
 __global__ __launch_bounds__(256) void k_mag_min(const v4i* __restrict__ qA,
                                                  const v4i* __restrict__ qB, int64_t M, int64_t N,
                                                  int64_t nkc, unsigned long long* minP)
@@ -920,8 +995,12 @@ hipError_t launch_mag_min(const void* qA, const void* qB, int64_t M, int64_t N, 
                           unsigned long long* minP, hipStream_t st)
 {
     dim3 grid((unsigned)((N + 127) / 128), (unsigned)((M + 127) / 128));
-    hipLaunchKernelGGL(k_mag_min, grid, dim3(256), 0, st, (const v4i*)qA, (const v4i*)qB, M, N,
-                       nkc, minP);
+    if (nkc <= 2048)
+        hipLaunchKernelGGL(k_mag_min_short, grid, dim3(256), 0, st, (const v4i*)qA, (const v4i*)qB,
+                           M, N, nkc, minP);
+    else
+        hipLaunchKernelGGL(k_mag_min, grid, dim3(256), 0, st, (const v4i*)qA, (const v4i*)qB, M, N,
+                           nkc, minP);
     return hipGetLastError();
 }
 
