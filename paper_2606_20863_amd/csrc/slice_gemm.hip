@@ -667,6 +667,78 @@ __device__ __forceinline__ double rn_step(uint32_t (&L)[NL], double& sgn, int um
     return w;
 }
 
+// Shift the limbs left so that the top set bit lands on bit 32 NL - 1; the
+// value L 2^scale is kept (scale drops by the shift).  False if L is zero.
+template <int NL>
+__device__ __forceinline__ bool align_left(uint32_t (&L)[NL], int& scale)
+{
+    int top = -1;
+#pragma unroll
+    for (int k = 0; k < NL; ++k)
+        top = L[k] ? 32 * k + 31 - __clz((int)L[k]) : top;
+    const int d = top < 0 ? 0 : 32 * NL - 1 - top;
+    const int q = d >> 5, r = d & 31;
+    // whole limbs: a shift by q as a network of shifts by 1, 2, 4, 8 limbs
+#pragma unroll
+    for (int b = 1; b < NL; b <<= 1) {
+        const bool on = (q & b) != 0;
+#pragma unroll
+        for (int k = NL - 1; k >= 0; --k)
+            L[k] = on ? (k >= b ? L[k - b] : 0u) : L[k];
+    }
+    // then r bits
+#pragma unroll
+    for (int k = NL - 1; k >= 0; --k) {
+        const uint32_t lo = k ? L[k - 1] : 0u;
+        L[k] = r ? __builtin_amdgcn_alignbit(L[k], lo, 32 - r) : L[k];
+    }
+    scale -= d;
+    return top >= 0;
+}
+
+// One greedy round-to-nearest step on left-aligned limbs whose unit
+// 2^(32 NL - 53 + scale) is not below 2^-1074: the significand, the round
+// bit and the sticky bits sit at fixed places.  Returns the word; the
+// remainder (sign in sgn) is left in L.
+template <int NL>
+__device__ __forceinline__ double rn_step_aligned(uint32_t (&L)[NL], double& sgn, int scale)
+{
+    static_assert(NL >= 3, "at least three limbs");
+    const uint64_t n = ((uint64_t)L[NL - 1] << 21) | (L[NL - 2] >> 11);
+    const bool rnd = (L[NL - 2] >> 10) & 1u;
+    uint32_t st = L[NL - 2] & 0x3ffu;
+#pragma unroll
+    for (int k = 0; k < NL - 2; ++k)
+        st |= L[k];
+    const bool up = rnd && (st || (n & 1));
+    const double w = sgn * ldexp((double)(n + up), 32 * NL - 53 + scale);
+    // remainder: the bits below the unit; rounded up, 2^unit minus them with
+    // the sign flipped
+    L[NL - 1] = 0;
+    L[NL - 2] &= 0x7ffu;
+    uint64_t cy = 1;
+#pragma unroll
+    for (int k = 0; k < NL - 1; ++k) {
+        const uint64_t v = (uint64_t)(~L[k]) + cy;
+        cy = v >> 32;
+        L[k] = up ? (uint32_t)v & (k == NL - 2 ? 0x7ffu : ~0u) : L[k];
+    }
+    sgn = up ? -sgn : sgn;
+    return w;
+}
+
+// Greedy step on any limbs: aligned, then the fixed-place step, or the
+// general one where the unit would fall below 2^-1074.
+template <int NL>
+__device__ __forceinline__ double rn_next(uint32_t (&L)[NL], double& sgn, int& scale)
+{
+    if (!align_left(L, scale))
+        return 0.0;
+    if (32 * NL - 53 + scale >= -1074)
+        return rn_step_aligned(L, sgn, scale);
+    return rn_step(L, sgn, -1074 - scale, scale);
+}
+
 // Magnitude limbs of the carried columns; returns the sign.
 template <int NC, int NL>
 __device__ __forceinline__ bool to_limbs(int64_t (&x)[NC], uint32_t (&L)[NL])
@@ -700,21 +772,20 @@ __device__ __forceinline__ void tri_outputs(int64_t (&x)[4 * R][Tri<S>::kCols], 
     constexpr int NL = Tri<S>::kLimbs, NO = 4 * R;
     uint32_t L[NO][NL];
     double sgn[NO], *out[NO];
-    int scale[NO], umin[NO];
+    int scale[NO];
     bool ok[NO];
 #pragma unroll
     for (int n = 0; n < NO; ++n) {
         const int64_t i = (rb0 + n / 4) * 16 + FormI8::row(lane, n % 4), j = cb * 16 + (lane & 15);
         ok[n] = i < a.M && j < a.N;
         scale[n] = ok[n] ? a.E[i] + a.F[j] - 7 * (S + 1) : 0;
-        umin[n] = -1074 - scale[n];
         out[n] = a.C + (ok[n] ? i * a.ldc + j : 0);
         sgn[n] = to_limbs(x[n], L[n]) ? -1.0 : 1.0;
     }
     for (int t = 0; t < a.m; ++t) {
 #pragma unroll
         for (int n = 0; n < NO; ++n) {
-            const double wv = rn_step(L[n], sgn[n], umin[n], scale[n]);
+            const double wv = rn_next(L[n], sgn[n], scale[n]);
             if (ok[n])
                 out[n][t * a.psc] = wv;
         }
