@@ -27,6 +27,7 @@
 // end).  The whole-triangle INT8 kernel, whose bit positions are all known at
 // compile time, keeps it in registers and renormalises there.
 #include "mdgemm_internal.h"
+#include "renorm.h"
 
 namespace mdg {
 namespace {
@@ -570,25 +571,7 @@ __global__ __launch_bounds__(256, 1) void k_slice_gemm(GemmArgs a)
 // 7 (e mod 4).  One depth chunk adds less than 2^31 (1 + 2^7 + 2^14 + 2^21)
 // < 2^53 to a column; after every chunk the columns are carried back to 28
 // bits.  The top column takes only carries and is the signed one.
-template <int S>
-struct Tri {
-    static constexpr int kCols = (S + 3) / 4 + 1;
-    // 32-bit limbs of the magnitude: kCols-1 columns of 28 bits, a top one
-    // below 2^64
-    static constexpr int kLimbs = (28 * (kCols - 1) + 64 + 31) / 32;
-};
-
-template <int NC>
-__device__ __forceinline__ void carry28(int64_t (&x)[NC])
-{
-#pragma unroll
-    for (int j = 0; j + 1 < NC; ++j) {
-        x[j + 1] += x[j] >> 28;
-        x[j] &= 0xfffffffLL;
-    }
-}
-
-// x[4 r + o]: output o of the lane in row block rb0 + r
+// x[4 r + o] holds output o of the lane in row block rb0 + r.
 template <int S, int R, bool DBG>
 __device__ __forceinline__ void tri_fold(const v4i (&acc)[R][S], int64_t (&x)[4 * R][Tri<S>::kCols],
                                          const GemmArgs& a, int64_t rb0, int64_t cb, int lane)
@@ -611,157 +594,6 @@ __device__ __forceinline__ void tri_fold(const v4i (&acc)[R][S], int64_t (&x)[4 
 #pragma unroll
     for (int n = 0; n < 4 * R; ++n)
         carry28(x[n]);
-}
-
-// Limb k of the integer whose limb 0 is zero and limbs 1..NL are L[0..NL-1]
-// (bits of X shifted up by 32, so that bit unit-1 >= -1 of X has a place).
-template <int NL>
-__device__ __forceinline__ uint32_t shifted_limb(const uint32_t (&L)[NL], int k)
-{
-    return (k >= 1 && k <= NL) ? L[k - 1] : 0u;
-}
-
-// One greedy round-to-nearest step on (-1)^neg X 2^scale, X >= 0 held in
-// 32-bit limbs L: returns the word RN(X 2^scale) (with sign) and leaves the
-// remainder in L and its sign in sgn.  The same steps as the LDS version,
-// with every limb index static (data-dependent positions become selects)
-// and no branches, so that the steps of several outputs interleave.
-template <int NL>
-__device__ __forceinline__ double rn_step(uint32_t (&L)[NL], double& sgn, int umin, int scale)
-{
-    int top = -1;
-#pragma unroll
-    for (int k = 0; k < NL; ++k)
-        top = L[k] ? 32 * k + 31 - __clz((int)L[k]) : top;
-    const int unit = max(max(top - 52, umin), 0);
-    // 64 bits of X from bit unit-1: the round bit, then the 53-bit
-    // significand; sticky: any bit below unit-1
-    const int P = unit + 31, q = P >> 5, r = P & 31;
-    uint32_t l0 = 0, l1 = 0, l2 = 0, st = 0;
-#pragma unroll
-    for (int k = 0; k <= NL; ++k) {
-        const uint32_t v = shifted_limb(L, k);
-        st |= k < q ? v : (k == q ? v & ((1u << r) - 1u) : 0u);
-        l0 = k == q ? v : l0;
-        l1 = k == q ? shifted_limb(L, k + 1) : l1;
-        l2 = k == q ? shifted_limb(L, k + 2) : l2;
-    }
-    const uint64_t lo = (uint64_t)l0 | ((uint64_t)l1 << 32);
-    const uint64_t win = r ? ((lo >> r) | ((uint64_t)l2 << (64 - r))) : lo;
-    uint64_t n = win >> 1;
-    const bool up = (win & 1) && (st || (n & 1));
-    n += up;
-    const double w = top >= 0 ? sgn * ldexp((double)n, unit + scale) : 0.0;
-    // remainder: the bits below unit; rounded up, 2^unit minus them with the
-    // sign flipped
-    uint64_t cy = 1;
-#pragma unroll
-    for (int k = 0; k < NL; ++k) {
-        const int b = unit - 32 * k;
-        const uint32_t keep = b >= 32 ? ~0u : (b <= 0 ? 0u : (1u << b) - 1u);
-        const uint64_t v = (uint64_t)(~L[k]) + cy;
-        cy = v >> 32;
-        L[k] = (up ? (uint32_t)v : L[k]) & keep;
-    }
-    sgn = up ? -sgn : sgn;
-    return w;
-}
-
-// Shift the limbs left so that the top set bit lands on bit 32 NL - 1; the
-// value L 2^scale is kept (scale drops by the shift).  False if L is zero.
-template <int NL>
-__device__ __forceinline__ bool align_left(uint32_t (&L)[NL], int& scale)
-{
-    int top = -1;
-#pragma unroll
-    for (int k = 0; k < NL; ++k)
-        top = L[k] ? 32 * k + 31 - __clz((int)L[k]) : top;
-    const int d = top < 0 ? 0 : 32 * NL - 1 - top;
-    const int q = d >> 5, r = d & 31;
-    // whole limbs: a shift by q as a network of shifts by 1, 2, 4, 8 limbs
-#pragma unroll
-    for (int b = 1; b < NL; b <<= 1) {
-        const bool on = (q & b) != 0;
-#pragma unroll
-        for (int k = NL - 1; k >= 0; --k)
-            L[k] = on ? (k >= b ? L[k - b] : 0u) : L[k];
-    }
-    // then r bits
-#pragma unroll
-    for (int k = NL - 1; k >= 0; --k) {
-        const uint32_t lo = k ? L[k - 1] : 0u;
-        L[k] = r ? __builtin_amdgcn_alignbit(L[k], lo, 32 - r) : L[k];
-    }
-    scale -= d;
-    return top >= 0;
-}
-
-// One greedy round-to-nearest step on left-aligned limbs whose unit
-// 2^(32 NL - 53 + scale) is not below 2^-1074: the significand, the round
-// bit and the sticky bits sit at fixed places.  Returns the word; the
-// remainder (sign in sgn) is left in L.
-template <int NL>
-__device__ __forceinline__ double rn_step_aligned(uint32_t (&L)[NL], double& sgn, int scale)
-{
-    static_assert(NL >= 3, "at least three limbs");
-    const uint64_t n = ((uint64_t)L[NL - 1] << 21) | (L[NL - 2] >> 11);
-    const bool rnd = (L[NL - 2] >> 10) & 1u;
-    uint32_t st = L[NL - 2] & 0x3ffu;
-#pragma unroll
-    for (int k = 0; k < NL - 2; ++k)
-        st |= L[k];
-    const bool up = rnd && (st || (n & 1));
-    const double w = sgn * ldexp((double)(n + up), 32 * NL - 53 + scale);
-    // remainder: the bits below the unit; rounded up, 2^unit minus them with
-    // the sign flipped
-    L[NL - 1] = 0;
-    L[NL - 2] &= 0x7ffu;
-    uint64_t cy = 1;
-#pragma unroll
-    for (int k = 0; k < NL - 1; ++k) {
-        const uint64_t v = (uint64_t)(~L[k]) + cy;
-        cy = v >> 32;
-        L[k] = up ? (uint32_t)v & (k == NL - 2 ? 0x7ffu : ~0u) : L[k];
-    }
-    sgn = up ? -sgn : sgn;
-    return w;
-}
-
-// Greedy step on any limbs: aligned, then the fixed-place step, or the
-// general one where the unit would fall below 2^-1074.
-template <int NL>
-__device__ __forceinline__ double rn_next(uint32_t (&L)[NL], double& sgn, int& scale)
-{
-    if (!align_left(L, scale))
-        return 0.0;
-    if (32 * NL - 53 + scale >= -1074)
-        return rn_step_aligned(L, sgn, scale);
-    return rn_step(L, sgn, -1074 - scale, scale);
-}
-
-// Magnitude limbs of the carried columns; returns the sign.
-template <int NC, int NL>
-__device__ __forceinline__ bool to_limbs(int64_t (&x)[NC], uint32_t (&L)[NL])
-{
-    const bool neg = x[NC - 1] < 0;
-#pragma unroll
-    for (int j = 0; j < NC; ++j)
-        x[j] = neg ? -x[j] : x[j];
-    carry28(x);
-#pragma unroll
-    for (int k = 0; k < NL; ++k)
-        L[k] = 0;
-#pragma unroll
-    for (int j = 0; j < NC; ++j) {
-        const uint64_t v = (uint64_t)x[j];
-        const int b = 28 * j, k = b >> 5, r = b & 31;
-        L[k] |= (uint32_t)(v << r);
-        if (k + 1 < NL)
-            L[k + 1] |= (uint32_t)(r ? v >> (32 - r) : v >> 32);
-        if (k + 2 < NL && r)
-            L[k + 2] |= (uint32_t)(v >> (64 - r));
-    }
-    return neg;
 }
 
 // Greedy renormalisation of the lane's 4 R outputs, their steps interleaved.
