@@ -32,13 +32,34 @@ PEAK_INT8_TOPS = 5000.0      # MI355X dense INT8 matrix peak, TOP/s
 PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 matrix peak, TFLOP/s
 
 
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_tri2_i8_qd4096_traffic.md")
+KERNEL_SOURCES = ("csrc/slice_gemm.hip", "csrc/renorm.h", "csrc/mdgemm_internal.h", "build.py")
+
+
+def kernel_fingerprint():
+    """sha256 over the sources of the slice contraction kernels, first 16 hex digits."""
+    import hashlib
+    pkg = os.path.join(ROOT, "paper_2606_20863_amd")
+    blob = b"".join(open(os.path.join(pkg, f), "rb").read() for f in KERNEL_SOURCES)
+    return hashlib.sha256(blob).hexdigest()[:16]
+
+
+def int8_kernel_name(info, K):
+    """The INT8 slice contraction kernel the library dispatches for these
+    parameters: the whole triangle (S <= 32) with two row blocks per wave when
+    the depth is one exactness chunk, else one row block; bands otherwise."""
+    S, band = info["S"], info["band"]
+    if band == S and S <= 32:
+        return f"k_tri2_i8<{S}>" if info["kc"] >= K else f"k_tri_i8<{S}, false>"
+    return f"k_slice_gemm<FormI8, {band}, false>"
+
+
 def measured_traffic(kernel: str):
     """HBM bytes per launch of the INT8 slice contraction from the committed
     counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by its reading
     for a plain 1 GiB copy); None when the summary is missing, covers another
     kernel, or the kernel source changed since the counters were taken."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", "k_tri_i8_qd4096_traffic.md")
+    path = TRAFFIC_SUMMARY
     if not os.path.exists(path):
         return None
     vals = {}
@@ -46,12 +67,8 @@ def measured_traffic(kernel: str):
         if ":" in line and not line.startswith(("|", " ", "#")):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    pkg = os.path.join(ROOT, "paper_2606_20863_amd")
-    blob = b"".join(open(os.path.join(pkg, f), "rb").read()
-                    for f in ("csrc/slice_gemm.hip", "csrc/mdgemm_internal.h", "build.py"))
-    fp = hashlib.sha256(blob).hexdigest()[:16]
     want = vals.get("Kernel source fingerprint", "").split("=")[-1].strip()
-    if fp != want or kernel != vals.get("kernel"):
+    if kernel_fingerprint() != want or kernel != vals.get("kernel"):
         return None
     copy = float(vals["copy_bytes"])
     fetch = float(vals["fetch_kib"]) * 1024 * copy / (float(vals["copy_fetch_kib"]) * 1024)
@@ -118,7 +135,7 @@ def cpu_baseline(A, B, K):
     import numpy as np
     from oracle import coracle
     N = B.shape[2]
-    rows = 8
+    rows = 32
     ii = np.arange(rows, dtype=np.int64).repeat(N)
     jj = np.tile(np.arange(N, dtype=np.int64), rows)
     t0 = time.perf_counter()
@@ -187,8 +204,7 @@ def main():
     ach8 = ops8 / (kern8 * 1e-3) / 1e12
     ach64 = ops64 / (kern64 * 1e-3) / 1e12
 
-    kname8 = (f"k_tri_i8<{S8}, false>" if info8["band"] == S8
-              else f"k_slice_gemm<FormI8, {info8['band']}, false>")
+    kname8 = int8_kernel_name(info8, K)
     traffic8 = measured_traffic(kname8)
     traffic8 = None if traffic8 is None else int(traffic8)
 
