@@ -142,6 +142,34 @@ int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, c
                const md_opts *opts, void *stream);
 
 /*
+ * Batched inner products of m-double vectors, the paper's experiment
+ * (Section 3, Table 2): out_b = sum_k x_bk y_bk for b = 0..batch-1.  The
+ * same four steps as md_gemm_ex with one row of X and one column (a row of
+ * Y) per product: every vector gets a shared exponent, every pair's digits
+ * are contracted on the matrix cores, and every sum is folded exactly and
+ * rounded once into m words.
+ *   m: 1, 2, 4, 8 or 16 words per entry.
+ *   X: word w of element k of vector b at X[w*plane_stride_X + b*ldx + k]
+ *      (ldx >= n); Y likewise with ldy, plane_stride_Y.
+ *   out: word w of product b at out[w*plane_stride_out + b]
+ *      (plane_stride_out >= batch when m > 1); fully overwritten; must not
+ *      overlap X or Y.
+ *   opts as for md_gemm_ex (NULL: FP64 form, MD_S_RHO rule, T = 50 m),
+ *   except that dbg must be NULL; ev_gemm_begin / ev_gemm_end bracket the
+ *   contraction and the fold.  Guarantee: md_gemm_ex's, with (|A||B|)_ij
+ *   read as sum_k |x_bk| |y_bk|.
+ * batch = 0 is a no-op; n = 0 writes zeros.  Return codes as md_gemm_ex.
+ */
+int md_dot_ex(int m, int64_t batch, int64_t n, const double *X, int64_t ldx,
+              int64_t plane_stride_X, const double *Y, int64_t ldy, int64_t plane_stride_Y,
+              double *out, int64_t plane_stride_out, const md_opts *opts, void *stream);
+
+/* md_dot_ex on dense planes (ldx = ldy = n, plane strides batch n and
+ * batch), the plain FP64-slice form. */
+int md_dot(int m, int64_t batch, int64_t n, const double *X, const double *Y, double *out,
+           void *stream);
+
+/*
  * Parameter rule alone (host only, no device work): (beta, S, kc, band) for
  * a form, contraction depth K, target T and ratio-bound exponent G.
  * Returns MD_OK, MD_EINVAL_OPT or MD_ERANGE.

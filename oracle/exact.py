@@ -42,7 +42,7 @@ import numpy as np
 
 # Target relative accuracy 2^-T of each m-double output entry, measured
 # against (|A||B|)_ij.
-TARGET_BITS = {1: 50, 2: 100, 4: 200, 8: 400}
+TARGET_BITS = {1: 50, 2: 100, 4: 200, 8: 400, 16: 800}
 
 
 # ---------------------------------------------------------------------------
@@ -496,6 +496,74 @@ def method_product(A: np.ndarray, B: np.ndarray, beta: int, S: int,
             C[:, a, b] = renorm_rn(x, m)
     return {"E": E, "F": F, "spanA": spanA, "spanB": spanB,
             "dA": dA, "dB": dB, "D": D, "C": C}
+
+
+# ---------------------------------------------------------------------------
+# batched inner products (the paper's experiment, Section 3)
+# ---------------------------------------------------------------------------
+
+def pair_operands(X: np.ndarray, Y: np.ndarray, b: int):
+    """Pair b of a batch as a 1 x 1 product: x_b as a row (m, 1, n), y_b as
+    a column (m, n, 1).  Every step of the method then is the matrix
+    product's: E is the row exponent of x_b, F the column exponent of y_b."""
+    return X[:, b:b + 1, :], np.ascontiguousarray(Y[:, b, :][:, :, None])
+
+
+def exact_dots(X: np.ndarray, Y: np.ndarray):
+    """Exact sum_k x_bk y_bk and sum_k |x_bk| |y_bk| for every pair b, as
+    lists of Fractions.  X and Y are (m, batch, n) planes."""
+    vals, absvals = [], []
+    for b in range(X.shape[1]):
+        x, y = pair_operands(X, Y, b)
+        num, L = exact_product(x, y)
+        anum, _ = abs_product(x, y)
+        vals.append(Fraction(int(num[0, 0]), 1 << L))
+        absvals.append(Fraction(int(anum[0, 0]), 1 << L))
+    return vals, absvals
+
+
+def rho_G_dot(X: np.ndarray, Y: np.ndarray):
+    """The magnitude certificate of ``rho_G`` over the pairs of a batch:
+    min P is the smallest pair's sum_k qx_bk qy_bk.  Returns (min P, G), G
+    None when min P = 0."""
+    n = X.shape[2]
+    minP = min(rho_G(*pair_operands(X, Y, b))[0] for b in range(X.shape[1]))
+    if minP == 0:
+        return 0, None
+    target = n * (1 << 14) + 1
+    g = 0
+    while (minP << g) < target:
+        g += 1
+    return minP, g
+
+
+def choose_dot_params(X: np.ndarray, Y: np.ndarray, form: str, rule: str = "rho", T: int = 0):
+    """(beta, S, Kc, band) for a batch of inner products: the matrix
+    product's rule with G from the spans of all vectors (and, for the rho
+    rule, the smallest pair's magnitude certificate), depth n."""
+    m, _, n = X.shape
+    T = T or TARGET_BITS[m]
+    _, sx = row_exponents(X[0])
+    _, sy = row_exponents(Y[0])
+    G = span_G(max(sx), max(sy))
+    if rule == "rho":
+        _, g = rho_G_dot(X, Y)
+        if g is not None:
+            G = min(G, g)
+    return choose_params(form, n, T, G)
+
+
+def method_dot(X: np.ndarray, Y: np.ndarray, beta: int, S: int):
+    """The method on every pair of a batch (``method_product`` on the 1 x 1
+    product of pair b).  Returns D (S, batch) and out (m, batch)."""
+    m, batch, _ = X.shape
+    D = np.zeros((S, batch), dtype=object)
+    out = np.zeros((m, batch))
+    for b in range(batch):
+        r = method_product(*pair_operands(X, Y, b), beta, S)
+        D[:, b] = r["D"][:, 0, 0]
+        out[:, b] = r["C"][:, 0, 0]
+    return D, out
 
 
 def exact_gradients(A: np.ndarray, B: np.ndarray, W: np.ndarray):

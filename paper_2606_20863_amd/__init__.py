@@ -84,6 +84,10 @@ def lib():
     L.md_gemm_ex.argtypes = [i32, i32, i32, i64, i64, i64, p, i64, i64, p, i64, i64, p, i64, i64,
                              ctypes.POINTER(MDOpts), p]
     L.md_gemm_ex.restype = i32
+    L.md_dot_ex.argtypes = [i32, i64, i64, p, i64, i64, p, i64, i64, p, i64, ctypes.POINTER(MDOpts), p]
+    L.md_dot_ex.restype = i32
+    L.md_dot.argtypes = [i32, i64, i64, p, p, p, p]
+    L.md_dot.restype = i32
     L.md_choose_params.argtypes = [i32, i64, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                    ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.md_choose_params.restype = i32
@@ -202,6 +206,47 @@ def gemm(A: torch.Tensor, B: torch.Tensor, form: str = "fp64", stream=None) -> t
     return gemm_ex(A, B, form=form, stream=stream)[0]
 
 
+def dot_ex(X: torch.Tensor, Y: torch.Tensor, out: torch.Tensor | None = None, *, form="fp64",
+           rule="rho", target_bits=0, force_S=0, force_beta=0, events=None, stream=None):
+    """Batched m-double inner products out_b = sum_k X[:, b, k] Y[:, b, k].
+
+    X and Y are (m, batch, n) float64 planes on the HIP device (m = 1, 2, 4,
+    8 or 16); out is (m, batch).  Returns (out, info dict); ``events`` as in
+    ``gemm_ex`` (recorded around the contraction and the fold).
+    """
+    _check_planes(X, "X")
+    _check_planes(Y, "Y")
+    X = X.contiguous()
+    Y = Y.contiguous()
+    if X.shape != Y.shape:
+        raise ValueError(f"X and Y differ in shape: {tuple(X.shape)} vs {tuple(Y.shape)}")
+    m, batch, n = X.shape
+    if out is None:
+        out = torch.empty((m, batch), dtype=torch.float64, device=X.device)
+    elif out.shape != (m, batch) or not out.is_contiguous() or out.dtype != torch.float64:
+        raise ValueError("out must be a contiguous float64 (m, batch) tensor")
+    info = MDInfo()
+    opts = MDOpts()
+    opts.form = _FORMS[form]
+    opts.s_rule = _RULES[rule]
+    opts.target_bits = target_bits
+    opts.force_S = force_S
+    opts.force_beta = force_beta
+    opts.info = ctypes.pointer(info)
+    if events is not None:
+        opts.ev_gemm_begin = ctypes.c_void_p(events[0])
+        opts.ev_gemm_end = ctypes.c_void_p(events[1])
+    rc = lib().md_dot_ex(m, batch, n, _ptr(X), n, batch * n, _ptr(Y), n, batch * n, _ptr(out), batch,
+                         ctypes.byref(opts), _stream_handle(stream))
+    _check(rc)
+    return out, info.as_dict()
+
+
+def dot(X: torch.Tensor, Y: torch.Tensor, form: str = "fp64", stream=None) -> torch.Tensor:
+    """out_b = sum_k X[:, b, k] Y[:, b, k] for m-double planes (m, batch, n)."""
+    return dot_ex(X, Y, form=form, stream=stream)[0]
+
+
 class MDGemm(torch.autograd.Function):
     """C = A B with the hand-written m-double adjoint.
 
@@ -227,4 +272,5 @@ class MDGemm(torch.autograd.Function):
         return dA, dB, None
 
 
-__all__ = ["gemm", "gemm_ex", "MDGemm", "choose_params", "lib", "MDError", "MDInfo"]
+__all__ = ["gemm", "gemm_ex", "dot", "dot_ex", "MDGemm", "choose_params", "lib", "MDError",
+           "MDInfo"]

@@ -491,6 +491,230 @@ int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, c
     return MD_OK;
 }
 
+int md_dot_ex(int m, int64_t batch, int64_t n, const double* X, int64_t ldx, int64_t plane_stride_X,
+              const double* Y, int64_t ldy, int64_t plane_stride_Y, double* out,
+              int64_t plane_stride_out, const md_opts* opts, void* stream)
+{
+    g_last_hip = 0;
+    if (m != 1 && m != 2 && m != 4 && m != 8 && m != 16)
+        return MD_EINVAL_M;
+    if (batch < 0 || n < 0)
+        return MD_EINVAL_DIM;
+    md_opts o;
+    memset(&o, 0, sizeof(o));
+    if (opts)
+        o = *opts;
+    if (o.form != MD_FORM_FP64 && o.form != MD_FORM_INT8)
+        return MD_EINVAL_OPT;
+    if (o.s_rule != MD_S_SPAN && o.s_rule != MD_S_RHO)
+        return MD_EINVAL_OPT;
+    if (o.dbg)
+        return MD_EINVAL_OPT;
+    if (batch == 0)
+        return MD_OK;
+    if (!out || (n > 0 && (!X || !Y)))
+        return MD_ENULL;
+    if (m > 1 && plane_stride_out < batch)
+        return MD_EINVAL_DIM;
+    if (n > 0 && (ldx < n || ldy < n || plane_stride_X < 1 || plane_stride_Y < 1))
+        return MD_EINVAL_DIM;
+    if (!mul_ok(batch, std::max<int64_t>(ldx, 1)) || !mul_ok(batch, std::max<int64_t>(ldy, 1)) ||
+        !mul_ok(m, std::max<int64_t>(plane_stride_out, 1)) || batch > (INT64_C(1) << 40) ||
+        n > (INT64_C(1) << 40))
+        return MD_EINVAL_DIM;
+    const Span so = extent(out, m, 1, batch, 0, 1, std::max<int64_t>(plane_stride_out, 1));
+    if (n > 0) {
+        const Span sx = extent(X, m, batch, n, ldx, 1, plane_stride_X);
+        const Span sy = extent(Y, m, batch, n, ldy, 1, plane_stride_Y);
+        if (overlap(so, sx) || overlap(so, sy))
+            return MD_EALIAS;
+    }
+    const int T = o.target_bits > 0 ? o.target_bits : 50 * m;
+    if (o.force_S < 0 || o.force_S > 512 || (o.force_S > 0 && (o.force_beta < 1 || o.force_beta > 24)) ||
+        (o.force_S > 0 && o.form == MD_FORM_INT8 && o.force_beta != 7))
+        return MD_EINVAL_OPT;
+
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    if (n == 0) {
+        if ((e = launch_fill_zero(out, m, 1, batch, batch, std::max<int64_t>(plane_stride_out, 1), st)) !=
+            hipSuccess)
+            return hip_fail(e);
+        if (o.info) {
+            memset(o.info, 0, sizeof(*o.info));
+            o.info->target_bits = T;
+            o.info->log2_bound = -1.0 / 0.0;
+        }
+        return MD_OK;
+    }
+
+    // both operands with the vectors as rows
+    Operand opX{X, plane_stride_X, ldx, 1, batch, n};
+    Operand opY{Y, plane_stride_Y, ldy, 1, batch, n};
+
+    Scratch scr;
+    scr.st = st;
+    if (o.workspace) {
+        scr.user = (char*)o.workspace;
+        scr.user_bytes = o.workspace_bytes;
+    }
+    int32_t *hiX, *loX, *hiY, *loY, *E, *F, *stats;
+    {
+        void* p;
+        int rc = scr.get(small_bytes(batch, batch), &p);
+        if (rc)
+            return rc;
+        int32_t* q = (int32_t*)p;
+        const int64_t Ba = round_up(batch + 64, 64);
+        hiX = q; q += Ba;
+        loX = q; q += Ba;
+        E = q; q += Ba;
+        hiY = q; q += Ba;
+        loY = q; q += Ba;
+        F = q; q += Ba;
+        stats = q;
+    }
+    if ((e = launch_exp_init(hiX, loX, batch, stats, st)) != hipSuccess) return hip_fail(e);
+    if ((e = launch_exp_init(hiY, loY, batch, nullptr, st)) != hipSuccess) return hip_fail(e);
+    if ((e = launch_exp_partial(opX, hiX, loX, st)) != hipSuccess) return hip_fail(e);
+    if ((e = launch_exp_partial(opY, hiY, loY, st)) != hipSuccess) return hip_fail(e);
+    if ((e = launch_exp_final(hiX, loX, batch, E, stats, nullptr, st)) != hipSuccess) return hip_fail(e);
+    if ((e = launch_exp_final(hiY, loY, batch, F, stats + 1, nullptr, st)) != hipSuccess) return hip_fail(e);
+
+    const int64_t nrb = round_up(batch, kTile) / kRowBlock;
+    int32_t spans[4] = {0, 0, 0, 0};   // span_X, span_Y, minimum magnitude product (uint64)
+    int beta, S, band;
+    int64_t kc;
+    int G = 0, G_span = 0, G_rho = -1;
+    const bool use_rho = o.force_S == 0 && o.s_rule == MD_S_RHO;
+    if (use_rho) {
+        // magnitude certificate over the pairs: min_b sum_k qX_bk qY_bk
+        const int64_t nkm = (n + kKcI8 - 1) / kKcI8;
+        void *qX, *qY;
+        int rc = scr.get(digits_bytes(MD_FORM_INT8, batch, n, 1), &qX);
+        if (rc)
+            return rc;
+        rc = scr.get(digits_bytes(MD_FORM_INT8, batch, n, 1), &qY);
+        if (rc)
+            return rc;
+        if ((e = launch_split_mag(opX, E, nrb, nkm, (int8_t*)qX, st)) != hipSuccess)
+            return hip_fail(e);
+        if ((e = launch_split_mag(opY, F, nrb, nkm, (int8_t*)qY, st)) != hipSuccess)
+            return hip_fail(e);
+        if ((e = launch_mag_min_diag(qX, qY, batch, nkm, (unsigned long long*)(stats + 2), st)) != hipSuccess)
+            return hip_fail(e);
+    }
+    if (o.force_S > 0) {
+        beta = o.force_beta;
+        const int gmax = o.form == MD_FORM_INT8 ? kGmaxI8 : kGmaxF64;
+        const int single = o.form == MD_FORM_INT8 ? kTriMaxI8 : 0;
+        int s2;
+        band_round(o.force_S, gmax, single, s2, band);
+        if (s2 != o.force_S)
+            return MD_EINVAL_OPT;
+        S = o.force_S;
+        kc = chunk_depth(S, beta, n, o.form == MD_FORM_INT8 ? ((int64_t)1 << 31) : ((int64_t)1 << 53),
+                         o.form == MD_FORM_INT8 ? kKcI8 : kKcF64);
+        if (kc <= 0)
+            return MD_ERANGE;
+    } else {
+        if ((e = hipMemcpyAsync(spans, stats, sizeof(spans), hipMemcpyDeviceToHost, st)) != hipSuccess)
+            return hip_fail(e);
+        if ((e = hipStreamSynchronize(st)) != hipSuccess)
+            return hip_fail(e);
+        G_span = spans[0] + spans[1] + 2;
+        G = G_span;
+        if (use_rho) {
+            uint64_t minP;
+            memcpy(&minP, spans + 2, sizeof(minP));
+            G_rho = rho_exponent(minP, n);
+            if (G_rho >= 0 && G_rho < G)
+                G = G_rho;
+        }
+        const int rc = choose(o.form, n, T, G, beta, S, kc, band);
+        if (rc)
+            return rc;
+    }
+    const int kcg = o.form == MD_FORM_INT8 ? kKcI8 : kKcF64;
+    const int64_t nkc = (n + kcg - 1) / kcg;
+    const int ncol = fold_columns(beta, S, nkc * kcg);
+    if ((size_t)ncol * 256 * sizeof(int64_t) > 160 * 1024)
+        return MD_ERANGE;
+
+    void *dX, *dY, *Dp;
+    int rc = scr.get(digits_bytes(o.form, batch, n, S), &dX);
+    if (rc)
+        return rc;
+    rc = scr.get(digits_bytes(o.form, batch, n, S), &dY);
+    if (rc)
+        return rc;
+    rc = scr.get((size_t)S * batch * sizeof(int64_t), &Dp);
+    if (rc)
+        return rc;
+    if (o.form == MD_FORM_INT8) {
+        if ((e = launch_split_i8(opX, m, E, S, nrb, nkc, (int8_t*)dX, nullptr, st)) != hipSuccess)
+            return hip_fail(e);
+        if ((e = launch_split_i8(opY, m, F, S, nrb, nkc, (int8_t*)dY, nullptr, st)) != hipSuccess)
+            return hip_fail(e);
+    } else {
+        if ((e = launch_split_f64(opX, m, E, S, beta, nrb, nkc, (double*)dX, nullptr, st)) != hipSuccess)
+            return hip_fail(e);
+        if ((e = launch_split_f64(opY, m, F, S, beta, nrb, nkc, (double*)dY, nullptr, st)) != hipSuccess)
+            return hip_fail(e);
+    }
+    if ((e = launch_fill_zero_i64((int64_t*)Dp, (int64_t)S * batch, st)) != hipSuccess)
+        return hip_fail(e);
+
+    DotArgs da;
+    da.X = dX;
+    da.Y = dY;
+    da.D = (int64_t*)Dp;
+    da.batch = batch;
+    da.nkc = nkc;
+    da.S = S;
+    da.band = band;
+    da.nbands = S / band;
+    // depth fragments per workgroup: within one exactness chunk, and short
+    // enough that about 2048 workgroups share the depth
+    {
+        const int64_t kcc = std::max<int64_t>(kc / kcg, 1);
+        const int64_t units = ((batch + 15) / 16) * da.nbands;
+        const int64_t want = (nkc * units + 2047) / 2048;
+        da.range = std::max<int64_t>(1, std::min<int64_t>(kcc, want));
+    }
+    if (o.ev_gemm_begin && (e = hipEventRecord((hipEvent_t)o.ev_gemm_begin, st)) != hipSuccess)
+        return hip_fail(e);
+    if ((e = launch_dot_diag(da, o.form == MD_FORM_INT8, st)) != hipSuccess)
+        return hip_fail(e);
+    if ((e = launch_dot_final((const int64_t*)Dp, E, F, batch, S, beta, ncol, m, out,
+                              std::max<int64_t>(plane_stride_out, 1), st)) != hipSuccess)
+        return hip_fail(e);
+    if (o.ev_gemm_end && (e = hipEventRecord((hipEvent_t)o.ev_gemm_end, st)) != hipSuccess)
+        return hip_fail(e);
+
+    if (o.info) {
+        md_info* in = o.info;
+        in->S = S;
+        in->beta = beta;
+        in->kc = (int)std::min<int64_t>(kc, INT_MAX);
+        in->band = band;
+        in->span_A = spans[0];
+        in->span_B = spans[1];
+        in->G = G;
+        in->G_span = G_span;
+        in->G_rho = G_rho;
+        in->target_bits = T;
+        const double lb = (double)(G - beta * S) + __builtin_log2((double)S + 2.0);
+        in->log2_bound = o.force_S > 0 ? 0.0 : __builtin_log2(__builtin_exp2(lb) + __builtin_exp2(-53.0 * m + 0.1));
+    }
+    return MD_OK;
+}
+
+int md_dot(int m, int64_t batch, int64_t n, const double* X, const double* Y, double* out, void* stream)
+{
+    return md_dot_ex(m, batch, n, X, n, batch * n, Y, n, batch * n, out, batch, nullptr, stream);
+}
+
 int md_gemm(int m, int64_t M, int64_t N, int64_t K, const double* A, const double* B, double* C,
             void* stream)
 {

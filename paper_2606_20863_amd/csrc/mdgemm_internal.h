@@ -77,4 +77,27 @@ hipError_t launch_mag_min(const void* qA, const void* qB, int64_t M, int64_t N, 
                           unsigned long long* minP, hipStream_t st);
 hipError_t launch_gemm_f64(const GemmArgs& a, hipStream_t st);
 
+// Batched inner products out_b = sum_k x_bk y_bk: both operands are split
+// with the vectors as rows (fragment layout of op(A)), so block rb of 16
+// pairs multiplies row block rb of X with row block rb of Y and keeps the
+// diagonal of each 16 x 16 slice product.
+struct DotArgs {
+    const void* X;       // digit fragments of X (rows = vectors)
+    const void* Y;       // digit fragments of Y
+    int64_t* D;          // S x batch diagonal sums, zeroed before the launch
+    int64_t batch, nkc;  // pairs, depth fragments
+    int64_t range;       // depth fragments per workgroup (within one exactness chunk)
+    int S, band, nbands;
+};
+hipError_t launch_dot_diag(const DotArgs& a, int form_int8, hipStream_t st);
+hipError_t launch_fill_zero_i64(int64_t* p, int64_t n, hipStream_t st);
+// out_b (m words, plane stride pso) from the diagonal sums: exact fold and
+// greedy rounding, ncol 32-bit fold columns per pair
+hipError_t launch_dot_final(const int64_t* D, const int32_t* E, const int32_t* F, int64_t batch,
+                            int S, int beta, int ncol, int m, double* out, int64_t pso,
+                            hipStream_t st);
+// min over pairs of sum_k qX_bk qY_bk into *minP (atomic min)
+hipError_t launch_mag_min_diag(const void* qX, const void* qY, int64_t batch, int64_t nkc,
+                               unsigned long long* minP, hipStream_t st);
+
 }  // namespace mdg

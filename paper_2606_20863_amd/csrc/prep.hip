@@ -356,9 +356,11 @@ hipError_t launch_split_i8(const Operand& op, int m, const int32_t* E, int S, in
 {
     dim3 grid((unsigned)nkc, (unsigned)nrb);
     switch (m) {
+    case 1: hipLaunchKernelGGL(k_split_i8<1>, grid, dim3(256), 0, st, op, E, S, nkc, out, dbg); break;
     case 2: hipLaunchKernelGGL(k_split_i8<2>, grid, dim3(256), 0, st, op, E, S, nkc, out, dbg); break;
     case 4: hipLaunchKernelGGL(k_split_i8<4>, grid, dim3(256), 0, st, op, E, S, nkc, out, dbg); break;
     case 8: hipLaunchKernelGGL(k_split_i8<8>, grid, dim3(256), 0, st, op, E, S, nkc, out, dbg); break;
+    case 16: hipLaunchKernelGGL(k_split_i8<16>, grid, dim3(256), 0, st, op, E, S, nkc, out, dbg); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -378,9 +380,11 @@ hipError_t launch_split_f64(const Operand& op, int m, const int32_t* E, int S, i
     const int64_t blocks = (nrb * nkc + 3) / 4;
     dim3 grid((unsigned)blocks);
     switch (m) {
+    case 1: hipLaunchKernelGGL(k_split_f64<1>, grid, dim3(256), 0, st, op, E, S, beta, nrb, nkc, out, dbg); break;
     case 2: hipLaunchKernelGGL(k_split_f64<2>, grid, dim3(256), 0, st, op, E, S, beta, nrb, nkc, out, dbg); break;
     case 4: hipLaunchKernelGGL(k_split_f64<4>, grid, dim3(256), 0, st, op, E, S, beta, nrb, nkc, out, dbg); break;
     case 8: hipLaunchKernelGGL(k_split_f64<8>, grid, dim3(256), 0, st, op, E, S, beta, nrb, nkc, out, dbg); break;
+    case 16: hipLaunchKernelGGL(k_split_f64<16>, grid, dim3(256), 0, st, op, E, S, beta, nrb, nkc, out, dbg); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

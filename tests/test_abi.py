@@ -69,6 +69,32 @@ def test_argument_errors_before_device_work():
                         ctypes.byref(opts), None) == 7
 
 
+def test_dot_argument_errors_before_device_work():
+    L = md.lib()
+    p = ctypes.c_void_p(0x1000)
+    x = ctypes.c_void_p(0x100000)
+    y = ctypes.c_void_p(0x900000)
+    o = ctypes.c_void_p(0x500000)
+    # m outside {1, 2, 4, 8, 16}
+    for m in (0, 3, 5, 32):
+        assert L.md_dot(m, 4, 4, p, p, p, None) == 1
+    # negative sizes; empty batch is a no-op even with NULL pointers
+    assert L.md_dot(2, -1, 4, p, p, p, None) == 2
+    assert L.md_dot(16, 0, 4, None, None, None, None) == 0
+    # NULL data
+    assert L.md_dot(2, 4, 4, None, y, o, None) == 3
+    # output overlapping X
+    assert L.md_dot(2, 4, 4, x, y, ctypes.c_void_p(0x100000 + 8), None) == 4
+    # leading dimension below n, output planes closer than the batch
+    opts = md.MDOpts()
+    assert L.md_dot_ex(2, 4, 8, x, 7, 32, y, 8, 32, o, 4, ctypes.byref(opts), None) == 2
+    assert L.md_dot_ex(2, 4, 8, x, 8, 32, y, 8, 32, o, 3, ctypes.byref(opts), None) == 2
+    # no debug dump for inner products
+    dbg = md.MDDebug()
+    opts.dbg = ctypes.pointer(dbg)
+    assert L.md_dot_ex(2, 4, 8, x, 8, 32, y, 8, 32, o, 4, ctypes.byref(opts), None) == 7
+
+
 @pytest.mark.parametrize("form", ["int8", "fp64"])
 @pytest.mark.parametrize("K", [1, 64, 100, 1024, 2048, 4096, 100000])
 @pytest.mark.parametrize("T,G", [(100, 2), (100, 40), (200, 3), (200, 44), (400, 9), (400, 34)])

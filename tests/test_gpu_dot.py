@@ -1,0 +1,133 @@
+"""Batched m-double inner products on the GPU (the paper's experiment,
+Section 3) against the oracle, through the C ABI (needs an MI355X).
+
+* small ragged batches, m = 1, 2, 4, 8, 16, both slice forms, the library's
+  own rule: parameters equal the oracle's rule, every output word equal to
+  the oracle's method (greedy rounding makes the output unique), and every
+  product within 2^-T of sum_k |x_k||y_k| of the exact one;
+* the paper's parameters (FP64 form, beta = 13, S = 4m) on the paper's bit
+  pattern, m = 1..16: bit-exact against the oracle;
+* the inner products against the diagonal of the matrix product (a separate
+  GPU path) with the same forced parameters: bit-identical;
+* the paper's workload size (1,024 pairs of length 6,144, bit pattern):
+  sampled pairs bit-exact against the C oracle's method and within 2^-T of
+  the exact products;
+* degenerate sizes.
+"""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import torch
+
+import mdinputs
+import paper_2606_20863_amd as md
+from oracle import coracle
+from oracle import exact as ox
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def random_batch(m, nb, n, seed, lead=("log2uniform", 8.0)):
+    r = rng(seed)
+    return mdinputs.mdouble(r, m, (nb, n), lead), mdinputs.mdouble(r, m, (nb, n), lead)
+
+
+def check_bound(X, Y, out, T):
+    vals, absvals = ox.exact_dots(X, Y)
+    for b in range(X.shape[1]):
+        err = abs(ox.entry_value(out[:, b]) - vals[b])
+        assert err <= Fraction(2) ** -T * absvals[b], b
+        assert ox.is_nonoverlapping(out[:, b], strong=True), b
+
+
+@pytest.mark.parametrize("m", [1, 2, 4, 8, 16])
+@pytest.mark.parametrize("form", ["int8", "fp64"])
+def test_dot_small_rule_bitexact(m, form):
+    X, Y = random_batch(m, 37, 130, 100 + m)
+    X[:, 5, :] = 0.0                      # an all-zero vector: its product is 0
+    out, info = md.dot_ex(dev(X), dev(Y), form=form)
+    out = host(out)
+    beta, S, kc, band = ox.choose_dot_params(X, Y, form)
+    assert (info["beta"], info["S"], info["kc"], info["band"]) == (beta, S, kc, band)
+    _, ref = ox.method_dot(X, Y, beta, S)
+    np.testing.assert_array_equal(out, ref)
+    assert np.all(out[:, 5] == 0.0)
+    check_bound(X, Y, out, ox.TARGET_BITS[m])
+
+
+@pytest.mark.parametrize("m", [1, 2, 4, 8, 16])
+def test_dot_paper_parameters_on_paper_pattern(m):
+    r = rng(200 + m)
+    X, _, _ = mdinputs.paper_pattern(r, m, (20, 100))
+    Y, _, _ = mdinputs.paper_pattern(r, m, (20, 100))
+    out, info = md.dot_ex(dev(X), dev(Y), form="fp64", force_S=4 * m, force_beta=13)
+    assert (info["S"], info["beta"]) == (4 * m, 13)
+    _, ref = ox.method_dot(X, Y, 13, 4 * m)
+    np.testing.assert_array_equal(host(out), ref)
+
+
+@pytest.mark.parametrize("form,S,beta", [("int8", 30, 7), ("int8", 48, 7), ("fp64", 12, 18)])
+def test_dot_equals_gemm_diagonal(form, S, beta):
+    """Pair b's product is entry (b, b) of X Y^T: the matrix-product kernels
+    with the same forced parameters must give the same words."""
+    X, Y = random_batch(4, 40, 200, 300)
+    out, _ = md.dot_ex(dev(X), dev(Y), form=form, force_S=S, force_beta=beta)
+    C, _ = md.gemm_ex(dev(X), dev(Y), transB=True, form=form, force_S=S, force_beta=beta)
+    C = host(C)
+    np.testing.assert_array_equal(host(out), C[:, np.arange(40), np.arange(40)])
+
+
+@pytest.mark.parametrize("m,nb", [(4, 1024), (16, 256)])
+def test_dot_paper_workload_sampled(m, nb):
+    """Inner products of length 6,144 on the bit pattern (the paper's Table 2
+    workload: 1,024 pairs; 256 at m = 16 to bound the generator's host
+    memory), INT8 form: 16 sampled pairs bit-exact against the C oracle's
+    method and within 2^-T of the exact products."""
+    r = rng(400 + m)
+    X, _, _ = mdinputs.paper_pattern(r, m, (nb, 6144))
+    Y, _, _ = mdinputs.paper_pattern(r, m, (nb, 6144))
+    out, info = md.dot_ex(dev(X), dev(Y), form="int8")
+    out = host(out)
+    pairs = np.linspace(0, nb - 1, 16).astype(np.int64)
+    Xs = np.ascontiguousarray(X[:, pairs, :])
+    Ys = np.ascontiguousarray(np.transpose(Y[:, pairs, :], (0, 2, 1)))
+    idx = np.arange(len(pairs), dtype=np.int64)
+    for a in idx:
+        _, _, _, Cref = coracle.method_entries(Xs, Ys, info["beta"], info["S"], idx[a:a + 1],
+                                               idx[a:a + 1])
+        np.testing.assert_array_equal(out[:, pairs[a]], Cref[:, 0, 0])
+    Cq = np.ascontiguousarray(out[:, pairs].T)
+    _, absab, err = coracle.exact_entries(Xs, Ys, idx, idx, Cq)
+    assert np.all(np.abs(err) / absab <= 2.0 ** -ox.TARGET_BITS[m])
+
+
+def test_dot_degenerate_sizes():
+    # n = 0: exact zeros
+    X = torch.zeros((4, 6, 0), dtype=torch.float64, device="cuda")
+    out = torch.full((4, 6), 3.0, dtype=torch.float64, device="cuda")
+    md.dot_ex(X, X, out)
+    assert np.all(host(out) == 0.0)
+    # batch = 0: nothing happens
+    E = torch.zeros((2, 0, 5), dtype=torch.float64, device="cuda")
+    assert md.dot_ex(E, E)[0].shape == (2, 0)
+    # one pair of length one: the m-double product of two m-doubles
+    for m in (1, 8, 16):
+        X, Y = random_batch(m, 1, 1, 500 + m)
+        for form in ("int8", "fp64"):
+            out, info = md.dot_ex(dev(X), dev(Y), form=form)
+            _, ref = ox.method_dot(X, Y, info["beta"], info["S"])
+            np.testing.assert_array_equal(host(out), ref)
