@@ -158,26 +158,37 @@ __device__ __forceinline__ void limb_pair(const uint64_t (&mant)[MW], const int 
     }
 }
 
-// INT8 split: one block of 256 threads writes one fragment (1 KB); thread T
-// writes bytes [4T, 4T+4): lane T/4 of the fragment, depth bytes 4 (T%4).. .
-template <int MW>
-__global__ __launch_bounds__(256) void k_split_i8(Operand op, const int32_t* E, int S, int64_t nkc,
-                                                  int8_t* out, int32_t* dbg)
+// Store of EPT consecutive digit bytes.
+template <int EPT> struct Bytes;
+template <> struct Bytes<4> { typedef uint32_t type; };
+template <> struct Bytes<2> { typedef uint16_t type; };
+template <> struct Bytes<1> { typedef uint8_t type; };
+
+// INT8 split: a fragment is 1 KB; the 256 threads of a block write 256 EPT
+// bytes of it, EPT bytes each (4 / EPT blocks per fragment): thread T of
+// part p covers fragment bytes [EPT T', EPT T' + EPT), T' = T + 256 p, i.e.
+// lane L = EPT T' / 16 (row L % 16) at depths 16 (L / 16) + (EPT T') % 16 + q.
+// With more words per entry, fewer entries per thread keep the decoded words
+// in registers.
+template <int MW, int EPT>
+__global__ __launch_bounds__(256) void k_split_i8(Operand op, const int32_t* E, int S,
+                                                  int64_t nkc, int8_t* out, int32_t* dbg)
 {
-    constexpr int beta = 7, D = 9, W = 63;
-    const int T = threadIdx.x;
-    const int64_t rb = blockIdx.y, kc = blockIdx.x;
-    const int L = T >> 2;                     // fragment lane
+    constexpr int beta = 7, D = 9, W = 63, parts = 4 / EPT;
+    typedef typename Bytes<EPT>::type Store;
+    const int64_t rb = blockIdx.y, kc = blockIdx.x / parts;
+    const int byte0 = EPT * ((int)threadIdx.x + 256 * (int)(blockIdx.x % parts));
+    const int L = byte0 >> 4;                 // fragment lane
     const int64_t r = rb * kRowBlock + (L & 15);
-    const int64_t kbase = kc * kKcI8 + 16 * (L >> 4) + 4 * (T & 3);
+    const int64_t kbase = kc * kKcI8 + 16 * (L >> 4) + (byte0 & 15);
     const bool row_ok = r < op.R;
     const int Er = row_ok ? E[r] : 0;
 
-    uint64_t mant[4][MW];
-    int sh0[4][MW];
-    bool neg[4][MW];
+    uint64_t mant[EPT][MW];
+    int sh0[EPT][MW];
+    bool neg[EPT][MW];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < EPT; ++q) {
         const int64_t k = kbase + q;
         const bool ok = row_ok && k < op.K;
 #pragma unroll
@@ -189,12 +200,12 @@ __global__ __launch_bounds__(256) void k_split_i8(Operand op, const int32_t* E, 
         }
     }
     const uint64_t wmask = (1ull << W) - 1;
-    uint32_t* o32 = reinterpret_cast<uint32_t*>(out) + ((rb * nkc + kc) * (int64_t)S) * 256 + T;
+    Store* o = reinterpret_cast<Store*>(out + ((rb * nkc + kc) * (int64_t)S) * 1024 + byte0);
     const int nl = (S + D - 1) / D;
     for (int j = 0; j < nl; ++j) {
-        uint64_t P[4], N[4];
+        uint64_t P[EPT], N[EPT];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < EPT; ++q)
             limb_pair<MW>(mant[q], sh0[q], neg[q], W * (j + 1), wmask, P[q], N[q]);
 #pragma unroll
         for (int i = 0; i < D; ++i) {
@@ -203,16 +214,16 @@ __global__ __launch_bounds__(256) void k_split_i8(Operand op, const int32_t* E, 
                 break;
             const int rs = W - beta * (i + 1);
             uint32_t packed = 0;
-            int dv[4];
+            int dv[EPT];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < EPT; ++q) {
                 dv[q] = (int)((P[q] >> rs) & 127) - (int)((N[q] >> rs) & 127);
                 packed |= ((uint32_t)(dv[q] & 0xff)) << (8 * q);
             }
-            o32[(int64_t)s * 256] = packed;
+            o[(int64_t)s * (1024 / EPT)] = (Store)packed;
             if (dbg && row_ok) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
+                for (int q = 0; q < EPT; ++q)
                     if (kbase + q < op.K)
                         dbg[((int64_t)s * op.R + r) * op.K + kbase + q] = dv[q];
             }
@@ -247,29 +258,59 @@ __global__ __launch_bounds__(256) void k_split_mag(Operand op, const int32_t* E,
     reinterpret_cast<uint32_t*>(out)[(rb * nkc + kc) * 256 + T] = packed;
 }
 
-// FP64 split: one wave writes one fragment (64 lanes x 4 doubles); lane l
-// holds row l%16, depth 4q + l/16.
-template <int MW>
+// Store of EPT consecutive digit doubles.
+template <int EPT> struct Doubles;
+template <> struct Doubles<4> { typedef double4 type; };
+template <> struct Doubles<2> { typedef double2 type; };
+template <> struct Doubles<1> { typedef double type; };
+
+template <int EPT>
+__device__ __forceinline__ typename Doubles<EPT>::type pack_doubles(const double (&v)[EPT]);
+template <>
+__device__ __forceinline__ double4 pack_doubles<4>(const double (&v)[4])
+{
+    return double4{v[0], v[1], v[2], v[3]};
+}
+template <>
+__device__ __forceinline__ double2 pack_doubles<2>(const double (&v)[2])
+{
+    return double2{v[0], v[1]};
+}
+template <>
+__device__ __forceinline__ double pack_doubles<1>(const double (&v)[1])
+{
+    return v[0];
+}
+
+// FP64 split: a fragment is 64 lanes x 4 doubles (lane l holds row l%16 at
+// depths 4q + l/16); a block of 256 threads writes EPT fragments, EPT
+// consecutive doubles per thread: thread u of a fragment covers doubles
+// [EPT u, EPT u + EPT), i.e. lane EPT u / 4, q from (EPT u) % 4.
+template <int MW, int EPT>
 __global__ __launch_bounds__(256) void k_split_f64(Operand op, const int32_t* E, int S, int beta,
                                                    int64_t nrb, int64_t nkc, double* out,
                                                    int32_t* dbg)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t frag = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    constexpr int TPF = 256 / EPT;            // threads per fragment
+    typedef typename Doubles<EPT>::type Store;
+    const int u = threadIdx.x % TPF;
+    const int64_t frag = (int64_t)blockIdx.x * EPT + threadIdx.x / TPF;
     if (frag >= nrb * nkc)
         return;
+    const int d0 = EPT * u;                   // first double of this thread
+    const int lane = d0 >> 2, q0 = d0 & 3;
     const int64_t rb = frag / nkc, kc = frag % nkc;
     const int64_t r = rb * kRowBlock + (lane & 15);
     const bool row_ok = r < op.R;
     const int Er = row_ok ? E[r] : 0;
     const int D = 63 / beta, W = D * beta;
 
-    uint64_t mant[4][MW];
-    int sh0[4][MW];
-    bool neg[4][MW];
+    uint64_t mant[EPT][MW];
+    int sh0[EPT][MW];
+    bool neg[EPT][MW];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int64_t k = kc * kKcF64 + 4 * q + (lane >> 4);
+    for (int q = 0; q < EPT; ++q) {
+        const int64_t k = kc * kKcF64 + 4 * (q0 + q) + (lane >> 4);
         const bool ok = row_ok && k < op.K;
 #pragma unroll
         for (int w = 0; w < MW; ++w) {
@@ -280,32 +321,27 @@ __global__ __launch_bounds__(256) void k_split_f64(Operand op, const int32_t* E,
         }
     }
     const uint64_t wmask = (1ull << W) - 1, dmask = (1ull << beta) - 1;
-    double* o = out + ((rb * nkc + kc) * (int64_t)S) * 256 + lane * 4;
+    Store* o = reinterpret_cast<Store*>(out + ((rb * nkc + kc) * (int64_t)S) * 256 + d0);
     const int nl = (S + D - 1) / D;
     for (int j = 0; j < nl; ++j) {
-        uint64_t P[4], N[4];
+        uint64_t P[EPT], N[EPT];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < EPT; ++q)
             limb_pair<MW>(mant[q], sh0[q], neg[q], W * (j + 1), wmask, P[q], N[q]);
         for (int i = 0; i < D; ++i) {
             const int s = D * j + i;
             if (s >= S)
                 break;
             const int rs = W - beta * (i + 1);
-            double dv[4];
+            double dv[EPT];
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < EPT; ++q)
                 dv[q] = (double)((int64_t)((P[q] >> rs) & dmask) - (int64_t)((N[q] >> rs) & dmask));
-            double4 v;
-            v.x = dv[0];
-            v.y = dv[1];
-            v.z = dv[2];
-            v.w = dv[3];
-            *reinterpret_cast<double4*>(o + (int64_t)s * 256) = v;
+            o[(int64_t)s * TPF] = pack_doubles<EPT>(dv);
             if (dbg && row_ok) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int64_t k = kc * kKcF64 + 4 * q + (lane >> 4);
+                for (int q = 0; q < EPT; ++q) {
+                    const int64_t k = kc * kKcF64 + 4 * (q0 + q) + (lane >> 4);
                     if (k < op.K)
                         dbg[((int64_t)s * op.R + r) * op.K + k] = (int32_t)dv[q];
                 }
@@ -351,19 +387,30 @@ hipError_t launch_exp_final(const int32_t* hi, const int32_t* lo, int64_t R, int
     return hipGetLastError();
 }
 
+// Entries per thread of the splits: fewer when an entry has more words.
+constexpr int split_ept(int m) { return m <= 4 ? 4 : (m == 8 ? 2 : 1); }
+
+template <int MW>
+hipError_t split_i8_m(const Operand& op, const int32_t* E, int S, int64_t nrb, int64_t nkc,
+                      int8_t* out, int32_t* dbg, hipStream_t st)
+{
+    constexpr int EPT = split_ept(MW);
+    hipLaunchKernelGGL((k_split_i8<MW, EPT>), dim3((unsigned)(nkc * (4 / EPT)), (unsigned)nrb),
+                       dim3(256), 0, st, op, E, S, nkc, out, dbg);
+    return hipGetLastError();
+}
+
 hipError_t launch_split_i8(const Operand& op, int m, const int32_t* E, int S, int64_t nrb,
                            int64_t nkc, int8_t* out, int32_t* dbg, hipStream_t st)
 {
-    dim3 grid((unsigned)nkc, (unsigned)nrb);
     switch (m) {
-    case 1: hipLaunchKernelGGL(k_split_i8<1>, grid, dim3(256), 0, st, op, E, S, nkc, out, dbg); break;
-    case 2: hipLaunchKernelGGL(k_split_i8<2>, grid, dim3(256), 0, st, op, E, S, nkc, out, dbg); break;
-    case 4: hipLaunchKernelGGL(k_split_i8<4>, grid, dim3(256), 0, st, op, E, S, nkc, out, dbg); break;
-    case 8: hipLaunchKernelGGL(k_split_i8<8>, grid, dim3(256), 0, st, op, E, S, nkc, out, dbg); break;
-    case 16: hipLaunchKernelGGL(k_split_i8<16>, grid, dim3(256), 0, st, op, E, S, nkc, out, dbg); break;
+    case 1: return split_i8_m<1>(op, E, S, nrb, nkc, out, dbg, st);
+    case 2: return split_i8_m<2>(op, E, S, nrb, nkc, out, dbg, st);
+    case 4: return split_i8_m<4>(op, E, S, nrb, nkc, out, dbg, st);
+    case 8: return split_i8_m<8>(op, E, S, nrb, nkc, out, dbg, st);
+    case 16: return split_i8_m<16>(op, E, S, nrb, nkc, out, dbg, st);
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_split_mag(const Operand& op, const int32_t* E, int64_t nrb, int64_t nkc,
@@ -374,20 +421,28 @@ hipError_t launch_split_mag(const Operand& op, const int32_t* E, int64_t nrb, in
     return hipGetLastError();
 }
 
+template <int MW>
+hipError_t split_f64_m(const Operand& op, const int32_t* E, int S, int beta, int64_t nrb,
+                       int64_t nkc, double* out, int32_t* dbg, hipStream_t st)
+{
+    constexpr int EPT = split_ept(MW);
+    const int64_t blocks = (nrb * nkc + EPT - 1) / EPT;
+    hipLaunchKernelGGL((k_split_f64<MW, EPT>), dim3((unsigned)blocks), dim3(256), 0, st, op, E, S,
+                       beta, nrb, nkc, out, dbg);
+    return hipGetLastError();
+}
+
 hipError_t launch_split_f64(const Operand& op, int m, const int32_t* E, int S, int beta,
                             int64_t nrb, int64_t nkc, double* out, int32_t* dbg, hipStream_t st)
 {
-    const int64_t blocks = (nrb * nkc + 3) / 4;
-    dim3 grid((unsigned)blocks);
     switch (m) {
-    case 1: hipLaunchKernelGGL(k_split_f64<1>, grid, dim3(256), 0, st, op, E, S, beta, nrb, nkc, out, dbg); break;
-    case 2: hipLaunchKernelGGL(k_split_f64<2>, grid, dim3(256), 0, st, op, E, S, beta, nrb, nkc, out, dbg); break;
-    case 4: hipLaunchKernelGGL(k_split_f64<4>, grid, dim3(256), 0, st, op, E, S, beta, nrb, nkc, out, dbg); break;
-    case 8: hipLaunchKernelGGL(k_split_f64<8>, grid, dim3(256), 0, st, op, E, S, beta, nrb, nkc, out, dbg); break;
-    case 16: hipLaunchKernelGGL(k_split_f64<16>, grid, dim3(256), 0, st, op, E, S, beta, nrb, nkc, out, dbg); break;
+    case 1: return split_f64_m<1>(op, E, S, beta, nrb, nkc, out, dbg, st);
+    case 2: return split_f64_m<2>(op, E, S, beta, nrb, nkc, out, dbg, st);
+    case 4: return split_f64_m<4>(op, E, S, beta, nrb, nkc, out, dbg, st);
+    case 8: return split_f64_m<8>(op, E, S, beta, nrb, nkc, out, dbg, st);
+    case 16: return split_f64_m<16>(op, E, S, beta, nrb, nkc, out, dbg, st);
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 }  // namespace mdg

@@ -30,6 +30,7 @@
 #include "renorm.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace mdg {
 namespace {
@@ -68,6 +69,26 @@ struct FormF64 {
     static __device__ __forceinline__ int64_t value(const acc& c, int o) { return (int64_t)c[o]; }
     // accumulator element o of lane l is row 4 o + l/16, column l%16
     static __device__ __forceinline__ int row(int lane, int o) { return 4 * o + (lane >> 4); }
+};
+
+// FP64 digits multiplied lane by lane on the vector units: lane l's four
+// doubles of an A fragment and of a B fragment sit at the same row l%16 and
+// depths, so for the batched inner products (row block of X against the same
+// row block of Y) the lane-wise products are exactly the pair products, with
+// none of the 16 x 16 tile's off-diagonal work.  The accumulator is one
+// double per lane and diagonal; exact while the sums stay below 2^53.
+struct FormF64Lane {
+    typedef v4d frag;
+    typedef double acc;
+    static constexpr bool kPipelined = false;
+    static __device__ __forceinline__ acc mma(const frag& a, const frag& b, acc c)
+    {
+        c = __builtin_fma(a[0], b[0], c);
+        c = __builtin_fma(a[1], b[1], c);
+        c = __builtin_fma(a[2], b[2], c);
+        return __builtin_fma(a[3], b[3], c);
+    }
+    static __device__ __forceinline__ acc zero() { return 0.0; }
 };
 
 // One depth chunk of one band: diagonals t0..t0+G-1, t0 a multiple of G.
@@ -921,10 +942,26 @@ __global__ __launch_bounds__(64) void k_dot_band(DotArgs a)
 #pragma unroll
     for (int g = 0; g < G; ++g)
         acc[g] = Form::zero();
-    for (int64_t kc = c0; kc < c1; ++kc)
-        band_chunk<Form, G>(acc, Xb + kc * fstride, Yb + kc * fstride, t0);
+    if constexpr (Form::kPipelined && G > 3) {
+        if (c1 > c0)
+            band_run<Form, G, 3>(acc, Xb, Yb, fstride, c0, c1, t0);
+    } else {
+        for (int64_t kc = c0; kc < c1; ++kc)
+            band_chunk<Form, G>(acc, Xb + kc * fstride, Yb + kc * fstride, t0);
+    }
     const int64_t b = rb * 16 + (lane & 15);
-    if (b < a.batch) {
+    if constexpr (std::is_same<Form, FormF64Lane>::value) {
+        // lanes l, l+16, l+32, l+48 hold the four depth quarters of pair l%16
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            double v = acc[g];
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            if (lane < 16 && b < a.batch)
+                atomicAdd(reinterpret_cast<unsigned long long*>(a.D + (int64_t)(t0 + g) * a.batch + b),
+                          (unsigned long long)(int64_t)v);
+        }
+    } else if (b < a.batch) {
 #pragma unroll
         for (int g = 0; g < G; ++g)
 #pragma unroll
@@ -1054,7 +1091,7 @@ hipError_t launch_dot_diag(const DotArgs& a, int form_int8, hipStream_t st)
 {
     if (form_int8)
         return DispatchDot<FormI8, kTriMaxI8>::run(a, st);
-    return DispatchDot<FormF64, kGmaxF64>::run(a, st);
+    return DispatchDot<FormF64Lane, kGmaxF64>::run(a, st);
 }
 
 hipError_t launch_fill_zero_i64(int64_t* p, int64_t n, hipStream_t st)
