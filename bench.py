@@ -33,7 +33,8 @@ PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 matrix peak, TFLOP/s
 
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_tri2_i8_qd4096_traffic.md")
-KERNEL_SOURCES = ("csrc/slice_gemm.hip", "csrc/renorm.h", "csrc/mdgemm_internal.h", "build.py")
+KERNEL_SOURCES = ("csrc/tri.h", "csrc/slice_common.h", "csrc/renorm.h", "csrc/mdgemm_internal.h",
+                  "csrc/tri_s29_32.hip", "build.py")
 
 
 def kernel_fingerprint():

@@ -76,6 +76,10 @@ hipError_t launch_gemm_i8(const GemmArgs& a, hipStream_t st);
 hipError_t launch_mag_min(const void* qA, const void* qB, int64_t M, int64_t N, int64_t nkc,
                           unsigned long long* minP, hipStream_t st);
 hipError_t launch_gemm_f64(const GemmArgs& a, hipStream_t st);
+// whole-triangle INT8 kernels, by range of S (one translation unit each)
+hipError_t launch_tri_s1_22(const GemmArgs& a, hipStream_t st);
+hipError_t launch_tri_s23_28(const GemmArgs& a, hipStream_t st);
+hipError_t launch_tri_s29_32(const GemmArgs& a, hipStream_t st);
 
 // Batched inner products out_b = sum_k x_bk y_bk: both operands are split
 // with the vectors as rows (fragment layout of op(A)), so block rb of 16

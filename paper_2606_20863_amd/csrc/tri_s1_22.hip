@@ -1,0 +1,11 @@
+// Whole-triangle INT8 slice contraction kernels for S = 1..22.
+#include "tri.h"
+
+namespace mdg {
+
+hipError_t launch_tri_s1_22(const GemmArgs& a, hipStream_t st)
+{
+    return DispatchTriRange<22, 1>::run(a, st);
+}
+
+}  // namespace mdg
