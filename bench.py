@@ -14,6 +14,11 @@ its algorithmic work per launch is 2 M N K S(S+1)/2 int8 operations (S(S+1)/2
 slice multiply-adds per m-double multiply-add), timed with HIP events on the
 call's stream around that kernel.  cpu_baseline: the exact C oracle on this
 host's cores over a bounded sample of output entries.
+
+paper_inner_products (skip with --no-dot): the paper's own experiment
+(Section 3, Table 2), 1,024 m-double inner products of length 6,144 on its
+bit pattern for m = 1, 2, 4, 8, 16, through the batched inner-product entry
+point in both slice forms and with the paper's parameters.
 """
 from __future__ import annotations
 
@@ -131,6 +136,61 @@ def accuracy_sample(A, B, C, n=8):
     return float(np.log2(max(rel.max(), 2.0 ** -1074)))
 
 
+# Table 2 of the paper: one CPU core, 1,024 inner products of length 6,144,
+# milliseconds ("vectorized" is the error-free method, "ordinary" classical
+# m-double arithmetic).  Context only: other hardware, other parameters.
+PAPER_TABLE2_MS = {1: (12, 30), 2: (158, 69), 4: (1977, 318), 8: (6428, 1520), 16: (40780, 9491)}
+
+
+def paper_inner_products(md, torch, steps=5):
+    """The paper's experiment on the GPU: 1,024 inner products of length
+    6,144 on the bit pattern, m = 1, 2, 4, 8, 16, through md_dot_ex in the
+    INT8 form and the FP64 form (the library's slice rule) and with the
+    paper's own parameters (FP64 form, beta = 13, S = 4m).  Whole-call
+    milliseconds (inputs resident), the contraction and fold alone from HIP
+    events, and the largest error over 8 sampled pairs against the exact
+    products (C oracle) relative to sum |x||y|."""
+    import numpy as np
+    import mdinputs
+    from oracle import coracle
+    X16, Y16 = mdinputs.paper_dot_workload(16)
+    hip, _ = hip_events(1)
+    pairs = np.linspace(0, X16.shape[1] - 1, 8).astype(np.int64)
+    idx = np.arange(len(pairs), dtype=np.int64)
+    rows = {}
+    for m in mdinputs.PAPER_DOT["m"]:
+        X = torch.from_numpy(np.ascontiguousarray(X16[:m])).cuda()
+        Y = torch.from_numpy(np.ascontiguousarray(Y16[:m])).cuda()
+        Xs = np.ascontiguousarray(X16[:m, pairs, :])
+        Ys = np.ascontiguousarray(np.transpose(Y16[:m, pairs, :], (0, 2, 1)))
+        row = {"paper_cpu_ms_ordinary": PAPER_TABLE2_MS[m][0],
+               "paper_cpu_ms_vectorized": PAPER_TABLE2_MS[m][1]}
+        for label, kw in (("int8", dict(form="int8")), ("fp64", dict(form="fp64")),
+                          ("fp64_paper_params", dict(form="fp64", force_S=4 * m, force_beta=13))):
+            md.dot_ex(X, Y, **kw)
+            torch.cuda.synchronize()
+            _, evs = hip_events(steps)
+            t0 = time.perf_counter()
+            for e in evs:
+                out, info = md.dot_ex(X, Y, events=e, **kw)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / steps
+            kern = sum(elapsed_ms(hip, e) for e in evs) / steps
+            for a, b in evs:
+                hip.hipEventDestroy(ctypes.c_void_p(a))
+                hip.hipEventDestroy(ctypes.c_void_p(b))
+            Cq = np.ascontiguousarray(out.cpu().numpy()[:, pairs].T)
+            _, absab, err = coracle.exact_entries(Xs, Ys, idx, idx, Cq)
+            rel = float(np.log2(max((np.abs(err) / absab).max(), 2.0 ** -1074)))
+            row[label] = {"S": info["S"], "beta": info["beta"], "ms_per_call": round(ms, 4),
+                          "contraction_fold_ms": round(kern, 4), "max_log2_err_sampled": round(rel, 2)}
+        rows[f"m{m}"] = row
+        del X, Y
+    return {"workload": "1024 inner products of length 6144, the paper's bit pattern (Section 2), "
+                        "m-double inputs, one md_dot_ex call each",
+            "target_bits": "50 m", "results": rows}
+
+
 def cpu_baseline(A, B, K):
     """The exact C oracle on whole output rows of the same product."""
     import numpy as np
@@ -156,6 +216,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-dot", action="store_true",
+                    help="skip the paper's inner-product workload (m = 1..16)")
     ap.add_argument("--forms", default="int8,fp64",
                     help="slice forms to run (int8 is the headline; fp64 runs beside it)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -249,6 +311,10 @@ def main():
                      "work_per_launch": f"2*M*N*K*S(S+1)/2 = {ops8:.4e} int8 ops (unit: int8 TOP/s)",
                      "algorithmic_bytes_per_launch": int(2 * S8 * M * K + 8 * m * M * N)},
     }
+    if not args.no_dot:
+        del A, B, C8, C64
+        torch.cuda.empty_cache()
+        out["paper_inner_products"] = paper_inner_products(md, torch)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(Ah, Bh, K)
     print(json.dumps(out))

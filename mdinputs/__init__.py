@@ -138,3 +138,21 @@ def paper_pattern(rng: np.random.Generator, m: int, shape):
         # the word is mant * 2^-51 * 2^(-52 w).
         planes[w] = signs[w] * np.ldexp(mant.astype(np.float64), -51 - 52 * w)
     return planes, groups, signs
+
+
+# The paper's experiment (Section 3, Table 2): 1,024 inner products of
+# vectors of length 6,144 in the bit pattern, m = 1, 2, 4, 8, 16.
+PAPER_DOT = {"index": 5, "batch": 1024, "n": 6144, "m": (1, 2, 4, 8, 16)}
+
+
+def paper_dot_workload(m: int = 16, batch=None, n=None):
+    """(X, Y), each (m, batch, n) planes in the paper's bit pattern, from
+    the seeded streams of the inner-product workload.  The first w words of
+    an m-word pattern entry are a w-word pattern entry, so one draw at
+    m = 16 serves every smaller m by slicing."""
+    batch = PAPER_DOT["batch"] if batch is None else batch
+    n = PAPER_DOT["n"] if n is None else n
+    rx, ry, _ = seeds(PAPER_DOT["index"])
+    X, _, _ = paper_pattern(rx, m, (batch, n))
+    Y, _, _ = paper_pattern(ry, m, (batch, n))
+    return X, Y
