@@ -128,6 +128,30 @@ def test_rule_and_bound_small(form, name, rule):
             assert ox.is_nonoverlapping(C[:, i, j], strong=True)
 
 
+@pytest.mark.parametrize("S", range(1, 33))
+def test_triangle_kernel_every_S_one_chunk(S):
+    """Every whole-triangle instantiation with two row blocks per wave
+    (forced S, beta = 7, no debug dump, depth within one exactness chunk);
+    M = 70 leaves a row block past the padded digit array."""
+    A, B = mdinputs.workload("qd1024", M=70, N=33, K=100)
+    C, info = md.gemm_ex(dev(A), dev(B), form="int8", force_S=S, force_beta=7)
+    assert info["kc"] >= 100
+    np.testing.assert_array_equal(host(C), ox.method_product(A, B, 7, S)["C"])
+
+
+@pytest.mark.parametrize("S", range(1, 33))
+def test_triangle_kernel_every_S_several_chunks(S):
+    """Every one-row-block triangle instantiation without the debug dump:
+    the depth exceeds one exactness chunk (S K 127^2 >= 2^31), so the
+    register fold carries between chunks."""
+    kc = ox.chunk_depth(S, 7, 1 << 30, 1 << 31, ox.INT8_KGRAN)
+    K = kc + 81
+    A, B = mdinputs.workload("dd64", M=17, N=19, K=K)
+    C, info = md.gemm_ex(dev(A), dev(B), form="int8", force_S=S, force_beta=7)
+    assert info["kc"] == kc < K
+    np.testing.assert_array_equal(host(C), ox.method_product(A, B, 7, S)["C"])
+
+
 def test_rho_certificate_falls_back_to_span():
     """A zero magnitude product (disjoint supports) leaves only the span
     certificate; the product is then exactly zero where it must be."""
