@@ -88,6 +88,8 @@ def lib():
     L.md_dot_ex.restype = i32
     L.md_dot.argtypes = [i32, i64, i64, p, p, p, p]
     L.md_dot.restype = i32
+    L.md_gemm_ordinary.argtypes = [i32, i64, i64, i64, p, p, p, p]
+    L.md_gemm_ordinary.restype = i32
     L.md_choose_params.argtypes = [i32, i64, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                    ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.md_choose_params.restype = i32
@@ -247,6 +249,22 @@ def dot(X: torch.Tensor, Y: torch.Tensor, form: str = "fp64", stream=None) -> to
     return dot_ex(X, Y, form=form, stream=stream)[0]
 
 
+def gemm_ordinary(A: torch.Tensor, B: torch.Tensor, stream=None) -> torch.Tensor:
+    """C = A B in ordinary m-double arithmetic (m = 2, 4), every operation
+    renormalised: the comparison baseline, not error-free."""
+    _check_planes(A, "A")
+    _check_planes(B, "B")
+    A = A.contiguous()
+    B = B.contiguous()
+    m, M, K = A.shape
+    N = B.shape[2]
+    if B.shape[:2] != (m, K):
+        raise ValueError("shape mismatch")
+    C = torch.empty((m, M, N), dtype=torch.float64, device=A.device)
+    _check(lib().md_gemm_ordinary(m, M, N, K, _ptr(A), _ptr(B), _ptr(C), _stream_handle(stream)))
+    return C
+
+
 class MDGemm(torch.autograd.Function):
     """C = A B with the hand-written m-double adjoint.
 
@@ -272,5 +290,5 @@ class MDGemm(torch.autograd.Function):
         return dA, dB, None
 
 
-__all__ = ["gemm", "gemm_ex", "dot", "dot_ex", "MDGemm", "choose_params", "lib", "MDError",
-           "MDInfo"]
+__all__ = ["gemm", "gemm_ex", "gemm_ordinary", "dot", "dot_ex", "MDGemm", "choose_params", "lib",
+           "MDError", "MDInfo"]

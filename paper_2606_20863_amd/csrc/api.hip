@@ -715,6 +715,30 @@ int md_dot(int m, int64_t batch, int64_t n, const double* X, const double* Y, do
     return md_dot_ex(m, batch, n, X, n, batch * n, Y, n, batch * n, out, batch, nullptr, stream);
 }
 
+int md_gemm_ordinary(int m, int64_t M, int64_t N, int64_t K, const double* A, const double* B,
+                     double* C, void* stream)
+{
+    g_last_hip = 0;
+    if (m != 2 && m != 4)
+        return MD_EINVAL_M;
+    if (M < 0 || N < 0 || K < 0)
+        return MD_EINVAL_DIM;
+    if (M == 0 || N == 0)
+        return MD_OK;
+    if (!C || (K > 0 && (!A || !B)))
+        return MD_ENULL;
+    if (!mul_ok(M, N) || !mul_ok(M, std::max<int64_t>(K, 1)) || !mul_ok(K, N) ||
+        M > (INT64_C(1) << 40) || N > (INT64_C(1) << 40) || K > (INT64_C(1) << 40) ||
+        ((M + 15) / 16) * ((N + 15) / 16) > (INT64_C(1) << 24))   // grid of 256-thread tiles
+        return MD_EINVAL_DIM;
+    const Span sc = extent(C, m, M, N, N, 1, M * N);
+    if (K > 0 && (overlap(sc, extent(A, m, M, K, K, 1, M * K)) || overlap(sc, extent(B, m, K, N, N, 1, K * N))))
+        return MD_EALIAS;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = K == 0 ? launch_fill_zero(C, m, M, N, N, M * N, st) : launch_ordinary(m, A, B, C, M, N, K, st);
+    return e == hipSuccess ? MD_OK : hip_fail(e);
+}
+
 int md_gemm(int m, int64_t M, int64_t N, int64_t K, const double* A, const double* B, double* C,
             void* stream)
 {

@@ -100,6 +100,9 @@ hipError_t launch_fill_zero_i64(int64_t* p, int64_t n, hipStream_t st);
 hipError_t launch_dot_final(const int64_t* D, const int32_t* E, const int32_t* F, int64_t batch,
                             int S, int beta, int ncol, int m, double* out, int64_t pso,
                             hipStream_t st);
+// ordinary m-double product (m = 2, 4) of dense planes
+hipError_t launch_ordinary(int m, const double* A, const double* B, double* C, int64_t M,
+                           int64_t N, int64_t K, hipStream_t st);
 // min over pairs of sum_k qX_bk qY_bk into *minP (atomic min)
 hipError_t launch_mag_min_diag(const void* qX, const void* qY, int64_t batch, int64_t nkc,
                                unsigned long long* minP, hipStream_t st);
