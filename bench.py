@@ -15,6 +15,10 @@ slice multiply-adds per m-double multiply-add), timed with HIP events on the
 call's stream around that kernel.  cpu_baseline: the exact C oracle on this
 host's cores over a bounded sample of output entries.
 
+ordinary_form: the same product in classical quad-double arithmetic (every
+operation renormalised; the paper's comparison baseline), its time, error
+and the INT8 form's speedup over it.
+
 paper_inner_products (skip with --no-dot): the paper's own experiment
 (Section 3, Table 2), 1,024 m-double inner products of length 6,144 on its
 bit pattern for m = 1, 2, 4, 8, 16, through the batched inner-product entry
@@ -215,6 +219,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--ordinary-steps", type=int, default=1,
+                    help="timed calls of the ordinary quad-double product (0 skips it)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-dot", action="store_true",
                     help="skip the paper's inner-product workload (m = 1..16)")
@@ -257,6 +263,20 @@ def main():
         print(json.dumps(out))
         return
     C64, info64, ms64, kern64 = run_form(md, torch, A, B, "fp64", args.fp64_steps, 1)
+
+    # the ordinary (classical) quad-double product on the same inputs, the
+    # paper's comparison baseline; one warm-up and args.ordinary_steps timed
+    ord_ms = None
+    if args.ordinary_steps > 0:
+        Co = md.gemm_ordinary(A, B)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.ordinary_steps):
+            Co = md.gemm_ordinary(A, B)
+        torch.cuda.synchronize()
+        ord_ms = (time.perf_counter() - t0) * 1e3 / args.ordinary_steps
+        Coh = Co.cpu().numpy()
+        del Co
 
     flop = 2.0 * M * N * K
     eff8 = flop / (ms8 * 1e-3) / 1e9
@@ -305,6 +325,12 @@ def main():
                       "max_log2_err_sampled": round(err64, 2),
                       "certified_log2_bound": round(info64["log2_bound"], 2)},
         "int8_over_fp64": round(eff8 / eff64, 3),
+        "ordinary_form": None if ord_ms is None else {
+            "arithmetic": "classical quad-double, every multiply and add renormalised (md_gemm_ordinary)",
+            "steps": args.ordinary_steps, "ms_per_call": round(ord_ms, 3),
+            "effective_gflops": round(flop / (ord_ms * 1e-3) / 1e9, 3),
+            "max_log2_err_sampled": round(accuracy_sample(Ah, Bh, Coh), 2),
+            "int8_form_speedup": round(ord_ms / ms8, 2)},
         "roofline": {"bound": "mfma", "kernel": kname8,
                      "achieved": round(ach8, 3), "peak": PEAK_INT8_TOPS, "unit": "TFLOP/s",
                      "frac": round(ach8 / PEAK_INT8_TOPS, 4), "traffic": traffic8,
