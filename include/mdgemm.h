@@ -116,7 +116,7 @@ typedef struct md_opts {
 
 /*
  * C = A B for m-double matrices, the plain FP64-slice form.
- *   m: words per entry, 2, 4 or 8.
+ *   m: words per entry, 1, 2, 4, 8 or 16.
  *   A: m planes of M x K, row-major, dense (lda = K, plane stride M K).
  *   B: m planes of K x N, row-major, dense.
  *   C: m planes of M x N, row-major, dense; fully overwritten; must not

@@ -106,6 +106,15 @@ int fold_columns(int beta, int S, int64_t Kp)
 
 int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 
+// The banded contraction's LDS fold (4 waves x ncol x 256 int64) exceeds the
+// 160 KB of LDS; the whole-triangle INT8 kernels never need it.
+bool needs_global_fold(int form, int band, int S, int ncol)
+{
+    if (form == MD_FORM_INT8 && band == S && S <= kTriMaxI8)
+        return false;
+    return (size_t)4 * ncol * 256 * sizeof(int64_t) > 160 * 1024;
+}
+
 // Magnitude certificate.  With q = floor(|a^(0)| 2^(7-E_i)) and strongly
 // nonoverlapping words, |a_ik||b_kj| >= (1 - 2^-51) 2^(E_i+F_j-14) qA_ik qB_kj,
 // so N_ij 2^(E_i+F_j) / (|A||B|)_ij <= K 2^14 / ((1 - 2^-51) minP).  Returns the
@@ -265,8 +274,16 @@ int md_choose_params(int form, int64_t K, int T, int G, int* beta, int* S, int* 
 
 size_t md_workspace_size(int form, int64_t M, int64_t N, int64_t K, int S)
 {
-    return small_bytes(M, N) + digits_bytes(MD_FORM_INT8, M, K, 1) + digits_bytes(MD_FORM_INT8, N, K, 1) +
-           digits_bytes(form, M, K, S) + digits_bytes(form, N, K, S) + 4096;
+    size_t bytes = small_bytes(M, N) + digits_bytes(MD_FORM_INT8, M, K, 1) +
+                   digits_bytes(MD_FORM_INT8, N, K, 1) + digits_bytes(form, M, K, S) +
+                   digits_bytes(form, N, K, S) + 4096;
+    // the diagonal-sum buffer where the LDS fold does not fit (widest FP64
+    // digits as the bound)
+    const int kcg = form == MD_FORM_INT8 ? kKcI8 : kKcF64;
+    const int ncol = fold_columns(form == MD_FORM_INT8 ? 7 : 24, S, round_up(std::max<int64_t>(K, 1), kcg));
+    if (!(form == MD_FORM_INT8 && S <= kTriMaxI8) && (size_t)4 * ncol * 256 * sizeof(int64_t) > 160 * 1024)
+        bytes += (size_t)S * M * N * sizeof(int64_t) + 256;
+    return bytes;
 }
 
 int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, const double* A,
@@ -275,7 +292,7 @@ int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, c
                const md_opts* opts, void* stream)
 {
     g_last_hip = 0;
-    if (m != 2 && m != 4 && m != 8)
+    if (m != 1 && m != 2 && m != 4 && m != 8 && m != 16)
         return MD_EINVAL_M;
     if (M < 0 || N < 0 || K < 0)
         return MD_EINVAL_DIM;
@@ -419,7 +436,12 @@ int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, c
     const int64_t nkc = (K + kcg - 1) / kcg;
     const int64_t Mp = round_up(M, kTile), Np = round_up(N, kTile);
     const int ncol = fold_columns(beta, S, nkc * kcg);
-    if ((size_t)4 * ncol * 256 * sizeof(int64_t) > 160 * 1024)
+    // the banded kernels fold in LDS when 4 waves' columns fit, else they
+    // add their diagonal sums into a [S][M][N] buffer that a second kernel
+    // folds and rounds (one entry per thread); the whole-triangle INT8
+    // kernels fold in registers
+    const bool global_fold = needs_global_fold(o.form, band, S, ncol);
+    if ((size_t)ncol * 256 * sizeof(int64_t) > 160 * 1024)
         return MD_ERANGE;
 
     void *dA, *dB;
@@ -445,6 +467,19 @@ int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, c
         if ((e = launch_fill_zero((double*)dbg->D, S, M, N, N, M * N, st)) != hipSuccess)
             return hip_fail(e);
     }
+    int64_t* gD = nullptr;
+    if (global_fold) {
+        if (dbg && dbg->D) {
+            gD = dbg->D;   // the debug dump is the same [S][M][N] sums
+        } else {
+            void* p;
+            if (!mul_ok((int64_t)S * M, N) || (rc = scr.get((size_t)S * M * N * sizeof(int64_t), &p)))
+                return rc ? rc : MD_ENOMEM;
+            gD = (int64_t*)p;
+            if ((e = launch_fill_zero_i64(gD, (int64_t)S * M * N, st)) != hipSuccess)
+                return hip_fail(e);
+        }
+    }
     GemmArgs ga;
     ga.A = dA;
     ga.B = dB;
@@ -463,11 +498,14 @@ int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, c
     ga.nbands = S / band;
     ga.m = m;
     ga.ncol = ncol;
-    ga.dbgD = dbg ? dbg->D : nullptr;
+    ga.dbgD = global_fold ? nullptr : (dbg ? dbg->D : nullptr);
+    ga.gD = gD;
     if (o.ev_gemm_begin && (e = hipEventRecord((hipEvent_t)o.ev_gemm_begin, st)) != hipSuccess)
         return hip_fail(e);
     e = o.form == MD_FORM_INT8 ? launch_gemm_i8(ga, st) : launch_gemm_f64(ga, st);
     if (e != hipSuccess)
+        return hip_fail(e);
+    if (global_fold && (e = launch_gemm_final(ga, st)) != hipSuccess)
         return hip_fail(e);
     if (o.ev_gemm_end && (e = hipEventRecord((hipEvent_t)o.ev_gemm_end, st)) != hipSuccess)
         return hip_fail(e);

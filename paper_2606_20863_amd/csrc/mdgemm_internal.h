@@ -51,6 +51,10 @@ struct GemmArgs {
     int S, beta, band, nbands, m;
     int ncol;               // 32-bit columns of the exact fold accumulator
     int64_t* dbgD;          // optional [S][M][N]
+    // [S][M][N], zeroed: when set, the banded kernels add their diagonal
+    // sums here instead of folding in LDS (the fold would not fit), and
+    // launch_gemm_final folds and rounds afterwards
+    int64_t* gD;
 };
 
 hipError_t launch_fill_zero(double* C, int m, int64_t M, int64_t N, int64_t ldc, int64_t psc,
@@ -76,6 +80,8 @@ hipError_t launch_gemm_i8(const GemmArgs& a, hipStream_t st);
 hipError_t launch_mag_min(const void* qA, const void* qB, int64_t M, int64_t N, int64_t nkc,
                           unsigned long long* minP, hipStream_t st);
 hipError_t launch_gemm_f64(const GemmArgs& a, hipStream_t st);
+// exact fold and rounding of every output from a.gD (one thread per entry)
+hipError_t launch_gemm_final(const GemmArgs& a, hipStream_t st);
 // whole-triangle INT8 kernels, by range of S (one translation unit each)
 hipError_t launch_tri_s1_22(const GemmArgs& a, hipStream_t st);
 hipError_t launch_tri_s23_28(const GemmArgs& a, hipStream_t st);

@@ -443,8 +443,10 @@ struct WaveTile {
 
 // Exact fold of one depth chunk's diagonal sums t0 .. t0+G-1.  DBG kernels
 // also add them into the debug buffer (a separate instantiation, so that the
-// production kernels carry no debug addressing).
-template <class Form, int G, bool DBG>
+// production kernels carry no debug addressing).  GLOBAL kernels only add
+// them into a.gD (every output belongs to one lane of one wave, so the
+// read-modify-writes do not race) and keep no LDS fold.
+template <class Form, int G, bool DBG, bool GLOBAL = false>
 __device__ __forceinline__ void fold_chunk(const typename Form::acc (&acc)[G], int t0,
                                            const GemmArgs& a, const WaveTile& w)
 {
@@ -455,11 +457,13 @@ __device__ __forceinline__ void fold_chunk(const typename Form::acc (&acc)[G], i
 #pragma unroll
         for (int o = 0; o < 4; ++o) {
             const int64_t v = Form::value(acc[g], o);
-            fold_add(w.cols, o, v, p);
-            if constexpr (DBG) {
+            if constexpr (!GLOBAL)
+                fold_add(w.cols, o, v, p);
+            if constexpr (DBG || GLOBAL) {
+                int64_t* D = GLOBAL ? a.gD : a.dbgD;
                 const int64_t i = w.rb * 16 + Form::row(w.lane, o), j = w.cb * 16 + (w.lane & 15);
                 if (i < a.M && j < a.N)
-                    a.dbgD[((int64_t)t * a.M + i) * a.N + j] += v;
+                    D[((int64_t)t * a.M + i) * a.N + j] += v;
             }
         }
     }

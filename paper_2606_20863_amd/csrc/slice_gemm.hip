@@ -6,15 +6,17 @@
 namespace mdg {
 namespace {
 
-// Banded contraction: S = nbands * G diagonals, G at a time.
-template <class Form, int G, bool DBG>
+// Banded contraction: S = nbands * G diagonals, G at a time.  GLOBAL: the
+// diagonal sums go to a.gD and launch_gemm_final rounds them.
+template <class Form, int G, bool DBG, bool GLOBAL>
 __global__ __launch_bounds__(256, 1) void k_slice_gemm(GemmArgs a)
 {
     typedef typename Form::frag Frag;
     typedef typename Form::acc Acc;
     extern __shared__ int64_t lds[];
     WaveTile w(a, 1);
-    w.init_cols(a, lds);
+    if constexpr (!GLOBAL)
+        w.init_cols(a, lds);
     const int64_t fstride = (int64_t)a.S * 64;   // fragments of one depth chunk
     const Frag* Ab = (const Frag*)a.A + w.rb * a.nkc * fstride + w.lane;
     const Frag* Bb = (const Frag*)a.B + w.cb * a.nkc * fstride + w.lane;
@@ -33,19 +35,43 @@ __global__ __launch_bounds__(256, 1) void k_slice_gemm(GemmArgs a)
                 for (int64_t kc = c0; kc < c1; ++kc)
                     band_chunk<Form, G>(acc, Ab + kc * fstride, Bb + kc * fstride, t0);
             }
-            fold_chunk<Form, G, DBG>(acc, t0, a, w);
+            fold_chunk<Form, G, DBG, GLOBAL>(acc, t0, a, w);
         }
     }
-    write_outputs<Form>(a, w);
+    if constexpr (!GLOBAL)
+        write_outputs<Form>(a, w);
+}
+
+// Fold and round every output from the diagonal sums in a.gD: one thread per
+// entry, its fold columns in LDS (ncol x 256).
+__global__ __launch_bounds__(256) void k_gemm_final(GemmArgs a)
+{
+    extern __shared__ int64_t lds[];
+    const int t = threadIdx.x;
+    const int64_t e = (int64_t)blockIdx.x * 256 + t;
+    const int64_t MN = a.M * a.N;
+    const bool ok = e < MN;
+    const int64_t i = ok ? e / a.N : 0, j = ok ? e % a.N : 0;
+    int64_t* cols = lds + t;
+    for (int q = 0; q < a.ncol; ++q)
+        cols[q * 256] = 0;
+    if (ok)
+        for (int s = 0; s < a.S; ++s)
+            fold_add(cols, 0, a.gD[(int64_t)s * MN + e], a.beta * (a.S - 1 - s));
+    const int scale = ok ? a.E[i] + a.F[j] - a.beta * (a.S + 1) : 0;
+    renormalise(cols, a.ncol, scale, a.m, ok ? a.C + i * a.ldc + j : nullptr, a.psc, ok);
 }
 
 template <class Form, int G>
 struct Dispatch {
     static hipError_t run(const GemmArgs& a, hipStream_t st)
     {
-        if (a.band == G)
-            return a.dbgD ? launch_kernel(k_slice_gemm<Form, G, true>, a, st)
-                          : launch_kernel(k_slice_gemm<Form, G, false>, a, st);
+        if (a.band == G) {
+            if (a.gD)
+                return launch_kernel(k_slice_gemm<Form, G, false, true>, a, st, false);
+            return a.dbgD ? launch_kernel(k_slice_gemm<Form, G, true, false>, a, st)
+                          : launch_kernel(k_slice_gemm<Form, G, false, false>, a, st);
+        }
         return Dispatch<Form, G - 1>::run(a, st);
     }
 };
@@ -73,6 +99,20 @@ hipError_t launch_gemm_i8(const GemmArgs& a, hipStream_t st)
 hipError_t launch_gemm_f64(const GemmArgs& a, hipStream_t st)
 {
     return Dispatch<FormF64, kGmaxF64>::run(a, st);
+}
+
+hipError_t launch_gemm_final(const GemmArgs& a, hipStream_t st)
+{
+    const size_t lds = (size_t)a.ncol * 256 * sizeof(int64_t);
+    if (lds > 64 * 1024) {
+        const hipError_t e = hipFuncSetAttribute((const void*)k_gemm_final,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess)
+            return e;
+    }
+    const int64_t blocks = (a.M * a.N + 255) / 256;
+    hipLaunchKernelGGL(k_gemm_final, dim3((unsigned)blocks), dim3(256), lds, st, a);
+    return hipGetLastError();
 }
 
 }  // namespace mdg

@@ -152,6 +152,44 @@ def test_triangle_kernel_every_S_several_chunks(S):
     np.testing.assert_array_equal(host(C), ox.method_product(A, B, 7, S)["C"])
 
 
+@pytest.mark.parametrize("m", [1, 16])
+@pytest.mark.parametrize("form", ["int8", "fp64"])
+def test_word_counts_one_and_sixteen(m, form):
+    """Doubles and hexa-doubles: the rule's parameters equal the oracle's,
+    the output equals the oracle's method bit for bit and is within 2^-T.
+    At m = 16 the banded kernels' LDS fold does not fit (S = 120 INT8,
+    about 40 FP64), so their diagonal sums go through the [S][M][N] buffer
+    and the separate fold-and-round kernel."""
+    r = np.random.Generator(np.random.PCG64(700 + m))
+    A = mdinputs.mdouble(r, m, (20, 50), ("log2uniform", 6.0))
+    B = mdinputs.mdouble(r, m, (50, 24), ("log2uniform", 6.0))
+    C, info = md.gemm_ex(dev(A), dev(B), form=form)
+    C = host(C)
+    T = ox.TARGET_BITS[m]
+    _, sA = ox.row_exponents(A[0])
+    _, sB = ox.row_exponents(B[0].T)
+    G = ox.span_G(max(sA), max(sB))
+    _, G_rho = ox.rho_G(A, B)
+    if G_rho is not None:
+        G = min(G, G_rho)
+    beta, S, kc, band = ox.choose_params(form, 50, T, G)
+    assert (info["beta"], info["S"], info["kc"], info["band"]) == (beta, S, kc, band)
+    np.testing.assert_array_equal(C, ox.method_product(A, B, beta, S)["C"])
+    num, L = ox.exact_product(A, B)
+    anum, _ = ox.abs_product(A, B)
+    assert max(ox.error_report(C, num, anum, L).values()) <= -T
+
+
+def test_global_fold_debug_dump():
+    """Forced S = 80 (five bands of 16): the LDS fold would need 172 KB, so
+    the banded kernel adds its diagonal sums into the caller's debug buffer,
+    which the fold-and-round kernel then reads; every step bit-exact."""
+    A, B = mdinputs.workload("od1024", M=37, N=45, K=130)
+    got, info = run_debug(A, B, "int8", 80, 7)
+    assert info["S"] == 80 and info["band"] == 16
+    check_against_oracle(A, B, got, 7, 80)
+
+
 def test_rho_certificate_falls_back_to_span():
     """A zero magnitude product (disjoint supports) leaves only the span
     certificate; the product is then exactly zero where it must be."""
