@@ -1,0 +1,74 @@
+"""API behaviour on the GPU: caller workspace, streams, concurrency
+(needs an MI355X)."""
+import numpy as np
+import pytest
+import torch
+
+import mdinputs
+import paper_2606_20863_amd as md
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.mark.parametrize("form", ["int8", "fp64"])
+def test_caller_workspace(form):
+    """With a workspace of md_workspace_size bytes the library allocates
+    nothing and gives the same words; a workspace too small is MD_ENOMEM."""
+    A, B = mdinputs.workload("qd1024", M=40, N=56, K=130)
+    ref, info = md.gemm_ex(dev(A), dev(B), form=form)
+    ref = host(ref)
+    nbytes = md.lib().md_workspace_size(md._FORMS[form], 40, 56, 130, info["S"])
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    C, info2 = md.gemm_ex(dev(A), dev(B), form=form, workspace=ws)
+    np.testing.assert_array_equal(host(C), ref)
+    assert info2["S"] == info["S"]
+    small = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    with pytest.raises(md.MDError) as e:
+        md.gemm_ex(dev(A), dev(B), form=form, workspace=small)
+    assert e.value.code == 5
+
+
+def test_workspace_covers_the_global_fold():
+    """Hexa-double FP64: the [S][M][N] diagonal-sum buffer is part of
+    md_workspace_size."""
+    r = np.random.Generator(np.random.PCG64(9))
+    A = mdinputs.mdouble(r, 16, (24, 40))
+    B = mdinputs.mdouble(r, 16, (40, 20))
+    ref, info = md.gemm_ex(dev(A), dev(B), form="fp64")
+    nbytes = md.lib().md_workspace_size(0, 24, 20, 40, info["S"])
+    assert nbytes >= info["S"] * 24 * 20 * 8
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    C, _ = md.gemm_ex(dev(A), dev(B), form="fp64", workspace=ws)
+    np.testing.assert_array_equal(host(C), host(ref))
+
+
+def test_streams_and_concurrency():
+    """Products queued on two non-default streams at once give the words of
+    the same products on the default stream."""
+    A1, B1 = mdinputs.workload("qd1024", M=64, N=64, K=256)
+    A2, B2 = mdinputs.workload("od1024", M=48, N=80, K=200)
+    r1 = host(md.gemm_ex(dev(A1), dev(B1), form="int8")[0])
+    r2 = host(md.gemm_ex(dev(A2), dev(B2), form="fp64")[0])
+    dA1, dB1, dA2, dB2 = dev(A1), dev(B1), dev(A2), dev(B2)
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    outs = []
+    for _ in range(3):
+        with torch.cuda.stream(s1):
+            c1 = md.gemm_ex(dA1, dB1, form="int8", stream=s1)[0]
+        with torch.cuda.stream(s2):
+            c2 = md.gemm_ex(dA2, dB2, form="fp64", stream=s2)[0]
+        outs.append((c1, c2))
+    torch.cuda.synchronize()
+    for c1, c2 in outs:
+        np.testing.assert_array_equal(c1.cpu().numpy(), r1)
+        np.testing.assert_array_equal(c2.cpu().numpy(), r2)
