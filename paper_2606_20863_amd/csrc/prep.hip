@@ -46,14 +46,13 @@ __device__ __forceinline__ bool decode(double x, uint64_t& mant, int& ex)
     return (b >> 63) != 0;
 }
 
-// floor(mant * 2^sh) mod 2^W, W <= 63
+// floor(mant * 2^sh) mod 2^W, W <= 63, mant < 2^53; branch-free (clamped
+// shift counts and selects), as the word offsets differ from lane to lane
 __device__ __forceinline__ uint64_t field(uint64_t mant, int sh, uint64_t wmask)
 {
-    uint64_t v;
-    if (sh >= 0)
-        v = sh >= 63 ? 0 : (mant << sh);
-    else
-        v = sh <= -64 ? 0 : (mant >> (-sh));
+    const uint64_t up = mant << (sh & 63);                     // used for 0 <= sh < 63
+    const uint64_t down = mant >> (sh < -63 ? 63 : -sh & 63);   // used for sh < 0
+    const uint64_t v = sh >= 63 ? 0 : (sh >= 0 ? up : down);
     return v & wmask;
 }
 
@@ -151,10 +150,8 @@ __device__ __forceinline__ void limb_pair(const uint64_t (&mant)[MW], const int 
 #pragma unroll
     for (int w = 0; w < MW; ++w) {
         const uint64_t v = field(mant[w], sh0[w] + shift, wmask);
-        if (neg[w])
-            N |= v;
-        else
-            P |= v;
+        N |= neg[w] ? v : 0;
+        P |= neg[w] ? 0 : v;
     }
 }
 
@@ -170,7 +167,7 @@ template <> struct Bytes<1> { typedef uint8_t type; };
 // lane L = EPT T' / 16 (row L % 16) at depths 16 (L / 16) + (EPT T') % 16 + q.
 // With more words per entry, fewer entries per thread keep the decoded words
 // in registers.
-template <int MW, int EPT>
+template <int MW, int EPT, bool DBG>
 __global__ __launch_bounds__(256) void k_split_i8(Operand op, const int32_t* E, int S,
                                                   int64_t nkc, int8_t* out, int32_t* dbg)
 {
@@ -221,7 +218,7 @@ __global__ __launch_bounds__(256) void k_split_i8(Operand op, const int32_t* E, 
                 packed |= ((uint32_t)(dv[q] & 0xff)) << (8 * q);
             }
             o[(int64_t)s * (1024 / EPT)] = (Store)packed;
-            if (dbg && row_ok) {
+            if (DBG && row_ok) {
 #pragma unroll
                 for (int q = 0; q < EPT; ++q)
                     if (kbase + q < op.K)
@@ -286,7 +283,7 @@ __device__ __forceinline__ double pack_doubles<1>(const double (&v)[1])
 // depths 4q + l/16); a block of 256 threads writes EPT fragments, EPT
 // consecutive doubles per thread: thread u of a fragment covers doubles
 // [EPT u, EPT u + EPT), i.e. lane EPT u / 4, q from (EPT u) % 4.
-template <int MW, int EPT>
+template <int MW, int EPT, bool DBG>
 __global__ __launch_bounds__(256) void k_split_f64(Operand op, const int32_t* E, int S, int beta,
                                                    int64_t nrb, int64_t nkc, double* out,
                                                    int32_t* dbg)
@@ -338,7 +335,7 @@ __global__ __launch_bounds__(256) void k_split_f64(Operand op, const int32_t* E,
             for (int q = 0; q < EPT; ++q)
                 dv[q] = (double)((int64_t)((P[q] >> rs) & dmask) - (int64_t)((N[q] >> rs) & dmask));
             o[(int64_t)s * TPF] = pack_doubles<EPT>(dv);
-            if (dbg && row_ok) {
+            if (DBG && row_ok) {
 #pragma unroll
                 for (int q = 0; q < EPT; ++q) {
                     const int64_t k = kc * kKcF64 + 4 * (q0 + q) + (lane >> 4);
@@ -395,8 +392,11 @@ hipError_t split_i8_m(const Operand& op, const int32_t* E, int S, int64_t nrb, i
                       int8_t* out, int32_t* dbg, hipStream_t st)
 {
     constexpr int EPT = split_ept(MW);
-    hipLaunchKernelGGL((k_split_i8<MW, EPT>), dim3((unsigned)(nkc * (4 / EPT)), (unsigned)nrb),
-                       dim3(256), 0, st, op, E, S, nkc, out, dbg);
+    const dim3 grid((unsigned)(nkc * (4 / EPT)), (unsigned)nrb);
+    if (dbg)
+        hipLaunchKernelGGL((k_split_i8<MW, EPT, true>), grid, dim3(256), 0, st, op, E, S, nkc, out, dbg);
+    else
+        hipLaunchKernelGGL((k_split_i8<MW, EPT, false>), grid, dim3(256), 0, st, op, E, S, nkc, out, dbg);
     return hipGetLastError();
 }
 
@@ -427,8 +427,12 @@ hipError_t split_f64_m(const Operand& op, const int32_t* E, int S, int beta, int
 {
     constexpr int EPT = split_ept(MW);
     const int64_t blocks = (nrb * nkc + EPT - 1) / EPT;
-    hipLaunchKernelGGL((k_split_f64<MW, EPT>), dim3((unsigned)blocks), dim3(256), 0, st, op, E, S,
-                       beta, nrb, nkc, out, dbg);
+    if (dbg)
+        hipLaunchKernelGGL((k_split_f64<MW, EPT, true>), dim3((unsigned)blocks), dim3(256), 0, st, op, E,
+                           S, beta, nrb, nkc, out, dbg);
+    else
+        hipLaunchKernelGGL((k_split_f64<MW, EPT, false>), dim3((unsigned)blocks), dim3(256), 0, st, op,
+                           E, S, beta, nrb, nkc, out, dbg);
     return hipGetLastError();
 }
 
