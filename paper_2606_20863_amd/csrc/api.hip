@@ -106,12 +106,14 @@ int fold_columns(int beta, int S, int64_t Kp)
 
 int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 
-// The banded contraction's LDS fold (4 waves x ncol x 256 int64) exceeds the
-// 160 KB of LDS; the whole-triangle INT8 kernels never need it.
+// The [S][M][N] diagonal-sum buffer: the banded INT8 kernels always use it
+// (two row blocks per wave), the FP64 bands when their LDS fold (4 waves x
+// ncol x 256 int64) exceeds the 160 KB of LDS; the whole-triangle INT8
+// kernels fold in registers.
 bool needs_global_fold(int form, int band, int S, int ncol)
 {
-    if (form == MD_FORM_INT8 && band == S && S <= kTriMaxI8)
-        return false;
+    if (form == MD_FORM_INT8)
+        return !(band == S && S <= kTriMaxI8);
     return (size_t)4 * ncol * 256 * sizeof(int64_t) > 160 * 1024;
 }
 
@@ -281,8 +283,10 @@ size_t md_workspace_size(int form, int64_t M, int64_t N, int64_t K, int S)
     // digits as the bound)
     const int kcg = form == MD_FORM_INT8 ? kKcI8 : kKcF64;
     const int ncol = fold_columns(form == MD_FORM_INT8 ? 7 : 24, S, round_up(std::max<int64_t>(K, 1), kcg));
-    if (!(form == MD_FORM_INT8 && S <= kTriMaxI8) && (size_t)4 * ncol * 256 * sizeof(int64_t) > 160 * 1024)
-        bytes += (size_t)S * M * N * sizeof(int64_t) + 256;
+    const bool global = form == MD_FORM_INT8 ? S > kTriMaxI8
+                                             : (size_t)4 * ncol * 256 * sizeof(int64_t) > 160 * 1024;
+    if (global)
+        bytes += (size_t)gd_elements(M, N, S, form == MD_FORM_INT8 ? 2 : 1) * sizeof(int64_t) + 256;
     return bytes;
 }
 
@@ -468,17 +472,15 @@ int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, c
             return hip_fail(e);
     }
     int64_t* gD = nullptr;
+    const int gR = o.form == MD_FORM_INT8 ? 2 : 1;   // row blocks per wave of the banded kernels
     if (global_fold) {
-        if (dbg && dbg->D) {
-            gD = dbg->D;   // the debug dump is the same [S][M][N] sums
-        } else {
-            void* p;
-            if (!mul_ok((int64_t)S * M, N) || (rc = scr.get((size_t)S * M * N * sizeof(int64_t), &p)))
-                return rc ? rc : MD_ENOMEM;
-            gD = (int64_t*)p;
-            if ((e = launch_fill_zero_i64(gD, (int64_t)S * M * N, st)) != hipSuccess)
-                return hip_fail(e);
-        }
+        const int64_t n = gd_elements(M, N, S, gR);
+        void* p;
+        if ((rc = scr.get((size_t)n * sizeof(int64_t), &p)))
+            return rc;
+        gD = (int64_t*)p;
+        if ((e = launch_fill_zero_i64(gD, n, st)) != hipSuccess)
+            return hip_fail(e);
     }
     GemmArgs ga;
     ga.A = dA;
@@ -498,8 +500,10 @@ int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, c
     ga.nbands = S / band;
     ga.m = m;
     ga.ncol = ncol;
-    ga.dbgD = global_fold ? nullptr : (dbg ? dbg->D : nullptr);
+    ga.dbgD = dbg ? dbg->D : nullptr;   // with the sum buffer, the final kernel fills it
     ga.gD = gD;
+    ga.gR = gR;
+    ga.gI8 = o.form == MD_FORM_INT8;
     if (o.ev_gemm_begin && (e = hipEventRecord((hipEvent_t)o.ev_gemm_begin, st)) != hipSuccess)
         return hip_fail(e);
     e = o.form == MD_FORM_INT8 ? launch_gemm_i8(ga, st) : launch_gemm_f64(ga, st);

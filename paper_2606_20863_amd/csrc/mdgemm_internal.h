@@ -51,11 +51,24 @@ struct GemmArgs {
     int S, beta, band, nbands, m;
     int ncol;               // 32-bit columns of the exact fold accumulator
     int64_t* dbgD;          // optional [S][M][N]
-    // [S][M][N], zeroed: when set, the banded kernels add their diagonal
-    // sums here instead of folding in LDS (the fold would not fit), and
-    // launch_gemm_final folds and rounds afterwards
+    // Diagonal-sum buffer, zeroed: when set, the banded kernels add their
+    // diagonal sums here instead of folding in LDS, and launch_gemm_final
+    // folds and rounds afterwards.  Tile-private layout: wave w of workgroup
+    // tile (ty, tx) (gx = ceil(N/32) tiles per row, tiles of 32 gR rows)
+    // keeps per diagonal t its 64 lanes x 4 gR consecutive int64, slot
+    // r*4 + o holding output o of the lane in its row block r:
+    //   ((((ty gx + tx) 4 + w) S + t) 64 + lane) 4 gR + r*4 + o.
     int64_t* gD;
+    int gR;                 // row blocks per wave of that layout (1 or 2)
+    int gI8;                // accumulator rows as in the INT8 (1) or FP64 (0) matrix cores
 };
+
+// int64 elements of the diagonal-sum buffer for an M x N product
+inline int64_t gd_elements(int64_t M, int64_t N, int S, int gR)
+{
+    const int64_t gy = (M + 32 * gR - 1) / (32 * gR), gx = (N + 31) / 32;
+    return gy * gx * 4 * (int64_t)S * 64 * 4 * gR;
+}
 
 hipError_t launch_fill_zero(double* C, int m, int64_t M, int64_t N, int64_t ldc, int64_t psc,
                             hipStream_t st);

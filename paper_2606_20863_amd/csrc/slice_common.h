@@ -415,6 +415,7 @@ __device__ __forceinline__ void tile_of_workgroup(int64_t gx, int64_t gy, int64_
 // 16 x 16 output tiles per workgroup.
 struct WaveTile {
     int lane, wave;
+    int64_t ty, tx;     // workgroup tile
     int64_t rb, cb;     // row block of op(A), column block of op(B)
     int64_t* cols;      // this lane's fold columns: cols[q * 256 + o * 64]
 
@@ -423,7 +424,6 @@ struct WaveTile {
     {
         lane = threadIdx.x & 63;
         wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
-        int64_t ty, tx;
         tile_of_workgroup((a.N + kTile - 1) / kTile, (a.M + kTile * R - 1) / (kTile * R), ty, tx);
         rb = (ty * 2 + (wave >> 1)) * R;
         cb = tx * 2 + (wave & 1);
@@ -441,11 +441,19 @@ struct WaveTile {
     }
 };
 
+// This lane's diagonal 0 in the diagonal-sum buffer (layout in GemmArgs);
+// diagonal t is 256 gR elements further.
+__device__ __forceinline__ int64_t* gd_lane(const GemmArgs& a, const WaveTile& w)
+{
+    const int64_t gx = (a.N + kTile - 1) / kTile;
+    return a.gD + ((((w.ty * gx + w.tx) * 4 + w.wave) * (int64_t)a.S) * 64 + w.lane) * (4 * a.gR);
+}
+
 // Exact fold of one depth chunk's diagonal sums t0 .. t0+G-1.  DBG kernels
 // also add them into the debug buffer (a separate instantiation, so that the
-// production kernels carry no debug addressing).  GLOBAL kernels only add
-// them into a.gD (every output belongs to one lane of one wave, so the
-// read-modify-writes do not race) and keep no LDS fold.
+// production kernels carry no debug addressing).  GLOBAL kernels (one row
+// block per wave) only add them into the lane's slots of a.gD (private to
+// the lane, so the read-modify-writes do not race) and keep no LDS fold.
 template <class Form, int G, bool DBG, bool GLOBAL = false>
 __device__ __forceinline__ void fold_chunk(const typename Form::acc (&acc)[G], int t0,
                                            const GemmArgs& a, const WaveTile& w)
@@ -457,13 +465,15 @@ __device__ __forceinline__ void fold_chunk(const typename Form::acc (&acc)[G], i
 #pragma unroll
         for (int o = 0; o < 4; ++o) {
             const int64_t v = Form::value(acc[g], o);
-            if constexpr (!GLOBAL)
+            if constexpr (GLOBAL) {
+                gd_lane(a, w)[(int64_t)t * 256 + o] += v;
+            } else {
                 fold_add(w.cols, o, v, p);
-            if constexpr (DBG || GLOBAL) {
-                int64_t* D = GLOBAL ? a.gD : a.dbgD;
-                const int64_t i = w.rb * 16 + Form::row(w.lane, o), j = w.cb * 16 + (w.lane & 15);
-                if (i < a.M && j < a.N)
-                    D[((int64_t)t * a.M + i) * a.N + j] += v;
+                if constexpr (DBG) {
+                    const int64_t i = w.rb * 16 + Form::row(w.lane, o), j = w.cb * 16 + (w.lane & 15);
+                    if (i < a.M && j < a.N)
+                        a.dbgD[((int64_t)t * a.M + i) * a.N + j] += v;
+                }
             }
         }
     }

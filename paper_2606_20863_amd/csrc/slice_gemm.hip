@@ -43,7 +43,11 @@ __global__ __launch_bounds__(256, 1) void k_slice_gemm(GemmArgs a)
 }
 
 // Fold and round every output from the diagonal sums in a.gD: one thread per
-// entry, its fold columns in LDS (ncol x 256).
+// entry, its fold columns in LDS (ncol x 256).  The entry's place in the
+// buffer's layout: tile (i / 32R, j / 32); wave (row half, column half); row
+// block r within the wave; lane and accumulator element o from the matrix
+// cores' row mapping (INT8: row 4 (lane/16) + o; FP64: row 4 o + lane/16).
+// With a debug buffer the sums are also written there as [S][M][N].
 __global__ __launch_bounds__(256) void k_gemm_final(GemmArgs a)
 {
     extern __shared__ int64_t lds[];
@@ -52,15 +56,219 @@ __global__ __launch_bounds__(256) void k_gemm_final(GemmArgs a)
     const int64_t MN = a.M * a.N;
     const bool ok = e < MN;
     const int64_t i = ok ? e / a.N : 0, j = ok ? e % a.N : 0;
+    const int R = a.gR;
+    const int64_t gx = (a.N + kTile - 1) / kTile;
+    const int64_t ty = i / (kTile * R), tx = j / kTile;
+    const int ir = (int)(i % (kTile * R)), jc = (int)(j % kTile);
+    const int wave = (ir / (16 * R)) * 2 + jc / 16;
+    const int r = (ir % (16 * R)) / 16, i16 = ir % 16;
+    const int lane = (jc % 16) + 16 * (a.gI8 ? i16 / 4 : i16 % 4);
+    const int o = a.gI8 ? i16 % 4 : i16 / 4;
+    const int64_t* src = a.gD + ((((ty * gx + tx) * 4 + wave) * (int64_t)a.S) * 64 + lane) * (4 * R) +
+                         r * 4 + o;
     int64_t* cols = lds + t;
     for (int q = 0; q < a.ncol; ++q)
         cols[q * 256] = 0;
     if (ok)
-        for (int s = 0; s < a.S; ++s)
-            fold_add(cols, 0, a.gD[(int64_t)s * MN + e], a.beta * (a.S - 1 - s));
+        for (int s = 0; s < a.S; ++s) {
+            const int64_t v = src[(int64_t)s * 256 * R];
+            fold_add(cols, 0, v, a.beta * (a.S - 1 - s));
+            if (a.dbgD)
+                a.dbgD[(int64_t)s * MN + e] = v;
+        }
     const int scale = ok ? a.E[i] + a.F[j] - a.beta * (a.S + 1) : 0;
     renormalise(cols, a.ncol, scale, a.m, ok ? a.C + i * a.ldc + j : nullptr, a.psc, ok);
 }
+
+// INT8 bands with R row blocks of op(A) sharing one window of B fragments
+// (as the whole-triangle kernel does), over the depth chunks [c0, c1).  A
+// chunk runs steps s = 0 .. t0+G-1: step s multiplies A_s of every row block
+// with B_{t0+g-s} into diagonal t0+g for every g with a partner (all g
+// while s < t0, g >= s - t0 after).  The window slot of B_u is u mod G; the
+// B fragment entering at step s (1 <= s <= t0) is B_{t0-s}.  A fragments and
+// entering B fragments are loaded P steps ahead into small rings, across
+// chunk boundaries; the next chunk's window is loaded in place during the
+// tail steps, slot G-p at tail step p (its last use was the step before).  Buffer
+// descriptors bound every load (offsets past a stream read zeros).
+template <int G, int R, int P>
+__device__ __forceinline__ void band_run_r(v4i (&acc)[R][G], const FragStream (&LDA)[R],
+                                           const FragStream& LDB, int64_t c0, int64_t c1, int t0,
+                                           int S)
+{
+    static_assert(P >= 1 && P < G, "prefetch distance must be below the band width");
+    constexpr uint32_t F = 1024;
+    const uint32_t CS = (uint32_t)S * F;
+    uint32_t ck = (uint32_t)c0 * CS;
+    v4i win[G], pa[R][P], pb[P];
+#pragma unroll
+    for (int g = G - 1; g >= 0; --g)
+        win[g] = LDB(ck + (uint32_t)(t0 + g) * F);
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            pa[r][q] = LDA[r](ck + q * F);
+        pb[q] = LDB(q <= t0 ? ck + (uint32_t)(t0 - q) * F : ck);
+    }
+    for (int64_t kc = c0; kc < c1; ++kc) {
+        const uint32_t cn = kc + 1 < c1 ? ck + CS : ck;
+        // steps s = 0 .. t0-1: every diagonal of the band has a partner
+        for (int s0 = 0; s0 < t0; s0 += G) {
+#pragma unroll
+            for (int r = 0; r < G; ++r) {
+                const int s = s0 + r;
+                v4i a[R];
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr)
+                    a[rr] = pa[rr][0];
+                const v4i b = pb[0];
+#pragma unroll
+                for (int q = 0; q + 1 < P; ++q) {
+#pragma unroll
+                    for (int rr = 0; rr < R; ++rr)
+                        pa[rr][q] = pa[rr][q + 1];
+                    pb[q] = pb[q + 1];
+                }
+                // step s + P < t0 + G is this chunk's
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr)
+                    pa[rr][P - 1] = LDA[rr](ck + (uint32_t)(s + P) * F);
+                if (s + P <= t0)
+                    pb[P - 1] = LDB(ck + (uint32_t)(t0 - s - P) * F);
+                if (r > 0 || s0 > 0)
+                    win[(G - r) % G] = b;
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int g = G - 1; g >= 0; --g)
+#pragma unroll
+                    for (int rr = 0; rr < R; ++rr)
+                        acc[rr][g] = FormI8::mma(a[rr], win[(g - r + G) % G], acc[rr][g]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        // step t0: B_0 enters
+        {
+            v4i a[R];
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr)
+                a[rr] = pa[rr][0];
+            const v4i b = pb[0];
+#pragma unroll
+            for (int q = 0; q + 1 < P; ++q) {
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr)
+                    pa[rr][q] = pa[rr][q + 1];
+                pb[q] = pb[q + 1];
+            }
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr)
+                pa[rr][P - 1] = LDA[rr](ck + (uint32_t)(t0 + P) * F);
+            if (t0 > 0)
+                win[0] = b;
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int g = G - 1; g >= 0; --g)
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr)
+                    acc[rr][g] = FormI8::mma(a[rr], win[g], acc[rr][g]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // tail steps t0 + p, p = 1 .. G-1: diagonals g >= p read slots
+        // 0 .. G-1-p, so slot G-p takes the next chunk's B_{t0+G-p}
+#pragma unroll
+        for (int p = 1; p < G; ++p) {
+            v4i a[R];
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr)
+                a[rr] = pa[rr][0];
+#pragma unroll
+            for (int q = 0; q + 1 < P; ++q) {
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr)
+                    pa[rr][q] = pa[rr][q + 1];
+                pb[q] = pb[q + 1];
+            }
+            const int nq = p + P - G;   // step of the next chunk, if >= 0
+            if (nq < 0) {
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr)
+                    pa[rr][P - 1] = LDA[rr](ck + (uint32_t)(t0 + p + P) * F);
+            } else {
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr)
+                    pa[rr][P - 1] = LDA[rr](cn + (uint32_t)nq * F);
+                if (nq >= 1 && nq <= t0)
+                    pb[P - 1] = LDB(cn + (uint32_t)(t0 - nq) * F);
+            }
+            win[G - p] = LDB(cn + (uint32_t)(t0 + G - p) * F);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int g = G - 1; g >= p; --g)
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr)
+                    acc[rr][g] = FormI8::mma(a[rr], win[g - p], acc[rr][g]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        win[0] = LDB(cn + (uint32_t)t0 * F);
+        ck = cn;
+    }
+}
+
+// Banded INT8 contraction (S > 32 diagonals, bands of G) with two row blocks
+// per wave, 64 x 32 workgroup tiles; the diagonal sums of every exactness
+// chunk are added into a.gD, which launch_gemm_final folds and rounds.
+template <int G>
+__global__ __launch_bounds__(256, 1) void k_band2_i8(GemmArgs a)
+{
+    const WaveTile w(a, 2);
+    const uint64_t bytes = (uint64_t)a.nkc * a.S * 1024;
+    const int64_t nrb = 2 * ((a.M + kTile - 1) / kTile);
+    FragStream LA[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+        LA[r] = frag_stream((const char*)a.A + (w.rb + r) * bytes, w.rb + r < nrb ? bytes : 0,
+                            w.lane);
+    const FragStream LB = frag_stream((const char*)a.B + w.cb * bytes, bytes, w.lane);
+    for (int b = 0; b < a.nbands; ++b) {
+        const int t0 = b * G;
+        for (int64_t c0 = 0; c0 < a.nkc; c0 += a.kcc) {
+            v4i acc[2][G];
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+                    acc[r][g] = FormI8::zero();
+            band_run_r<G, 2, 3>(acc, LA, LB, c0, min(c0 + a.kcc, a.nkc), t0, a.S);
+            // the lane's eight slots of each diagonal (private, padded: no
+            // bounds checks), one diagonal at a time
+            int64_t* D = gd_lane(a, w) + (int64_t)t0 * 512;
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+#pragma unroll
+                for (int r = 0; r < 2; ++r)
+#pragma unroll
+                    for (int o = 0; o < 4; ++o)
+                        D[r * 4 + o] += acc[r][g][o];
+                D += 512;
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    }
+}
+
+template <int G>
+struct DispatchBand2 {
+    static hipError_t run(const GemmArgs& a, hipStream_t st)
+    {
+        if (a.band == G)
+            return launch_kernel(k_band2_i8<G>, a, st, false, 2 * kTile);
+        return DispatchBand2<G - 1>::run(a, st);
+    }
+};
+template <>
+struct DispatchBand2<3> {   // the pipeline needs bands wider than its depth
+    static hipError_t run(const GemmArgs&, hipStream_t) { return hipErrorInvalidValue; }
+};
 
 template <class Form, int G>
 struct Dispatch {
@@ -93,7 +301,10 @@ hipError_t launch_gemm_i8(const GemmArgs& a, hipStream_t st)
             return launch_tri_s23_28(a, st);
         return launch_tri_s29_32(a, st);
     }
-    return Dispatch<FormI8, kGmaxI8>::run(a, st);
+    // bands: the diagonal sums go through a.gD
+    if (!a.gD)
+        return hipErrorInvalidValue;
+    return DispatchBand2<kGmaxI8>::run(a, st);
 }
 
 hipError_t launch_gemm_f64(const GemmArgs& a, hipStream_t st)
