@@ -306,17 +306,41 @@ static void split_entry(int m, const double *x, int64_t wstride, int E, int beta
 }
 
 /*
+ * Balanced base-256 digits of the integer sum_s d[s] 256^(S-1-s) (any signs,
+ * d[0] most significant): each digit plus the carry from below becomes its
+ * centred remainder in [-128, 127], the rest is carried up.  Returns the
+ * carry out of the top digit (0 when S balanced digits reach the integer).
+ */
+static int recode_balanced(int32_t *d, int S)
+{
+    int carry = 0;
+    for (int s = S - 1; s >= 0; --s) {
+        int v = d[s] + carry;
+        int r = ((v + 128) % 256 + 256) % 256 - 128;
+        d[s] = r;
+        carry = (v - r) / 256;
+    }
+    return carry;
+}
+
+/*
  * Method layer for the entries rows x cols.
  * E[i] (M) and F[j] (N) are computed over full rows / columns and returned.
  * D[(a*ncols + b)*S + t] = D_t of entry (rows[a], cols[b]);
  * C[(a*ncols + b)*m + w] = greedy RN of the fold.
+ * balanced: the balanced 8-bit digits (beta = 8): each entry truncated on
+ * the grid that starts at 2^(E+2) and recoded into digits in [-128, 127];
+ * the fold then takes E+2 and F+2.
  */
 int orc_method_entries(int m, int64_t M, int64_t N, int64_t K, const double *A, const double *B,
-                       int beta, int S, int64_t nrows, const int64_t *rows, int64_t ncols,
-                       const int64_t *cols, int32_t *E, int32_t *F, int64_t *D, double *C)
+                       int beta, int S, int balanced, int64_t nrows, const int64_t *rows,
+                       int64_t ncols, const int64_t *cols, int32_t *E, int32_t *F, int64_t *D,
+                       double *C)
 {
-    if (m < 1 || beta < 1 || beta > 30 || S < 1)
+    if (m < 1 || beta < 1 || beta > 30 || S < 1 || (balanced && beta != 8))
         return 1;
+    const int h = balanced ? 2 : 0;
+    int bad = 0;
     orc_exponents(M, K, A, K, 1, E, NULL);
     orc_exponents(N, K, B, 1, N, F, NULL);
     int32_t *dA = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nrows * K * S + 1));
@@ -326,14 +350,27 @@ int orc_method_entries(int m, int64_t M, int64_t N, int64_t K, const double *A, 
         free(dB);
         return 2;
     }
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) reduction(|: bad)
     for (int64_t a = 0; a < nrows; ++a)
-        for (int64_t k = 0; k < K; ++k)
-            split_entry(m, A + rows[a] * K + k, M * K, E[rows[a]], beta, S, dA + (a * K + k) * S);
-#pragma omp parallel for schedule(static)
+        for (int64_t k = 0; k < K; ++k) {
+            int32_t *d = dA + (a * K + k) * S;
+            split_entry(m, A + rows[a] * K + k, M * K, E[rows[a]] + h, beta, S, d);
+            if (balanced)
+                bad |= recode_balanced(d, S) != 0;
+        }
+#pragma omp parallel for schedule(static) reduction(|: bad)
     for (int64_t b = 0; b < ncols; ++b)
-        for (int64_t k = 0; k < K; ++k)
-            split_entry(m, B + k * N + cols[b], K * N, F[cols[b]], beta, S, dB + (b * K + k) * S);
+        for (int64_t k = 0; k < K; ++k) {
+            int32_t *d = dB + (b * K + k) * S;
+            split_entry(m, B + k * N + cols[b], K * N, F[cols[b]] + h, beta, S, d);
+            if (balanced)
+                bad |= recode_balanced(d, S) != 0;
+        }
+    if (bad) {
+        free(dA);
+        free(dB);
+        return 3;
+    }
 #pragma omp parallel for collapse(2) schedule(dynamic, 1)
     for (int64_t a = 0; a < nrows; ++a) {
         for (int64_t b = 0; b < ncols; ++b) {
@@ -350,7 +387,7 @@ int orc_method_entries(int m, int64_t M, int64_t N, int64_t K, const double *A, 
             }
             acc_t *acc = (acc_t *)malloc(sizeof(acc_t));
             acc_clear(acc);
-            int ef = E[rows[a]] + F[cols[b]];
+            int ef = E[rows[a]] + F[cols[b]] + 2 * h;
             for (int t = 0; t < S; ++t)
                 acc_add_int64(acc, Dt[t], ef - beta * (t + 2));
             acc_renorm(acc, m, C + (a * ncols + b) * m, 1);

@@ -39,7 +39,7 @@ def load():
     lib.orc_exact_entries.restype = i32
     lib.orc_exponents.argtypes = [i64, i64, p, i64, i64, p, p]
     lib.orc_exponents.restype = i32
-    lib.orc_method_entries.argtypes = [i32, i64, i64, i64, p, p, i32, i32, i64, p, i64, p,
+    lib.orc_method_entries.argtypes = [i32, i64, i64, i64, p, p, i32, i32, i32, i64, p, i64, p,
                                        p, p, p, p]
     lib.orc_method_entries.restype = i32
     _lib = lib
@@ -98,8 +98,10 @@ def exponents(lead: np.ndarray, by_columns: bool):
     return E, span
 
 
-def method_entries(A: np.ndarray, B: np.ndarray, beta: int, S: int, rows, cols):
-    """Method layer for rows x cols: (E, F, D (nr, nc, S), C (m, nr, nc))."""
+def method_entries(A: np.ndarray, B: np.ndarray, beta: int, S: int, rows, cols,
+                   balanced: bool = False):
+    """Method layer for rows x cols: (E, F, D (nr, nc, S), C (m, nr, nc));
+    ``balanced``: the balanced 8-bit digits (beta = 8)."""
     lib = load()
     A = np.ascontiguousarray(A, dtype=np.float64)
     B = np.ascontiguousarray(B, dtype=np.float64)
@@ -112,7 +114,7 @@ def method_entries(A: np.ndarray, B: np.ndarray, beta: int, S: int, rows, cols):
     F = np.zeros(N, dtype=np.int32)
     D = np.zeros((nr, nc, S), dtype=np.int64)
     C = np.zeros((nr, nc, m))
-    rc = lib.orc_method_entries(m, M, N, K, _ptr(A), _ptr(B), beta, S, nr, _ptr(rows), nc,
+    rc = lib.orc_method_entries(m, M, N, K, _ptr(A), _ptr(B), beta, S, int(balanced), nr, _ptr(rows), nc,
                                 _ptr(cols), _ptr(E), _ptr(F), _ptr(D), _ptr(C))
     if rc:
         raise RuntimeError(f"orc_method_entries failed ({rc})")

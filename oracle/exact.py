@@ -29,6 +29,9 @@ Readings of the paper used here (the paper states none of these rules):
   word a_ik^(0), zero words skipped, E_i = 0 for an all-zero row;
 * split: per-word truncation toward zero, sign-magnitude digits,
   d_s = sum_w sgn(w) (floor(|w| 2^(beta(s+1)-E)) mod 2^beta);
+* balanced INT8 digits (a second INT8 encoding, not in the paper): the same
+  per-word truncation on the 8-bit grid that starts at 2^(E+2), the
+  truncated integer written in base 256 with digits in [-128, 127];
 * kept products: the triangle s + u <= S-1, as the paper keeps s_0..s_7;
 * fusion: the diagonal sums are folded exactly and rounded once, greedily
   to nearest (ties to even) word by word.
@@ -177,6 +180,81 @@ def split_planes(planes: np.ndarray, E, beta: int, S: int, by_columns: bool) -> 
                              np.where(-sh >= 63, 0, num >> right))
             out[s] += sgn * (field & mask)
     return out
+
+
+# Balanced INT8 digits.  The sign-magnitude digits above leave the int8
+# value -128 unused and spend a bit of every digit on the sign; the INT8
+# matrix cores take any value in [-128, 127].  Here the digit grid starts at
+# 2^(E+2), each word is truncated toward zero on it 8 S bits down, exactly
+# as the sign-magnitude split truncates, and the truncated integer X is
+# written in base 256 with balanced digits:
+#   X = sum_s d_s 256^(S-1-s),  d_s in [-128, 127].
+# |X| < 2^(8S-2) (the words' bits are disjoint and below 2^E), inside the
+# range S balanced digits reach.  The entry is X 2^(E + 2 - 8 S).
+BAL_BETA = 8        # digit width of the balanced form
+BAL_HEADROOM = 2    # its grid starts at 2^(E + BAL_HEADROOM)
+BAL_DMAX = 128      # largest digit magnitude
+
+
+def truncated_integer(words, Eg: int, bits: int) -> int:
+    """X = sum_w sgn(w) floor(|w| 2^(bits - Eg)): every word truncated toward
+    zero on the grid of unit 2^(Eg - bits)."""
+    X = 0
+    for w in words:
+        w = float(w)
+        if w == 0.0:
+            continue
+        x = Fraction(abs(w)) * Fraction(2) ** (bits - Eg)
+        v = x.numerator // x.denominator
+        X += v if w > 0 else -v
+    return X
+
+
+def balanced_digits(X: int, S: int):
+    """The digits d_0..d_{S-1} in [-128, 127] (d_0 most significant) with
+    X = sum_s d_s 256^(S-1-s): centred remainders from the least
+    significant digit up.  ValueError if S digits do not reach X."""
+    d = [0] * S
+    for s in range(S - 1, -1, -1):
+        r = X % 256
+        if r >= 128:
+            r -= 256
+        d[s] = r
+        X = (X - r) // 256
+    if X != 0:
+        raise ValueError("no balanced representation in S digits")
+    return d
+
+
+def split_entry_balanced(words, E: int, S: int):
+    """Balanced digits of one m-double entry whose shared exponent is E."""
+    return balanced_digits(truncated_integer(words, E + BAL_HEADROOM, BAL_BETA * S), S)
+
+
+def recode_balanced(d: np.ndarray) -> np.ndarray:
+    """Base-256 digits (S, ...) of any sign, d_0 most significant, rewritten
+    as balanced digits of the same integers: each digit plus the carry from
+    below is replaced by its centred remainder mod 256, the rest carried up.
+    ValueError if a carry leaves the top digit."""
+    out = np.empty_like(d)
+    carry = np.zeros(d.shape[1:], dtype=np.int64)
+    for s in range(d.shape[0] - 1, -1, -1):
+        v = d[s] + carry
+        r = (v + 128) % 256 - 128
+        out[s] = r
+        carry = (v - r) // 256
+    if np.any(carry != 0):
+        raise ValueError("no balanced representation in S digits")
+    return out
+
+
+def split_planes_balanced(planes: np.ndarray, E, S: int, by_columns: bool) -> np.ndarray:
+    """Balanced digits of every entry (layout as ``split_planes``): the
+    sign-magnitude 8-bit digits on the grid 2^(E+2) hold the truncated
+    integer with digits in [-255, 255]; ``recode_balanced`` carries them
+    into [-128, 127]."""
+    Eg = np.asarray(E, dtype=np.int64) + BAL_HEADROOM
+    return recode_balanced(split_planes(planes, Eg, BAL_BETA, S, by_columns))
 
 
 def diagonal_sums_loop(dA, dB, S: int):
@@ -365,6 +443,24 @@ def slice_count(beta: int, T: int, G: int) -> int:
     return S
 
 
+def slice_count_balanced(T: int, G: int) -> int:
+    """Smallest S with 8 S >= T + G + ceil(log2(S+3)) + 3 (balanced form).
+
+    Budget per product term a b (|a| < 2^E_i, |b| < 2^F_j, grids 2^(E_i+2)
+    and 2^(F_j+2)): truncation errs by less than 2^(E_i+2-8S) on a (the
+    dropped bits of the words are disjoint) and |a^| < 2^E_i, so the
+    truncated product errs by less than 2^(E_i+F_j+3-8S); the dropped pairs
+    s + u >= S, with |d| <= 128, add less than
+    (S-1) (256/255) 2^(E_i+F_j+2-8S).  Together less than
+    (S+3) 2^(E_i+F_j+2-8S) for S <= 511, which the rule keeps below
+    2^-(T+1) of (|A||B|)_ij as for the sign-magnitude form.
+    """
+    S = 1
+    while BAL_BETA * S < T + G + ceil_log2(S + 3) + 3:
+        S += 1
+    return S
+
+
 def span_G(span_A: int, span_B: int) -> int:
     """G from exponent spans: every nonzero |a_ik| >= 2^(E_i - span_A - 1)
     (strongly nonoverlapping words), likewise b, so the ratio
@@ -423,10 +519,12 @@ def band_round(S: int, gmax: int, single: int = 0):
     return nb * band, band
 
 
-def chunk_depth(S: int, beta: int, K: int, limit: int, gran: int) -> int:
-    """Largest multiple of ``gran`` with S * Kc * (2^beta - 1)^2 < limit,
-    capped at K rounded up to ``gran`` (0 if even one granule overflows)."""
-    per = S * ((1 << beta) - 1) ** 2
+def chunk_depth(S: int, beta: int, K: int, limit: int, gran: int, dmax: int = 0) -> int:
+    """Largest multiple of ``gran`` with S * Kc * dmax^2 < limit, dmax the
+    largest digit magnitude (2^beta - 1 unless given), capped at K rounded
+    up to ``gran`` (0 if even one granule overflows)."""
+    dmax = dmax or (1 << beta) - 1
+    per = S * dmax * dmax
     kc = ((limit - 1) // per) // gran * gran
     kfull = -(-max(K, 1) // gran) * gran
     return min(kc, kfull)
@@ -438,6 +536,8 @@ def choose_params(form: str, K: int, T: int, G: int):
     S is the budget's slice count rounded up to equal bands (``band_round``).
     int8: beta = 7 (digits in [-127, 127]); every diagonal sum of a depth
     chunk Kc stays below 2^31 (INT32 accumulation exact).
+    int8bal: balanced 8-bit digits (``slice_count_balanced``), same chunks
+    with digits up to 128 in magnitude.
     fp64: beta in [8, 24]; every diagonal sum of a chunk stays below 2^53
     (FP64 accumulation exact).  The smallest S wins, ties go to the larger
     chunk Kc.
@@ -448,6 +548,12 @@ def choose_params(form: str, K: int, T: int, G: int):
         if kc <= 0:
             raise ValueError("no exact INT8 chunking")
         return 7, S, kc, band
+    if form == "int8bal":
+        S, band = band_round(slice_count_balanced(T, G), INT8_GMAX, INT8_SINGLE)
+        kc = chunk_depth(S, BAL_BETA, K, 1 << 31, INT8_KGRAN, BAL_DMAX)
+        if kc <= 0:
+            raise ValueError("no exact INT8 chunking")
+        return BAL_BETA, S, kc, band
     if form == "fp64":
         best = None
         for beta in range(8, 25):
@@ -467,14 +573,18 @@ def choose_params(form: str, K: int, T: int, G: int):
 # ---------------------------------------------------------------------------
 
 def method_product(A: np.ndarray, B: np.ndarray, beta: int, S: int,
-                   rows=None, cols=None):
+                   rows=None, cols=None, balanced: bool = False):
     """The method end to end for the entries rows x cols.
 
     Exponents come from the full rows of A and columns of B; only the
     sampled rows and columns are split.  Returns a dict with E, F (full),
     the digits of the sampled rows/columns, D (S, len(rows), len(cols)) and
-    the renormalised output C (m, len(rows), len(cols)).
+    the renormalised output C (m, len(rows), len(cols)).  ``balanced``: the
+    balanced 8-bit digits (beta must be 8); the fold then takes the grids
+    2^(E_i+2) and 2^(F_j+2).
     """
+    if balanced and beta != BAL_BETA:
+        raise ValueError("balanced digits are 8 bits wide")
     m = A.shape[0]
     M, K = A.shape[1], A.shape[2]
     N = B.shape[2]
@@ -486,13 +596,18 @@ def method_product(A: np.ndarray, B: np.ndarray, beta: int, S: int,
     Bs = B[:, :, cols]
     Er = [E[i] for i in rows]
     Fc = [F[j] for j in cols]
-    dA = split_planes(As, Er, beta, S, by_columns=False)
-    dB = split_planes(Bs, Fc, beta, S, by_columns=True)
+    if balanced:
+        dA = split_planes_balanced(As, Er, S, by_columns=False)
+        dB = split_planes_balanced(Bs, Fc, S, by_columns=True)
+    else:
+        dA = split_planes(As, Er, beta, S, by_columns=False)
+        dB = split_planes(Bs, Fc, beta, S, by_columns=True)
+    h = BAL_HEADROOM if balanced else 0
     D = diagonal_sums(dA, dB, S)
     C = np.zeros((m, len(rows), len(cols)))
     for a, i in enumerate(rows):
         for b, j in enumerate(cols):
-            x = fold(D[:, a, b], E[i], F[j], beta)
+            x = fold(D[:, a, b], E[i] + h, F[j] + h, beta)
             C[:, a, b] = renorm_rn(x, m)
     return {"E": E, "F": F, "spanA": spanA, "spanB": spanB,
             "dA": dA, "dB": dB, "D": D, "C": C}
@@ -553,14 +668,14 @@ def choose_dot_params(X: np.ndarray, Y: np.ndarray, form: str, rule: str = "rho"
     return choose_params(form, n, T, G)
 
 
-def method_dot(X: np.ndarray, Y: np.ndarray, beta: int, S: int):
+def method_dot(X: np.ndarray, Y: np.ndarray, beta: int, S: int, balanced: bool = False):
     """The method on every pair of a batch (``method_product`` on the 1 x 1
     product of pair b).  Returns D (S, batch) and out (m, batch)."""
     m, batch, _ = X.shape
     D = np.zeros((S, batch), dtype=object)
     out = np.zeros((m, batch))
     for b in range(batch):
-        r = method_product(*pair_operands(X, Y, b), beta, S)
+        r = method_product(*pair_operands(X, Y, b), beta, S, balanced=balanced)
         D[:, b] = r["D"][:, 0, 0]
         out[:, b] = r["C"][:, 0, 0]
     return D, out
