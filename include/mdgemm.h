@@ -16,12 +16,18 @@
  *      once, greedily to nearest, into m nonoverlapping output words
  *      (postponed renormalisation, Conclusions).
  *
- * Two slice forms:
+ * Three slice forms:
  *   MD_FORM_FP64: digits of up to 24 bits held in doubles, FP64 matrix-core
  *                 products, exact while every partial sum stays below 2^53;
  *   MD_FORM_INT8: 7-bit sign-magnitude digits in int8, INT8 matrix-core
  *                 products with INT32 accumulation, exact while every
- *                 partial sum stays below 2^31.
+ *                 partial sum stays below 2^31;
+ *   MD_FORM_INT8_BAL: the same truncation on the 8-bit grid that starts at
+ *                 2^(E_i + 2), the truncated integer written in base 256
+ *                 with balanced digits in [-128, 127] (all int8 values, so
+ *                 8 bits per slice: fewer slices for the same T); the fold
+ *                 then takes E_i + F_j + 4.  Not in the paper, whose
+ *                 quarters are sign-magnitude bit fields.
  * S and beta are chosen per call from the target accuracy 2^-T (T = 50 m)
  * relative to (|A||B|)_ij.  The contraction is cut into depth chunks so that
  * every accumulation stays exact.
@@ -54,7 +60,7 @@ extern "C" {
 
 /* return codes */
 #define MD_OK 0
-#define MD_EINVAL_M 1      /* m not in {2, 4, 8} */
+#define MD_EINVAL_M 1      /* m not in {1, 2, 4, 8, 16} */
 #define MD_EINVAL_DIM 2    /* negative size, bad leading dimension or stride, overflow */
 #define MD_ENULL 3         /* NULL data pointer with a nonzero size */
 #define MD_EALIAS 4        /* C overlaps A or B */
@@ -66,10 +72,12 @@ extern "C" {
 /* slice forms */
 #define MD_FORM_FP64 0
 #define MD_FORM_INT8 1
+#define MD_FORM_INT8_BAL 2
 
 /* slice-count rules: both bound 2^G >= max_ij N_ij 2^(E_i+F_j) / (|A||B|)_ij,
  * N_ij the number of k with a_ik b_kj != 0; S is the smallest count with
- * beta S >= T + G + ceil(log2(S+2)) + 1 (rounded up to equal bands).  The
+ * beta S >= T + G + ceil(log2(S+2)) + 1, for the balanced digits with
+ * 8 S >= T + G + ceil(log2(S+3)) + 3 (rounded up to equal bands).  The
  * certificates assume strongly nonoverlapping words, |w_{t+1}| <= ulp(w_t)/2. */
 #define MD_S_RHO 0         /* default: the smaller of the span bound and a magnitude bound
                               from one extra INT8 product of 7-bit leading-word magnitudes */
@@ -93,7 +101,8 @@ typedef struct md_info {
 /* Debug dump (small shapes): every non-NULL pointer is a device buffer the
  * caller owns; the library writes it during the call. */
 typedef struct md_debug {
-    int32_t *E;         /* [M]      shared exponents of the rows of op(A) */
+    int32_t *E;         /* [M]      shared exponents of the rows of op(A) (the balanced
+                                    digits' grid starts 2 above) */
     int32_t *F;         /* [N]      shared exponents of the columns of op(B) */
     int32_t *digits_A;  /* [S][M][K] digits of op(A) */
     int32_t *digits_B;  /* [S][N][K] digits of op(B), by column */
@@ -101,11 +110,11 @@ typedef struct md_debug {
 } md_debug;
 
 typedef struct md_opts {
-    int form;              /* MD_FORM_FP64 (default) or MD_FORM_INT8 */
+    int form;              /* MD_FORM_FP64 (default), MD_FORM_INT8 or MD_FORM_INT8_BAL */
     int s_rule;            /* MD_S_RHO (default) or MD_S_SPAN */
     int target_bits;       /* 0: T = 50 m */
     int force_S;           /* > 0: use this S (and force_beta) instead of the rule */
-    int force_beta;        /* with force_S: slice width (INT8: 7; FP64: 8..24) */
+    int force_beta;        /* with force_S: slice width (INT8: 7; INT8_BAL: 8; FP64: 8..24) */
     void *workspace;       /* optional device scratch; NULL: allocate per call */
     size_t workspace_bytes;
     md_debug *dbg;         /* optional debug dump */

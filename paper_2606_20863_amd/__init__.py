@@ -8,6 +8,7 @@ An m-double matrix is a float64 tensor of shape (m, rows, cols) on the HIP
 device, one plane per word (word 0 the leading one).
 
     C = gemm(A, B, form="int8")          # (m, M, K) x (m, K, N) -> (m, M, N)
+    C = gemm(A, B, form="int8bal")       # balanced 8-bit INT8 digits
     C = MDGemm.apply(A, B, "fp64")       # differentiable; C.backward(W)
 
 The backward pass of ``MDGemm`` takes dC as m-double planes and returns the
@@ -28,7 +29,8 @@ LIB_PATH = os.path.join(HERE, "libmdgemm.so")
 
 FORM_FP64 = 0
 FORM_INT8 = 1
-_FORMS = {"fp64": FORM_FP64, "int8": FORM_INT8}
+FORM_INT8_BAL = 2
+_FORMS = {"fp64": FORM_FP64, "int8": FORM_INT8, "int8bal": FORM_INT8_BAL}
 _RULES = {"rho": 0, "span": 1}
 
 ERRORS = {

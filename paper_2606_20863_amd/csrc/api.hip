@@ -42,6 +42,31 @@ int slice_count(int beta, int T, int G)
     return S;
 }
 
+// Balanced INT8 digits: smallest S with 8 S >= T + G + ceil(log2(S + 3)) + 3.
+// The grids start at 2^(E_i + 2) and 2^(F_j + 2); per product term the
+// truncation errs by less than 2^(E_i + F_j + 3 - 8 S) and the dropped pairs
+// (digits up to 128 in magnitude) by less than
+// (S - 1) (256/255) 2^(E_i + F_j + 2 - 8 S), together less than
+// (S + 3) 2^(E_i + F_j + 2 - 8 S) for S <= 511.
+int slice_count_balanced(int T, int G)
+{
+    int S = 1;
+    while ((int64_t)8 * S < (int64_t)T + G + ceil_log2(S + 3) + 3)
+        ++S;
+    return S;
+}
+
+bool is_i8(int form) { return form == MD_FORM_INT8 || form == MD_FORM_INT8_BAL; }
+
+// the digit grid of a row starts at 2^(E + grid_offset)
+int grid_offset(int form) { return form == MD_FORM_INT8_BAL ? 2 : 0; }
+
+// largest digit magnitude
+int64_t digit_max(int form, int beta)
+{
+    return form == MD_FORM_INT8_BAL ? 128 : ((int64_t)1 << beta) - 1;
+}
+
 // Bands of at most gmax diagonals, all of one width: S rounds up to
 // nb * ceil(S / nb) with nb = ceil(S / gmax); S <= single stays one band
 // (INT8 contracts up to kTriMaxI8 diagonals at once).
@@ -56,12 +81,11 @@ void band_round(int Smin, int gmax, int single, int& S, int& band)
     S = nb * band;
 }
 
-// Largest multiple of gran with S * kc * (2^beta - 1)^2 < limit, capped at K
-// rounded up to gran.
-int64_t chunk_depth(int S, int beta, int64_t K, int64_t limit, int gran)
+// Largest multiple of gran with S * kc * dmax^2 < limit (dmax the largest
+// digit magnitude), capped at K rounded up to gran.
+int64_t chunk_depth(int S, int64_t dmax, int64_t K, int64_t limit, int gran)
 {
-    const int64_t d = ((int64_t)1 << beta) - 1;
-    const int64_t per = (int64_t)S * d * d;
+    const int64_t per = (int64_t)S * dmax * dmax;
     int64_t kc = ((limit - 1) / per) / gran * gran;
     const int64_t kfull = (std::max<int64_t>(K, 1) + gran - 1) / gran * gran;
     return std::min(kc, kfull);
@@ -74,7 +98,13 @@ int choose(int form, int64_t K, int T, int G, int& beta, int& S, int64_t& kc, in
     if (form == MD_FORM_INT8) {
         beta = 7;
         band_round(slice_count(7, T, G), kGmaxI8, kTriMaxI8, S, band);
-        kc = chunk_depth(S, 7, K, (int64_t)1 << 31, kKcI8);
+        kc = chunk_depth(S, 127, K, (int64_t)1 << 31, kKcI8);
+        return kc > 0 ? MD_OK : MD_ERANGE;
+    }
+    if (form == MD_FORM_INT8_BAL) {
+        beta = 8;
+        band_round(slice_count_balanced(T, G), kGmaxI8, kTriMaxI8, S, band);
+        kc = chunk_depth(S, 128, K, (int64_t)1 << 31, kKcI8);
         return kc > 0 ? MD_OK : MD_ERANGE;
     }
     if (form == MD_FORM_FP64) {
@@ -82,7 +112,7 @@ int choose(int form, int64_t K, int T, int G, int& beta, int& S, int64_t& kc, in
         for (int b = 8; b <= 24; ++b) {
             int s, bd;
             band_round(slice_count(b, T, G), kGmaxF64, 0, s, bd);
-            const int64_t k = chunk_depth(s, b, K, (int64_t)1 << 53, kKcF64);
+            const int64_t k = chunk_depth(s, ((int64_t)1 << b) - 1, K, (int64_t)1 << 53, kKcF64);
             if (k <= 0)
                 continue;
             if (!found || s < S || (s == S && k > kc)) {
@@ -112,7 +142,7 @@ int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 // kernels fold in registers.
 bool needs_global_fold(int form, int band, int S, int ncol)
 {
-    if (form == MD_FORM_INT8)
+    if (is_i8(form))
         return !(band == S && S <= kTriMaxI8);
     return (size_t)4 * ncol * 256 * sizeof(int64_t) > 160 * 1024;
 }
@@ -226,7 +256,7 @@ struct Scratch {
 size_t digits_bytes(int form, int64_t R, int64_t K, int S)
 {
     const int64_t Rp = round_up(std::max<int64_t>(R, 1), kTile);
-    if (form == MD_FORM_INT8)
+    if (is_i8(form))
         return (size_t)S * Rp * round_up(std::max<int64_t>(K, 1), kKcI8);
     return (size_t)S * Rp * round_up(std::max<int64_t>(K, 1), kKcF64) * sizeof(double);
 }
@@ -244,7 +274,7 @@ const char* md_strerror(int code)
 {
     switch (code) {
     case MD_OK: return "success";
-    case MD_EINVAL_M: return "m must be 2, 4 or 8";
+    case MD_EINVAL_M: return "m must be 1, 2, 4, 8 or 16";
     case MD_EINVAL_DIM: return "invalid size, leading dimension or plane stride";
     case MD_ENULL: return "NULL data pointer";
     case MD_EALIAS: return "C overlaps A or B";
@@ -281,12 +311,12 @@ size_t md_workspace_size(int form, int64_t M, int64_t N, int64_t K, int S)
                    digits_bytes(form, N, K, S) + 4096;
     // the diagonal-sum buffer where the LDS fold does not fit (widest FP64
     // digits as the bound)
-    const int kcg = form == MD_FORM_INT8 ? kKcI8 : kKcF64;
-    const int ncol = fold_columns(form == MD_FORM_INT8 ? 7 : 24, S, round_up(std::max<int64_t>(K, 1), kcg));
-    const bool global = form == MD_FORM_INT8 ? S > kTriMaxI8
-                                             : (size_t)4 * ncol * 256 * sizeof(int64_t) > 160 * 1024;
+    const int kcg = is_i8(form) ? kKcI8 : kKcF64;
+    const int ncol = fold_columns(is_i8(form) ? 8 : 24, S, round_up(std::max<int64_t>(K, 1), kcg));
+    const bool global = is_i8(form) ? S > kTriMaxI8
+                                    : (size_t)4 * ncol * 256 * sizeof(int64_t) > 160 * 1024;
     if (global)
-        bytes += (size_t)gd_elements(M, N, S, form == MD_FORM_INT8 ? 2 : 1) * sizeof(int64_t) + 256;
+        bytes += (size_t)gd_elements(M, N, S, is_i8(form) ? 2 : 1) * sizeof(int64_t) + 256;
     return bytes;
 }
 
@@ -304,7 +334,7 @@ int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, c
     memset(&o, 0, sizeof(o));
     if (opts)
         o = *opts;
-    if (o.form != MD_FORM_FP64 && o.form != MD_FORM_INT8)
+    if (o.form != MD_FORM_FP64 && !is_i8(o.form))
         return MD_EINVAL_OPT;
     if (o.s_rule != MD_S_SPAN && o.s_rule != MD_S_RHO)
         return MD_EINVAL_OPT;
@@ -332,7 +362,8 @@ int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, c
     }
     const int T = o.target_bits > 0 ? o.target_bits : 50 * m;
     if (o.force_S < 0 || o.force_S > 512 || (o.force_S > 0 && (o.force_beta < 1 || o.force_beta > 24)) ||
-        (o.force_S > 0 && o.form == MD_FORM_INT8 && o.force_beta != 7))
+        (o.force_S > 0 && o.form == MD_FORM_INT8 && o.force_beta != 7) ||
+        (o.force_S > 0 && o.form == MD_FORM_INT8_BAL && o.force_beta != 8))
         return MD_EINVAL_OPT;
 
     hipStream_t st = (hipStream_t)stream;
@@ -379,8 +410,9 @@ int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, c
     if ((e = launch_exp_init(hiB, loB, N, nullptr, st)) != hipSuccess) return hip_fail(e);
     if ((e = launch_exp_partial(opA, hiA, loA, st)) != hipSuccess) return hip_fail(e);
     if ((e = launch_exp_partial(opB, hiB, loB, st)) != hipSuccess) return hip_fail(e);
-    if ((e = launch_exp_final(hiA, loA, M, E, stats, dbg ? dbg->E : nullptr, st)) != hipSuccess) return hip_fail(e);
-    if ((e = launch_exp_final(hiB, loB, N, F, stats + 1, dbg ? dbg->F : nullptr, st)) != hipSuccess) return hip_fail(e);
+    const int eoff = grid_offset(o.form);
+    if ((e = launch_exp_final(hiA, loA, M, E, stats, dbg ? dbg->E : nullptr, eoff, st)) != hipSuccess) return hip_fail(e);
+    if ((e = launch_exp_final(hiB, loB, N, F, stats + 1, dbg ? dbg->F : nullptr, eoff, st)) != hipSuccess) return hip_fail(e);
 
     int32_t spans[4] = {0, 0, 0, 0};   // span_A, span_B, minimum magnitude product (uint64)
     int beta, S, band;
@@ -398,24 +430,24 @@ int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, c
         rc = scr.get(digits_bytes(MD_FORM_INT8, N, K, 1), &qB);
         if (rc)
             return rc;
-        if ((e = launch_split_mag(opA, E, round_up(M, kTile) / kRowBlock, nkm, (int8_t*)qA, st)) != hipSuccess)
+        if ((e = launch_split_mag(opA, E, eoff, round_up(M, kTile) / kRowBlock, nkm, (int8_t*)qA, st)) != hipSuccess)
             return hip_fail(e);
-        if ((e = launch_split_mag(opB, F, round_up(N, kTile) / kRowBlock, nkm, (int8_t*)qB, st)) != hipSuccess)
+        if ((e = launch_split_mag(opB, F, eoff, round_up(N, kTile) / kRowBlock, nkm, (int8_t*)qB, st)) != hipSuccess)
             return hip_fail(e);
         if ((e = launch_mag_min(qA, qB, M, N, nkm, (unsigned long long*)(stats + 2), st)) != hipSuccess)
             return hip_fail(e);
     }
     if (o.force_S > 0) {
         beta = o.force_beta;
-        const int gmax = o.form == MD_FORM_INT8 ? kGmaxI8 : kGmaxF64;
-        const int single = o.form == MD_FORM_INT8 ? kTriMaxI8 : 0;
+        const int gmax = is_i8(o.form) ? kGmaxI8 : kGmaxF64;
+        const int single = is_i8(o.form) ? kTriMaxI8 : 0;
         int s2;
         band_round(o.force_S, gmax, single, s2, band);
         if (s2 != o.force_S)
             return MD_EINVAL_OPT;   // forced S must split into equal bands
         S = o.force_S;
-        kc = chunk_depth(S, beta, K, o.form == MD_FORM_INT8 ? ((int64_t)1 << 31) : ((int64_t)1 << 53),
-                         o.form == MD_FORM_INT8 ? kKcI8 : kKcF64);
+        kc = chunk_depth(S, digit_max(o.form, beta), K, is_i8(o.form) ? ((int64_t)1 << 31) : ((int64_t)1 << 53),
+                         is_i8(o.form) ? kKcI8 : kKcF64);
         if (kc <= 0)
             return MD_ERANGE;
     } else {
@@ -436,7 +468,7 @@ int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, c
         if (rc)
             return rc;
     }
-    const int kcg = o.form == MD_FORM_INT8 ? kKcI8 : kKcF64;
+    const int kcg = is_i8(o.form) ? kKcI8 : kKcF64;
     const int64_t nkc = (K + kcg - 1) / kcg;
     const int64_t Mp = round_up(M, kTile), Np = round_up(N, kTile);
     const int ncol = fold_columns(beta, S, nkc * kcg);
@@ -456,10 +488,11 @@ int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, c
     if (rc)
         return rc;
 
-    if (o.form == MD_FORM_INT8) {
-        if ((e = launch_split_i8(opA, m, E, S, Mp / kRowBlock, nkc, (int8_t*)dA, dbg ? dbg->digits_A : nullptr, st)) != hipSuccess)
+    if (is_i8(o.form)) {
+        const bool bal = o.form == MD_FORM_INT8_BAL;
+        if ((e = launch_split_i8(opA, m, E, S, Mp / kRowBlock, nkc, (int8_t*)dA, dbg ? dbg->digits_A : nullptr, bal, st)) != hipSuccess)
             return hip_fail(e);
-        if ((e = launch_split_i8(opB, m, F, S, Np / kRowBlock, nkc, (int8_t*)dB, dbg ? dbg->digits_B : nullptr, st)) != hipSuccess)
+        if ((e = launch_split_i8(opB, m, F, S, Np / kRowBlock, nkc, (int8_t*)dB, dbg ? dbg->digits_B : nullptr, bal, st)) != hipSuccess)
             return hip_fail(e);
     } else {
         if ((e = launch_split_f64(opA, m, E, S, beta, Mp / kRowBlock, nkc, (double*)dA, dbg ? dbg->digits_A : nullptr, st)) != hipSuccess)
@@ -472,7 +505,7 @@ int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, c
             return hip_fail(e);
     }
     int64_t* gD = nullptr;
-    const int gR = o.form == MD_FORM_INT8 ? 2 : 1;   // row blocks per wave of the banded kernels
+    const int gR = is_i8(o.form) ? 2 : 1;   // row blocks per wave of the banded kernels
     if (global_fold) {
         const int64_t n = gd_elements(M, N, S, gR);
         void* p;
@@ -503,10 +536,10 @@ int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, c
     ga.dbgD = dbg ? dbg->D : nullptr;   // with the sum buffer, the final kernel fills it
     ga.gD = gD;
     ga.gR = gR;
-    ga.gI8 = o.form == MD_FORM_INT8;
+    ga.gI8 = is_i8(o.form);
     if (o.ev_gemm_begin && (e = hipEventRecord((hipEvent_t)o.ev_gemm_begin, st)) != hipSuccess)
         return hip_fail(e);
-    e = o.form == MD_FORM_INT8 ? launch_gemm_i8(ga, st) : launch_gemm_f64(ga, st);
+    e = is_i8(o.form) ? launch_gemm_i8(ga, st) : launch_gemm_f64(ga, st);
     if (e != hipSuccess)
         return hip_fail(e);
     if (global_fold && (e = launch_gemm_final(ga, st)) != hipSuccess)
@@ -527,7 +560,9 @@ int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, c
         in->G_rho = G_rho;
         in->target_bits = T;
         // certified bound of the method plus the final rounding
-        const double lb = (double)(G - beta * S) + __builtin_log2((double)S + 2.0);
+        const double lb = o.form == MD_FORM_INT8_BAL
+                              ? (double)(G + 2 - 8 * S) + __builtin_log2((double)S + 3.0)
+                              : (double)(G - beta * S) + __builtin_log2((double)S + 2.0);
         in->log2_bound = o.force_S > 0 ? 0.0 : __builtin_log2(__builtin_exp2(lb) + __builtin_exp2(-53.0 * m + 0.1));
     }
     return MD_OK;
@@ -546,7 +581,7 @@ int md_dot_ex(int m, int64_t batch, int64_t n, const double* X, int64_t ldx, int
     memset(&o, 0, sizeof(o));
     if (opts)
         o = *opts;
-    if (o.form != MD_FORM_FP64 && o.form != MD_FORM_INT8)
+    if (o.form != MD_FORM_FP64 && !is_i8(o.form))
         return MD_EINVAL_OPT;
     if (o.s_rule != MD_S_SPAN && o.s_rule != MD_S_RHO)
         return MD_EINVAL_OPT;
@@ -573,7 +608,8 @@ int md_dot_ex(int m, int64_t batch, int64_t n, const double* X, int64_t ldx, int
     }
     const int T = o.target_bits > 0 ? o.target_bits : 50 * m;
     if (o.force_S < 0 || o.force_S > 512 || (o.force_S > 0 && (o.force_beta < 1 || o.force_beta > 24)) ||
-        (o.force_S > 0 && o.form == MD_FORM_INT8 && o.force_beta != 7))
+        (o.force_S > 0 && o.form == MD_FORM_INT8 && o.force_beta != 7) ||
+        (o.force_S > 0 && o.form == MD_FORM_INT8_BAL && o.force_beta != 8))
         return MD_EINVAL_OPT;
 
     hipStream_t st = (hipStream_t)stream;
@@ -620,8 +656,9 @@ int md_dot_ex(int m, int64_t batch, int64_t n, const double* X, int64_t ldx, int
     if ((e = launch_exp_init(hiY, loY, batch, nullptr, st)) != hipSuccess) return hip_fail(e);
     if ((e = launch_exp_partial(opX, hiX, loX, st)) != hipSuccess) return hip_fail(e);
     if ((e = launch_exp_partial(opY, hiY, loY, st)) != hipSuccess) return hip_fail(e);
-    if ((e = launch_exp_final(hiX, loX, batch, E, stats, nullptr, st)) != hipSuccess) return hip_fail(e);
-    if ((e = launch_exp_final(hiY, loY, batch, F, stats + 1, nullptr, st)) != hipSuccess) return hip_fail(e);
+    const int eoff = grid_offset(o.form);
+    if ((e = launch_exp_final(hiX, loX, batch, E, stats, nullptr, eoff, st)) != hipSuccess) return hip_fail(e);
+    if ((e = launch_exp_final(hiY, loY, batch, F, stats + 1, nullptr, eoff, st)) != hipSuccess) return hip_fail(e);
 
     const int64_t nrb = round_up(batch, kTile) / kRowBlock;
     int32_t spans[4] = {0, 0, 0, 0};   // span_X, span_Y, minimum magnitude product (uint64)
@@ -639,24 +676,24 @@ int md_dot_ex(int m, int64_t batch, int64_t n, const double* X, int64_t ldx, int
         rc = scr.get(digits_bytes(MD_FORM_INT8, batch, n, 1), &qY);
         if (rc)
             return rc;
-        if ((e = launch_split_mag(opX, E, nrb, nkm, (int8_t*)qX, st)) != hipSuccess)
+        if ((e = launch_split_mag(opX, E, eoff, nrb, nkm, (int8_t*)qX, st)) != hipSuccess)
             return hip_fail(e);
-        if ((e = launch_split_mag(opY, F, nrb, nkm, (int8_t*)qY, st)) != hipSuccess)
+        if ((e = launch_split_mag(opY, F, eoff, nrb, nkm, (int8_t*)qY, st)) != hipSuccess)
             return hip_fail(e);
         if ((e = launch_mag_min_diag(qX, qY, batch, nkm, (unsigned long long*)(stats + 2), st)) != hipSuccess)
             return hip_fail(e);
     }
     if (o.force_S > 0) {
         beta = o.force_beta;
-        const int gmax = o.form == MD_FORM_INT8 ? kGmaxI8 : kGmaxF64;
-        const int single = o.form == MD_FORM_INT8 ? kTriMaxI8 : 0;
+        const int gmax = is_i8(o.form) ? kGmaxI8 : kGmaxF64;
+        const int single = is_i8(o.form) ? kTriMaxI8 : 0;
         int s2;
         band_round(o.force_S, gmax, single, s2, band);
         if (s2 != o.force_S)
             return MD_EINVAL_OPT;
         S = o.force_S;
-        kc = chunk_depth(S, beta, n, o.form == MD_FORM_INT8 ? ((int64_t)1 << 31) : ((int64_t)1 << 53),
-                         o.form == MD_FORM_INT8 ? kKcI8 : kKcF64);
+        kc = chunk_depth(S, digit_max(o.form, beta), n, is_i8(o.form) ? ((int64_t)1 << 31) : ((int64_t)1 << 53),
+                         is_i8(o.form) ? kKcI8 : kKcF64);
         if (kc <= 0)
             return MD_ERANGE;
     } else {
@@ -677,7 +714,7 @@ int md_dot_ex(int m, int64_t batch, int64_t n, const double* X, int64_t ldx, int
         if (rc)
             return rc;
     }
-    const int kcg = o.form == MD_FORM_INT8 ? kKcI8 : kKcF64;
+    const int kcg = is_i8(o.form) ? kKcI8 : kKcF64;
     const int64_t nkc = (n + kcg - 1) / kcg;
     const int ncol = fold_columns(beta, S, nkc * kcg);
     if ((size_t)ncol * 256 * sizeof(int64_t) > 160 * 1024)
@@ -693,10 +730,11 @@ int md_dot_ex(int m, int64_t batch, int64_t n, const double* X, int64_t ldx, int
     rc = scr.get((size_t)S * batch * sizeof(int64_t), &Dp);
     if (rc)
         return rc;
-    if (o.form == MD_FORM_INT8) {
-        if ((e = launch_split_i8(opX, m, E, S, nrb, nkc, (int8_t*)dX, nullptr, st)) != hipSuccess)
+    if (is_i8(o.form)) {
+        const bool bal = o.form == MD_FORM_INT8_BAL;
+        if ((e = launch_split_i8(opX, m, E, S, nrb, nkc, (int8_t*)dX, nullptr, bal, st)) != hipSuccess)
             return hip_fail(e);
-        if ((e = launch_split_i8(opY, m, F, S, nrb, nkc, (int8_t*)dY, nullptr, st)) != hipSuccess)
+        if ((e = launch_split_i8(opY, m, F, S, nrb, nkc, (int8_t*)dY, nullptr, bal, st)) != hipSuccess)
             return hip_fail(e);
     } else {
         if ((e = launch_split_f64(opX, m, E, S, beta, nrb, nkc, (double*)dX, nullptr, st)) != hipSuccess)
@@ -726,7 +764,7 @@ int md_dot_ex(int m, int64_t batch, int64_t n, const double* X, int64_t ldx, int
     }
     if (o.ev_gemm_begin && (e = hipEventRecord((hipEvent_t)o.ev_gemm_begin, st)) != hipSuccess)
         return hip_fail(e);
-    if ((e = launch_dot_diag(da, o.form == MD_FORM_INT8, st)) != hipSuccess)
+    if ((e = launch_dot_diag(da, is_i8(o.form), st)) != hipSuccess)
         return hip_fail(e);
     if ((e = launch_dot_final((const int64_t*)Dp, E, F, batch, S, beta, ncol, m, out,
                               std::max<int64_t>(plane_stride_out, 1), st)) != hipSuccess)
@@ -746,7 +784,9 @@ int md_dot_ex(int m, int64_t batch, int64_t n, const double* X, int64_t ldx, int
         in->G_span = G_span;
         in->G_rho = G_rho;
         in->target_bits = T;
-        const double lb = (double)(G - beta * S) + __builtin_log2((double)S + 2.0);
+        const double lb = o.form == MD_FORM_INT8_BAL
+                              ? (double)(G + 2 - 8 * S) + __builtin_log2((double)S + 3.0)
+                              : (double)(G - beta * S) + __builtin_log2((double)S + 2.0);
         in->log2_bound = o.force_S > 0 ? 0.0 : __builtin_log2(__builtin_exp2(lb) + __builtin_exp2(-53.0 * m + 0.1));
     }
     return MD_OK;

@@ -76,13 +76,18 @@ hipError_t launch_fill_zero(double* C, int m, int64_t M, int64_t N, int64_t ldc,
 // stats[0..1]: span maxima of A and B (reset by launch_exp_init)
 hipError_t launch_exp_init(int32_t* hi, int32_t* lo, int64_t R, int32_t* stats, hipStream_t st);
 hipError_t launch_exp_partial(const Operand& op, int32_t* hi, int32_t* lo, hipStream_t st);
+// E[r] = shared exponent + eoff (2 for the balanced INT8 digits, else 0);
+// dbgE gets the shared exponent itself
 hipError_t launch_exp_final(const int32_t* hi, const int32_t* lo, int64_t R, int32_t* E,
-                            int32_t* span_max, int32_t* dbgE, hipStream_t st);
+                            int32_t* span_max, int32_t* dbgE, int eoff, hipStream_t st);
 
+// INT8 digits: 7-bit sign-magnitude, or balanced 8-bit (E then holds the
+// shared exponent + 2)
 hipError_t launch_split_i8(const Operand& op, int m, const int32_t* E, int S, int64_t nrb,
-                           int64_t nkc, int8_t* out, int32_t* dbg, hipStream_t st);
-// one INT8 slice of leading-word magnitudes (ratio certificate)
-hipError_t launch_split_mag(const Operand& op, const int32_t* E, int64_t nrb, int64_t nkc,
+                           int64_t nkc, int8_t* out, int32_t* dbg, bool balanced, hipStream_t st);
+// one INT8 slice of leading-word magnitudes (ratio certificate); E holds
+// the shared exponent + eoff
+hipError_t launch_split_mag(const Operand& op, const int32_t* E, int eoff, int64_t nrb, int64_t nkc,
                             int8_t* out, hipStream_t st);
 hipError_t launch_split_f64(const Operand& op, int m, const int32_t* E, int S, int beta,
                             int64_t nrb, int64_t nkc, double* out, int32_t* dbg, hipStream_t st);
@@ -95,10 +100,14 @@ hipError_t launch_mag_min(const void* qA, const void* qB, int64_t M, int64_t N, 
 hipError_t launch_gemm_f64(const GemmArgs& a, hipStream_t st);
 // exact fold and rounding of every output from a.gD (one thread per entry)
 hipError_t launch_gemm_final(const GemmArgs& a, hipStream_t st);
-// whole-triangle INT8 kernels, by range of S (one translation unit each)
+// whole-triangle INT8 kernels, by digit width (7 or 8 bits) and range of S
+// (one translation unit each)
 hipError_t launch_tri_s1_22(const GemmArgs& a, hipStream_t st);
 hipError_t launch_tri_s23_28(const GemmArgs& a, hipStream_t st);
 hipError_t launch_tri_s29_32(const GemmArgs& a, hipStream_t st);
+hipError_t launch_tri8_s1_22(const GemmArgs& a, hipStream_t st);
+hipError_t launch_tri8_s23_28(const GemmArgs& a, hipStream_t st);
+hipError_t launch_tri8_s29_32(const GemmArgs& a, hipStream_t st);
 
 // Batched inner products out_b = sum_k x_bk y_bk: both operands are split
 // with the vectors as rows (fragment layout of op(A)), so block rb of 16

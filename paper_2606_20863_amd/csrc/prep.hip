@@ -18,6 +18,13 @@
 // negative words are each gathered into one W-bit integer (their bits are
 // disjoint, so OR adds them), and digit D j + i is the difference of the
 // i-th beta-bit fields of the two.
+//
+// Balanced INT8 digits (an encoding of the same truncation that uses all
+// 256 int8 values): the grid starts at 2^(E_r + 2) (the exponent array then
+// holds E_r + 2), beta = 8, and the truncated integer
+// X = sum_w sgn(w) floor(|w| 2^(8 S - E_r - 2)) is written as
+// X = sum_s d_s 256^(S-1-s) with d_s in [-128, 127].  |X| < 2^(8S-2), inside
+// what S such digits reach.
 #include "mdgemm_internal.h"
 
 #include <climits>
@@ -123,8 +130,10 @@ __global__ __launch_bounds__(256) void k_exp_partial(Operand op, int32_t* hi, in
     }
 }
 
+// E[r] = the shared exponent plus eoff (the digit grid's start); the debug
+// dump and the spans take the shared exponent itself.
 __global__ void k_exp_final(const int32_t* hi, const int32_t* lo, int64_t R, int32_t* E,
-                            int32_t* span_max, int32_t* dbgE)
+                            int32_t* span_max, int32_t* dbgE, int eoff)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= R)
@@ -132,7 +141,7 @@ __global__ void k_exp_final(const int32_t* hi, const int32_t* lo, int64_t R, int
     const int h = hi[r];
     const int e = h == INT_MIN ? 0 : h;
     const int span = h == INT_MIN ? 0 : h - lo[r];
-    E[r] = e;
+    E[r] = e + eoff;
     if (dbgE)
         dbgE[r] = e;
     atomicMax(span_max, span);
@@ -228,11 +237,89 @@ __global__ __launch_bounds__(256) void k_split_i8(Operand op, const int32_t* E, 
     }
 }
 
+// Balanced INT8 split, same threads and stores as k_split_i8.  Limbs of
+// D = 7 digits (56 bits) go from the least significant end: limb j holds
+// digits [S - 7 (j+1), S - 7 j) (the top limb may reach below s = 0, where
+// the digits are zero).  Its positive and negative words are gathered as in
+// the sign-magnitude split, V = P - N + carry from the limb below, and with
+// the bias 0x80..80 (7 bytes) U = V + bias: byte i of U mod 2^56, top bit
+// flipped, is the digit 128 below it, d_(S - 7 j - 1 - i), and U >> 56 (in
+// {-1, 0, 1}) is carried up.
+template <int MW, int EPT, bool DBG>
+__global__ __launch_bounds__(256) void k_split_i8bal(Operand op, const int32_t* E, int S,
+                                                     int64_t nkc, int8_t* out, int32_t* dbg)
+{
+    constexpr int D = 7, W = 56, parts = 4 / EPT;
+    constexpr int64_t kBias = 0x80808080808080LL;
+    typedef typename Bytes<EPT>::type Store;
+    const int64_t rb = blockIdx.y, kc = blockIdx.x / parts;
+    const int byte0 = EPT * ((int)threadIdx.x + 256 * (int)(blockIdx.x % parts));
+    const int L = byte0 >> 4;                 // fragment lane
+    const int64_t r = rb * kRowBlock + (L & 15);
+    const int64_t kbase = kc * kKcI8 + 16 * (L >> 4) + (byte0 & 15);
+    const bool row_ok = r < op.R;
+    const int Er = row_ok ? E[r] : 0;
+
+    uint64_t mant[EPT][MW];
+    int sh0[EPT][MW];
+    bool neg[EPT][MW];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        const int64_t k = kbase + q;
+        const bool ok = row_ok && k < op.K;
+#pragma unroll
+        for (int w = 0; w < MW; ++w) {
+            const double x = ok ? op.p[w * op.ps + r * op.sr + k * op.sk] : 0.0;
+            int ex;
+            neg[q][w] = decode(x, mant[q][w], ex);
+            sh0[q][w] = ex - Er;
+        }
+    }
+    const uint64_t wmask = (1ull << W) - 1;
+    Store* o = reinterpret_cast<Store*>(out + ((rb * nkc + kc) * (int64_t)S) * 1024 + byte0);
+    int64_t carry[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q)
+        carry[q] = 0;
+    const int nl = (S + D - 1) / D;
+    for (int j = 0; j < nl; ++j) {
+        const int s_end = S - D * j;
+        uint64_t U[EPT];
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            uint64_t P, N;
+            limb_pair<MW>(mant[q], sh0[q], neg[q], 8 * s_end, wmask, P, N);
+            const int64_t u = (int64_t)P - (int64_t)N + carry[q] + kBias;
+            carry[q] = u >> W;
+            U[q] = (uint64_t)u;
+        }
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const int s = s_end - 1 - i;
+            if (s < 0)
+                break;
+            uint32_t packed = 0;
+#pragma unroll
+            for (int q = 0; q < EPT; ++q)
+                packed |= (((uint32_t)(U[q] >> (8 * i)) & 0xffu) ^ 0x80u) << (8 * q);
+            o[(int64_t)s * (1024 / EPT)] = (Store)packed;
+            if (DBG && row_ok) {
+#pragma unroll
+                for (int q = 0; q < EPT; ++q)
+                    if (kbase + q < op.K)
+                        dbg[((int64_t)s * op.R + r) * op.K + kbase + q] =
+                            (int)((U[q] >> (8 * i)) & 0xffu) - 128;
+            }
+        }
+    }
+}
+
 // Magnitude digits for the ratio certificate: q = floor(|a^(0)| 2^(7 - E_r)),
 // in [0, 127] because |a^(0)| < 2^E_r; one slice in INT8 fragment order.
 // Nonoverlapping words give |a| >= |a^(0)| (1 - 2^-52) >= q 2^(E_r - 7) (1 - 2^-52).
-__global__ __launch_bounds__(256) void k_split_mag(Operand op, const int32_t* E, int64_t nkc,
-                                                   int8_t* out)
+// E holds E_r + eoff.
+__global__ __launch_bounds__(256) void k_split_mag(Operand op, const int32_t* E, int eoff,
+                                                   int64_t nkc, int8_t* out)
 {
     const int T = threadIdx.x;
     const int64_t rb = blockIdx.y, kc = blockIdx.x;
@@ -240,7 +327,7 @@ __global__ __launch_bounds__(256) void k_split_mag(Operand op, const int32_t* E,
     const int64_t r = rb * kRowBlock + (L & 15);
     const int64_t kbase = kc * kKcI8 + 16 * (L >> 4) + 4 * (T & 3);
     const bool row_ok = r < op.R;
-    const int Er = row_ok ? E[r] : 0;
+    const int Er = row_ok ? E[r] - eoff : 0;
     uint32_t packed = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -376,11 +463,11 @@ hipError_t launch_exp_partial(const Operand& op, int32_t* hi, int32_t* lo, hipSt
 }
 
 hipError_t launch_exp_final(const int32_t* hi, const int32_t* lo, int64_t R, int32_t* E,
-                            int32_t* span_max, int32_t* dbgE, hipStream_t st)
+                            int32_t* span_max, int32_t* dbgE, int eoff, hipStream_t st)
 {
     const int64_t blocks = std::max<int64_t>((R + 255) / 256, 1);
     hipLaunchKernelGGL(k_exp_final, dim3((unsigned)blocks), dim3(256), 0, st, hi, lo, R, E,
-                       span_max, dbgE);
+                       span_max, dbgE, eoff);
     return hipGetLastError();
 }
 
@@ -389,35 +476,41 @@ constexpr int split_ept(int m) { return m <= 4 ? 4 : (m == 8 ? 2 : 1); }
 
 template <int MW>
 hipError_t split_i8_m(const Operand& op, const int32_t* E, int S, int64_t nrb, int64_t nkc,
-                      int8_t* out, int32_t* dbg, hipStream_t st)
+                      int8_t* out, int32_t* dbg, bool balanced, hipStream_t st)
 {
     constexpr int EPT = split_ept(MW);
     const dim3 grid((unsigned)(nkc * (4 / EPT)), (unsigned)nrb);
-    if (dbg)
+    if (balanced) {
+        if (dbg)
+            hipLaunchKernelGGL((k_split_i8bal<MW, EPT, true>), grid, dim3(256), 0, st, op, E, S, nkc, out, dbg);
+        else
+            hipLaunchKernelGGL((k_split_i8bal<MW, EPT, false>), grid, dim3(256), 0, st, op, E, S, nkc, out, dbg);
+    } else if (dbg) {
         hipLaunchKernelGGL((k_split_i8<MW, EPT, true>), grid, dim3(256), 0, st, op, E, S, nkc, out, dbg);
-    else
+    } else {
         hipLaunchKernelGGL((k_split_i8<MW, EPT, false>), grid, dim3(256), 0, st, op, E, S, nkc, out, dbg);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_split_i8(const Operand& op, int m, const int32_t* E, int S, int64_t nrb,
-                           int64_t nkc, int8_t* out, int32_t* dbg, hipStream_t st)
+                           int64_t nkc, int8_t* out, int32_t* dbg, bool balanced, hipStream_t st)
 {
     switch (m) {
-    case 1: return split_i8_m<1>(op, E, S, nrb, nkc, out, dbg, st);
-    case 2: return split_i8_m<2>(op, E, S, nrb, nkc, out, dbg, st);
-    case 4: return split_i8_m<4>(op, E, S, nrb, nkc, out, dbg, st);
-    case 8: return split_i8_m<8>(op, E, S, nrb, nkc, out, dbg, st);
-    case 16: return split_i8_m<16>(op, E, S, nrb, nkc, out, dbg, st);
+    case 1: return split_i8_m<1>(op, E, S, nrb, nkc, out, dbg, balanced, st);
+    case 2: return split_i8_m<2>(op, E, S, nrb, nkc, out, dbg, balanced, st);
+    case 4: return split_i8_m<4>(op, E, S, nrb, nkc, out, dbg, balanced, st);
+    case 8: return split_i8_m<8>(op, E, S, nrb, nkc, out, dbg, balanced, st);
+    case 16: return split_i8_m<16>(op, E, S, nrb, nkc, out, dbg, balanced, st);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_split_mag(const Operand& op, const int32_t* E, int64_t nrb, int64_t nkc,
+hipError_t launch_split_mag(const Operand& op, const int32_t* E, int eoff, int64_t nrb, int64_t nkc,
                             int8_t* out, hipStream_t st)
 {
     dim3 grid((unsigned)nkc, (unsigned)nrb);
-    hipLaunchKernelGGL(k_split_mag, grid, dim3(256), 0, st, op, E, nkc, out);
+    hipLaunchKernelGGL(k_split_mag, grid, dim3(256), 0, st, op, E, eoff, nkc, out);
     return hipGetLastError();
 }
 

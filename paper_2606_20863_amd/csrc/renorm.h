@@ -2,8 +2,9 @@
 // renormalisation step of the m-double product (the paper's postponed
 // renormalisation, done once per output entry).
 //
-// The value is X 2^scale with X an integer held as 28-bit columns (carried,
-// the top one signed) and then as the magnitude in 32-bit limbs L[0..NL).
+// The value is X 2^scale with X an integer held as 4 beta-bit columns
+// (carried, the top one signed) and then as the magnitude in 32-bit limbs
+// L[0..NL).
 // Word t is RN(X_t 2^scale), X_0 = X, X_(t+1) = X_t - word t, round to
 // nearest with ties to even and the unit clamped at 2^-1074 (subnormal
 // words).  Every limb index is a compile-time constant, so the limbs stay in
@@ -20,24 +21,25 @@ namespace mdg {
 
 __device__ __forceinline__ int imax(int a, int b) { return a > b ? a : b; }
 
-// Register layout for S diagonals at beta = 7: kCols columns of weight
-// 2^(28 j) (the top one takes only carries and is signed) and the kLimbs
-// 32-bit limbs of the magnitude (kCols-1 columns of 28 bits, a top one below
-// 2^64).
-template <int S>
+// Register layout for S diagonals of B-bit digits (B = 7 or 8): four
+// diagonals per column, kCols columns of weight 2^(kCW j) (the top one takes
+// only carries and is signed) and the kLimbs 32-bit limbs of the magnitude
+// (kCols-1 columns of kCW bits, a top one below 2^64).
+template <int S, int B = 7>
 struct Tri {
+    static constexpr int kCW = 4 * B;
     static constexpr int kCols = (S + 3) / 4 + 1;
-    static constexpr int kLimbs = (28 * (kCols - 1) + 64 + 31) / 32;
+    static constexpr int kLimbs = (kCW * (kCols - 1) + 64 + 31) / 32;
 };
 
-// Carry every column but the top one into [0, 2^28).
-template <int NC>
-__device__ __forceinline__ void carry28(int64_t (&x)[NC])
+// Carry every column but the top one into [0, 2^CW).
+template <int CW, int NC>
+__device__ __forceinline__ void carry_cols(int64_t (&x)[NC])
 {
 #pragma unroll
     for (int j = 0; j + 1 < NC; ++j) {
-        x[j + 1] += x[j] >> 28;
-        x[j] &= 0xfffffffLL;
+        x[j + 1] += x[j] >> CW;
+        x[j] &= ((int64_t)1 << CW) - 1;
     }
 }
 
@@ -166,22 +168,22 @@ __device__ __forceinline__ double rn_next(uint32_t (&L)[NL], double& sgn, int& s
     return rn_step(L, sgn, -1074 - scale, scale);
 }
 
-// Magnitude limbs of the carried columns; returns the sign.
-template <int NC, int NL>
+// Magnitude limbs of the carried CW-bit columns; returns the sign.
+template <int CW, int NC, int NL>
 __device__ __forceinline__ bool to_limbs(int64_t (&x)[NC], uint32_t (&L)[NL])
 {
     const bool neg = x[NC - 1] < 0;
 #pragma unroll
     for (int j = 0; j < NC; ++j)
         x[j] = neg ? -x[j] : x[j];
-    carry28(x);
+    carry_cols<CW>(x);
 #pragma unroll
     for (int k = 0; k < NL; ++k)
         L[k] = 0;
 #pragma unroll
     for (int j = 0; j < NC; ++j) {
         const uint64_t v = (uint64_t)x[j];
-        const int b = 28 * j, k = b >> 5, r = b & 31;
+        const int b = CW * j, k = b >> 5, r = b & 31;
         L[k] |= (uint32_t)(v << r);
         if (k + 1 < NL)
             L[k + 1] |= (uint32_t)(r ? v >> (32 - r) : v >> 32);

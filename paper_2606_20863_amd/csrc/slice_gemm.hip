@@ -292,9 +292,18 @@ struct Dispatch<Form, 0> {
 
 hipError_t launch_gemm_i8(const GemmArgs& a, hipStream_t st)
 {
-    // the triangle kernel's register fold holds |X| / 2^(28 ceil(S/4)) < K 2^9
-    // in its signed top column
+    // the triangle kernel's register fold holds |X| / 2^(4 beta ceil(S/4))
+    // < K 2^9 in its signed top column
     if (a.nbands == 1 && a.S <= kTriMaxI8 && a.nkc * kKcI8 < ((int64_t)1 << 48)) {
+        if (a.beta == 8) {
+            if (a.S <= 22)
+                return launch_tri8_s1_22(a, st);
+            if (a.S <= 28)
+                return launch_tri8_s23_28(a, st);
+            return launch_tri8_s29_32(a, st);
+        }
+        if (a.beta != 7)
+            return hipErrorInvalidValue;
         if (a.S <= 22)
             return launch_tri_s1_22(a, st);
         if (a.S <= 28)

@@ -91,15 +91,16 @@ __device__ __forceinline__ void tri_run_i8(v4i (&acc)[R][S], const FragStream (&
     }
 }
 
-// Register-resident fold of the whole-triangle kernel.  There beta = 7 and
-// the band starts at t = 0, so diagonal t lands at bit 7 e, e = S-1-t, which
-// is column e / 4 (weight 2^(28 (e / 4))) shifted left by the static amount
-// 7 (e mod 4).  One depth chunk adds less than 2^31 (1 + 2^7 + 2^14 + 2^21)
-// < 2^53 to a column; after every chunk the columns are carried back to 28
-// bits.  The top column takes only carries and is the signed one.
-// x[4 r + o] holds output o of the lane in row block rb0 + r.
-template <int S, int R, bool DBG>
-__device__ __forceinline__ void tri_fold(const v4i (&acc)[R][S], int64_t (&x)[4 * R][Tri<S>::kCols],
+// Register-resident fold of the whole-triangle kernel for digits of B bits
+// (7: sign-magnitude, 8: balanced).  The band starts at t = 0, so diagonal
+// t lands at bit B e, e = S-1-t, which is column e / 4 (weight
+// 2^(4 B (e / 4))) shifted left by the static amount B (e mod 4).  One depth
+// chunk adds less than 2^31 (1 + 2^B + 2^2B + 2^3B) < 2^56 to a column;
+// after every chunk the columns are carried back to 4 B bits.  The top
+// column takes only carries and is the signed one.  x[4 r + o] holds output
+// o of the lane in row block rb0 + r.
+template <int S, int R, bool DBG, int B>
+__device__ __forceinline__ void tri_fold(const v4i (&acc)[R][S], int64_t (&x)[4 * R][Tri<S, B>::kCols],
                                          const GemmArgs& a, int64_t rb0, int64_t cb, int lane)
 {
 #pragma unroll
@@ -109,7 +110,7 @@ __device__ __forceinline__ void tri_fold(const v4i (&acc)[R][S], int64_t (&x)[4 
         for (int r = 0; r < R; ++r)
 #pragma unroll
             for (int o = 0; o < 4; ++o) {
-                x[4 * r + o][e >> 2] += (int64_t)acc[r][g][o] * ((int64_t)1 << (7 * (e & 3)));
+                x[4 * r + o][e >> 2] += (int64_t)acc[r][g][o] * ((int64_t)1 << (B * (e & 3)));
                 if constexpr (DBG) {
                     const int64_t i = (rb0 + r) * 16 + FormI8::row(lane, o), j = cb * 16 + (lane & 15);
                     if (i < a.M && j < a.N)
@@ -119,15 +120,15 @@ __device__ __forceinline__ void tri_fold(const v4i (&acc)[R][S], int64_t (&x)[4 
     }
 #pragma unroll
     for (int n = 0; n < 4 * R; ++n)
-        carry28(x[n]);
+        carry_cols<Tri<S, B>::kCW>(x[n]);
 }
 
 // Greedy renormalisation of the lane's 4 R outputs, their steps interleaved.
-template <int S, int R>
-__device__ __forceinline__ void tri_outputs(int64_t (&x)[4 * R][Tri<S>::kCols], const GemmArgs& a,
+template <int S, int R, int B>
+__device__ __forceinline__ void tri_outputs(int64_t (&x)[4 * R][(Tri<S, B>::kCols)], const GemmArgs& a,
                                             int64_t rb0, int64_t cb, int lane)
 {
-    constexpr int NL = Tri<S>::kLimbs, NO = 4 * R;
+    constexpr int NL = Tri<S, B>::kLimbs, NO = 4 * R;
     uint32_t L[NO][NL];
     double sgn[NO], *out[NO];
     int scale[NO];
@@ -136,9 +137,9 @@ __device__ __forceinline__ void tri_outputs(int64_t (&x)[4 * R][Tri<S>::kCols], 
     for (int n = 0; n < NO; ++n) {
         const int64_t i = (rb0 + n / 4) * 16 + FormI8::row(lane, n % 4), j = cb * 16 + (lane & 15);
         ok[n] = i < a.M && j < a.N;
-        scale[n] = ok[n] ? a.E[i] + a.F[j] - 7 * (S + 1) : 0;
+        scale[n] = ok[n] ? a.E[i] + a.F[j] - B * (S + 1) : 0;
         out[n] = a.C + (ok[n] ? i * a.ldc + j : 0);
-        sgn[n] = to_limbs(x[n], L[n]) ? -1.0 : 1.0;
+        sgn[n] = to_limbs<Tri<S, B>::kCW>(x[n], L[n]) ? -1.0 : 1.0;
     }
     for (int t = 0; t < a.m; ++t) {
 #pragma unroll
@@ -154,19 +155,20 @@ __device__ __forceinline__ void tri_outputs(int64_t (&x)[4 * R][Tri<S>::kCols], 
 constexpr int kLeadA = 48;
 
 // Whole-triangle INT8 contraction, S <= 32 diagonals in one band, one row
-// block per wave (32 x 32 workgroup tile), any number of exactness chunks.
-template <int S, bool DBG>
+// block per wave (32 x 32 workgroup tile), any number of exactness chunks;
+// B-bit digits.
+template <int S, bool DBG, int B>
 __global__ __launch_bounds__(256, 1) void k_tri_i8(GemmArgs a)
 {
     const WaveTile w(a, 1);
     const uint64_t bytes = (uint64_t)a.nkc * S * 1024;   // one row block of fragments
     const FragStream LA[1] = {frag_stream((const char*)a.A + w.rb * bytes, bytes, w.lane)};
     const FragStream LB = frag_stream((const char*)a.B + w.cb * bytes, bytes, w.lane);
-    int64_t x[4][Tri<S>::kCols];
+    int64_t x[4][Tri<S, B>::kCols];
 #pragma unroll
     for (int o = 0; o < 4; ++o)
 #pragma unroll
-        for (int j = 0; j < Tri<S>::kCols; ++j)
+        for (int j = 0; j < Tri<S, B>::kCols; ++j)
             x[o][j] = 0;
     for (int64_t c0 = 0; c0 < a.nkc; c0 += a.kcc) {
         v4i acc[1][S];
@@ -174,9 +176,9 @@ __global__ __launch_bounds__(256, 1) void k_tri_i8(GemmArgs a)
         for (int g = 0; g < S; ++g)
             acc[0][g] = FormI8::zero();
         tri_run_i8<S, 1, kLeadA>(acc, LA, LB, c0, min(c0 + a.kcc, a.nkc));
-        tri_fold<S, 1, DBG>(acc, x, a, w.rb, w.cb, w.lane);
+        tri_fold<S, 1, DBG, B>(acc, x, a, w.rb, w.cb, w.lane);
     }
-    tri_outputs<S, 1>(x, a, w.rb, w.cb, w.lane);
+    tri_outputs<S, 1, B>(x, a, w.rb, w.cb, w.lane);
 }
 
 // The same with two row blocks per wave (64 x 32 workgroup tile), which
@@ -184,7 +186,7 @@ __global__ __launch_bounds__(256, 1) void k_tri_i8(GemmArgs a)
 // depth is one exactness chunk, so the fold columns exist only after the
 // contraction.  A row block past the digit array (M padded to 32 rows) reads
 // through an empty descriptor: zeros.
-template <int S>
+template <int S, int B>
 __global__ __launch_bounds__(256, 1) void k_tri2_i8(GemmArgs a)
 {
     const WaveTile w(a, 2);
@@ -203,31 +205,31 @@ __global__ __launch_bounds__(256, 1) void k_tri2_i8(GemmArgs a)
         for (int g = 0; g < S; ++g)
             acc[r][g] = FormI8::zero();
     tri_run_i8<S, 2, kLeadA>(acc, LA, LB, 0, a.nkc);
-    int64_t x[8][Tri<S>::kCols];
+    int64_t x[8][Tri<S, B>::kCols];
 #pragma unroll
     for (int n = 0; n < 8; ++n)
 #pragma unroll
-        for (int j = 0; j < Tri<S>::kCols; ++j)
+        for (int j = 0; j < Tri<S, B>::kCols; ++j)
             x[n][j] = 0;
-    tri_fold<S, 2, false>(acc, x, a, w.rb, w.cb, w.lane);
-    tri_outputs<S, 2>(x, a, w.rb, w.cb, w.lane);
+    tri_fold<S, 2, false, B>(acc, x, a, w.rb, w.cb, w.lane);
+    tri_outputs<S, 2, B>(x, a, w.rb, w.cb, w.lane);
 }
 
-// Launch the triangle kernel for a.S in [LO, S]: two row blocks per wave
-// when the whole depth is one exactness chunk (and no debug dump is asked
-// for), else one.
-template <int S, int LO>
+// Launch the triangle kernel for a.S in [LO, S], B-bit digits: two row
+// blocks per wave when the whole depth is one exactness chunk (and no debug
+// dump is asked for), else one.
+template <int S, int LO, int B>
 struct DispatchTriRange {
     static hipError_t run(const GemmArgs& a, hipStream_t st)
     {
         if (a.S == S) {
             if (a.kcc >= a.nkc && !a.dbgD)
-                return launch_kernel(k_tri2_i8<S>, a, st, false, 2 * kTile);
-            return a.dbgD ? launch_kernel(k_tri_i8<S, true>, a, st, false)
-                          : launch_kernel(k_tri_i8<S, false>, a, st, false);
+                return launch_kernel(k_tri2_i8<S, B>, a, st, false, 2 * kTile);
+            return a.dbgD ? launch_kernel(k_tri_i8<S, true, B>, a, st, false)
+                          : launch_kernel(k_tri_i8<S, false, B>, a, st, false);
         }
         if constexpr (S > LO)
-            return DispatchTriRange<S - 1, LO>::run(a, st);
+            return DispatchTriRange<S - 1, LO, B>::run(a, st);
         return hipErrorInvalidValue;
     }
 };

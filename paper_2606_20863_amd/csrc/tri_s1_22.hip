@@ -1,11 +1,12 @@
-// Whole-triangle INT8 slice contraction kernels for S = 1..22.
+// Whole-triangle INT8 slice contraction kernels for S = 1..22, 7-bit
+// sign-magnitude digits.
 #include "tri.h"
 
 namespace mdg {
 
 hipError_t launch_tri_s1_22(const GemmArgs& a, hipStream_t st)
 {
-    return DispatchTriRange<22, 1>::run(a, st);
+    return DispatchTriRange<22, 1, 7>::run(a, st);
 }
 
 }  // namespace mdg

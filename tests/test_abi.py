@@ -95,7 +95,7 @@ def test_dot_argument_errors_before_device_work():
     assert L.md_dot_ex(2, 4, 8, x, 8, 32, y, 8, 32, o, 4, ctypes.byref(opts), None) == 7
 
 
-@pytest.mark.parametrize("form", ["int8", "fp64"])
+@pytest.mark.parametrize("form", ["int8", "int8bal", "fp64"])
 @pytest.mark.parametrize("K", [1, 64, 100, 1024, 2048, 4096, 100000])
 @pytest.mark.parametrize("T,G", [(100, 2), (100, 40), (200, 3), (200, 44), (400, 9), (400, 34)])
 def test_parameter_rule_matches_oracle(form, K, T, G):
@@ -119,3 +119,9 @@ def test_parameter_rule_exactness_and_budget():
                 assert S * kc * (2 ** beta - 1) ** 2 < limit
                 assert S % band == 0 and band <= 16
                 assert beta * S >= T + G + ox.ceil_log2(S + 2) + 1
+    for K in (64, 1000, 4096):
+        for T, G in ((100, 2), (200, 44), (400, 34)):
+            beta, S, kc, band = md.choose_params("int8bal", K, T, G)
+            assert beta == 8 and S * kc * 128 ** 2 < 2 ** 31
+            assert S % band == 0 and (band <= 16 or band == S <= 32)
+            assert 8 * S >= T + G + ox.ceil_log2(S + 3) + 3

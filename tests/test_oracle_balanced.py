@@ -75,10 +75,12 @@ def adversarial_entries(r, m, n):
     X = mdinputs.mdouble(r, m, (1, n), ("log2uniform", 4.0))[:, 0, :]
     for k in range(0, n, 3):
         X[0, k] = np.copysign(np.nextafter(2.0, 0.0), X[0, k])   # (2 - 2^-52), E = 1
+        X[1:, k] = 0.0
         if m > 1:
-            X[1, k] = -np.copysign(2.0 ** -54, X[0, k])           # below half an ulp
+            X[1, k] = -np.copysign(2.0 ** -54, X[0, k])           # half an ulp, other sign
     for k in range(1, n, 5):
         X[1:, k] = 0.0
+    assert all(ox.is_nonoverlapping(X[:, k], strong=True) for k in range(n))
     return X
 
 

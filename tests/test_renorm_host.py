@@ -2,7 +2,8 @@
 
 ``paper_2606_20863_amd/csrc/renorm.h`` holds the exact greedy
 round-to-nearest that the INT8 triangle kernels run in registers: carry the
-28-bit fold columns, take the magnitude in 32-bit limbs, then one rounding
+fold columns (28 bits for 7-bit digits, 32 for the balanced 8-bit ones),
+take the magnitude in 32-bit limbs, then one rounding
 step per word (left-aligned limbs with fixed-place significand, round and
 sticky bits; the general step where a word would be subnormal).  Compiled
 for the host with g++ (the two device annotations defined away), it must
@@ -27,8 +28,9 @@ from oracle import exact as ox
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2606_20863_amd", "csrc")
 
-# S values whose register layouts differ: (columns, limbs) = (2, 3), (5, 6), (9, 9)
-S_VALUES = (4, 16, 30)
+# (S, digit bits) whose register layouts differ: (columns, limbs) =
+# (2, 3), (5, 6), (9, 9) for 28-bit columns, (3, 4), (8, 9) for 32-bit ones
+LAYOUTS = ((4, 7), (16, 7), (30, 7), (5, 8), (27, 8))
 
 DRIVER = r"""
 #define __device__
@@ -36,36 +38,55 @@ DRIVER = r"""
 #include "renorm.h"
 using namespace mdg;
 
-template <int S>
+template <int S, int B>
 static void run(const int64_t* cols, int scale, int m, double* out)
 {
-    int64_t x[Tri<S>::kCols];
-    for (int j = 0; j < Tri<S>::kCols; ++j)
+    typedef Tri<S, B> T;
+    int64_t x[T::kCols];
+    for (int j = 0; j < T::kCols; ++j)
         x[j] = cols[j];
-    carry28(x);
-    uint32_t L[Tri<S>::kLimbs];
-    double sgn = to_limbs(x, L) ? -1.0 : 1.0;
+    carry_cols<T::kCW>(x);
+    uint32_t L[T::kLimbs];
+    double sgn = to_limbs<T::kCW>(x, L) ? -1.0 : 1.0;
     for (int t = 0; t < m; ++t)
         out[t] = rn_next(L, sgn, scale);
 }
 
-extern "C" int layout(int S, int which)
+template <int S, int B>
+static int lay(int which)
 {
-    switch (S) {
-    case 4: return which ? Tri<4>::kLimbs : Tri<4>::kCols;
-    case 16: return which ? Tri<16>::kLimbs : Tri<16>::kCols;
-    case 30: return which ? Tri<30>::kLimbs : Tri<30>::kCols;
-    }
+    return which == 2 ? Tri<S, B>::kCW : (which ? Tri<S, B>::kLimbs : Tri<S, B>::kCols);
+}
+
+extern "C" int layout(int S, int B, int which)
+{
+    if (B == 7)
+        switch (S) {
+        case 4: return lay<4, 7>(which);
+        case 16: return lay<16, 7>(which);
+        case 30: return lay<30, 7>(which);
+        }
+    if (B == 8)
+        switch (S) {
+        case 5: return lay<5, 8>(which);
+        case 27: return lay<27, 8>(which);
+        }
     return -1;
 }
 
-extern "C" void renorm(int S, const int64_t* cols, int scale, int m, double* out)
+extern "C" void renorm(int S, int B, const int64_t* cols, int scale, int m, double* out)
 {
-    switch (S) {
-    case 4: run<4>(cols, scale, m, out); break;
-    case 16: run<16>(cols, scale, m, out); break;
-    case 30: run<30>(cols, scale, m, out); break;
-    }
+    if (B == 7)
+        switch (S) {
+        case 4: run<4, 7>(cols, scale, m, out); break;
+        case 16: run<16, 7>(cols, scale, m, out); break;
+        case 30: run<30, 7>(cols, scale, m, out); break;
+        }
+    if (B == 8)
+        switch (S) {
+        case 5: run<5, 8>(cols, scale, m, out); break;
+        case 27: run<27, 8>(cols, scale, m, out); break;
+        }
 }
 """
 
@@ -79,32 +100,32 @@ def lib(tmp_path_factory):
     subprocess.run(["g++", "-std=c++17", "-O1", "-shared", "-fPIC", "-I", CSRC, str(src), "-o",
                     str(so)], check=True)
     L = ctypes.CDLL(str(so))
-    L.layout.argtypes = [ctypes.c_int, ctypes.c_int]
-    L.renorm.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_int,
-                         ctypes.POINTER(ctypes.c_double)]
+    L.layout.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    L.renorm.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.c_int,
+                         ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
     return L
 
 
-def columns_of(X: int, nc: int):
-    """28-bit columns of X (sign on every column), the top one taking the rest."""
+def columns_of(X: int, nc: int, cw: int = 28):
+    """cw-bit columns of X (sign on every column), the top one taking the rest."""
     s = -1 if X < 0 else 1
     a = abs(X)
-    cols = [(a >> (28 * j)) & ((1 << 28) - 1) for j in range(nc - 1)] + [a >> (28 * (nc - 1))]
+    cols = [(a >> (cw * j)) & ((1 << cw) - 1) for j in range(nc - 1)] + [a >> (cw * (nc - 1))]
     return [s * c for c in cols]
 
 
-def value_of(cols):
-    return sum(c * (1 << (28 * j)) for j, c in enumerate(cols))
+def value_of(cols, cw: int = 28):
+    return sum(c * (1 << (cw * j)) for j, c in enumerate(cols))
 
 
-def cases(rng: random.Random, nc: int, n: int):
+def cases(rng: random.Random, nc: int, n: int, cw: int = 28):
     """(columns, scale, m): the integer stays within what the layout holds
     (top column below 2^62)."""
-    width = 28 * (nc - 1) + 62
+    width = cw * (nc - 1) + 62
     for it in range(n):
         kind = it % 5
         if kind == 0:       # carried columns, random top
-            cols = [rng.randrange(0, 1 << 28) for _ in range(nc - 1)] + [rng.randrange(-(1 << 40), 1 << 40)]
+            cols = [rng.randrange(0, 1 << cw) for _ in range(nc - 1)] + [rng.randrange(-(1 << 40), 1 << 40)]
         elif kind == 1:     # uncarried column sums as a depth chunk leaves them
             cols = [rng.randrange(-(1 << 52), 1 << 52) for _ in range(nc - 1)] + [0]
         elif kind == 2:     # sparse bits: exact ties, runs of ones
@@ -113,13 +134,13 @@ def cases(rng: random.Random, nc: int, n: int):
                 X += rng.choice([1, -1]) * (1 << rng.randrange(0, width - 60))
             if rng.random() < 0.5:
                 X *= (1 << rng.randrange(1, 58)) - 1
-            cols = columns_of(X, nc)
+            cols = columns_of(X, nc, cw)
         elif kind == 3:     # small integers (fewer than 53 bits)
             cols = [rng.randrange(-(1 << 60), 1 << 60)] + [0] * (nc - 1)
         else:               # a random prefix of columns
             k = rng.randrange(1, nc)
             cols = [rng.randrange(-(1 << 52), 1 << 52) for _ in range(k)] + [0] * (nc - k)
-        X = value_of(cols)
+        X = value_of(cols, cw)
         r = rng.random()
         if r < 0.6:
             scale = rng.randrange(-300, 10)
@@ -134,18 +155,18 @@ def same_words(got, ref):
     return all(a == b and np.signbit(a) == np.signbit(b) for a, b in zip(got, ref))
 
 
-@pytest.mark.parametrize("S", S_VALUES)
-def test_renorm_header_matches_oracle(lib, S):
-    nc, nl = lib.layout(S, 0), lib.layout(S, 1)
-    assert nc == (S + 3) // 4 + 1 and nl * 32 >= 28 * (nc - 1) + 64
+@pytest.mark.parametrize("S,B", LAYOUTS)
+def test_renorm_header_matches_oracle(lib, S, B):
+    nc, nl, cw = lib.layout(S, B, 0), lib.layout(S, B, 1), lib.layout(S, B, 2)
+    assert cw == 4 * B and nc == (S + 3) // 4 + 1 and nl * 32 >= cw * (nc - 1) + 64
     rng = random.Random(1000 + S)
     out = (ctypes.c_double * 8)()
     bad = []
-    for cols, scale, m in cases(rng, nc, 2500):
+    for cols, scale, m in cases(rng, nc, 2500, cw):
         arr = (ctypes.c_int64 * nc)(*cols)
-        lib.renorm(S, arr, scale, m, out)
+        lib.renorm(S, B, arr, scale, m, out)
         got = list(out)[:m]
-        ref = ox.renorm_rn(Fraction(value_of(cols)) * Fraction(2) ** scale, m)
+        ref = ox.renorm_rn(Fraction(value_of(cols, cw)) * Fraction(2) ** scale, m)
         if not same_words(got, ref):
             bad.append((cols, scale, m, got, ref))
     assert not bad, bad[:3]
@@ -153,9 +174,10 @@ def test_renorm_header_matches_oracle(lib, S):
 
 def test_renorm_header_zero_and_exact_halves(lib):
     """X = 0 gives +0 words; X = 2^53 + 1 (a tie) rounds to even, leaving +-1."""
-    nc = lib.layout(30, 0)
-    out = (ctypes.c_double * 4)()
-    for X, scale in ((0, 0), ((1 << 53) + 1, 0), (-((1 << 53) + 3), -10), ((1 << 200) - 1, -200)):
-        lib.renorm(30, (ctypes.c_int64 * nc)(*columns_of(X, nc)), scale, 4, out)
-        ref = ox.renorm_rn(Fraction(X) * Fraction(2) ** scale, 4)
-        assert same_words(list(out), ref), (X, list(out), ref)
+    for S, B in ((30, 7), (27, 8)):
+        nc, cw = lib.layout(S, B, 0), lib.layout(S, B, 2)
+        out = (ctypes.c_double * 4)()
+        for X, scale in ((0, 0), ((1 << 53) + 1, 0), (-((1 << 53) + 3), -10), ((1 << 200) - 1, -200)):
+            lib.renorm(S, B, (ctypes.c_int64 * nc)(*columns_of(X, nc, cw)), scale, 4, out)
+            ref = ox.renorm_rn(Fraction(X) * Fraction(2) ** scale, 4)
+            assert same_words(list(out), ref), (S, X, list(out), ref)
