@@ -5,11 +5,12 @@
 One step is one whole m-double product C = A B (exponent alignment, split,
 slice contraction, exact fold, renormalisation) on resident seeded inputs
 (leading words U(-1,1), trailing words scaled by 2^-53 U(-1,1)).  The
-headline value is the INT8-slice form's effective GFLOP/s, 2 M N K / t; the
-FP64-slice form runs beside it with the same slice-count rule and the same
-2^-200 target.  Prints one JSON line.
+headline value is the INT8-slice form's effective GFLOP/s, 2 M N K / t, with
+balanced 8-bit digits (int8bal); the INT8 form with 7-bit sign-magnitude
+digits and the FP64-slice form run beside it with their slice-count rules
+and the same 2^-200 target.  Prints one JSON line.
 
-roofline: the dominant kernel is the slice contraction of the INT8 form;
+roofline: the dominant kernel is the slice contraction of the headline form;
 its algorithmic work per launch is 2 M N K S(S+1)/2 int8 operations (S(S+1)/2
 slice multiply-adds per m-double multiply-add), timed with HIP events on the
 call's stream around that kernel.  cpu_baseline: the exact C oracle on this
@@ -17,12 +18,12 @@ host's cores over a bounded sample of output entries.
 
 ordinary_form: the same product in classical quad-double arithmetic (every
 operation renormalised; the paper's comparison baseline), its time, error
-and the INT8 form's speedup over it.
+and the headline form's speedup over it.
 
 paper_inner_products (skip with --no-dot): the paper's own experiment
 (Section 3, Table 2), 1,024 m-double inner products of length 6,144 on its
 bit pattern for m = 1, 2, 4, 8, 16, through the batched inner-product entry
-point in both slice forms and with the paper's parameters.
+point in the three slice forms and with the paper's parameters.
 """
 from __future__ import annotations
 
@@ -43,7 +44,7 @@ PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 matrix peak, TFLOP/s
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_tri2_i8_qd4096_traffic.md")
 KERNEL_SOURCES = ("csrc/tri.h", "csrc/slice_common.h", "csrc/renorm.h", "csrc/mdgemm_internal.h",
-                  "csrc/tri_s29_32.hip", "build.py")
+                  "csrc/tri8_s23_28.hip", "build.py")
 
 
 def kernel_fingerprint():
@@ -56,12 +57,13 @@ def kernel_fingerprint():
 
 def int8_kernel_name(info, K):
     """The INT8 slice contraction kernel the library dispatches for these
-    parameters: the whole triangle (S <= 32) with two row blocks per wave when
-    the depth is one exactness chunk, else one row block; bands otherwise."""
-    S, band = info["S"], info["band"]
+    parameters (digit width beta = 7 or 8): the whole triangle (S <= 32)
+    with two row blocks per wave when the depth is one exactness chunk, else
+    one row block; bands of two row blocks per wave otherwise."""
+    S, band, b = info["S"], info["band"], info["beta"]
     if band == S and S <= 32:
-        return f"k_tri2_i8<{S}>" if info["kc"] >= K else f"k_tri_i8<{S}, false>"
-    return f"k_slice_gemm<FormI8, {band}, false>"
+        return f"k_tri2_i8<{S}, {b}>" if info["kc"] >= K else f"k_tri_i8<{S}, false, {b}>"
+    return f"k_band2_i8<{band}>"
 
 
 def measured_traffic(kernel: str):
@@ -149,7 +151,7 @@ PAPER_TABLE2_MS = {1: (12, 30), 2: (158, 69), 4: (1977, 318), 8: (6428, 1520), 1
 def paper_inner_products(md, torch, steps=5):
     """The paper's experiment on the GPU: 1,024 inner products of length
     6,144 on the bit pattern, m = 1, 2, 4, 8, 16, through md_dot_ex in the
-    INT8 form and the FP64 form (the library's slice rule) and with the
+    two INT8 forms and the FP64 form (the library's slice rule) and with the
     paper's own parameters (FP64 form, beta = 13, S = 4m).  Whole-call
     milliseconds (inputs resident), the contraction and fold alone from HIP
     events, and the largest error over 8 sampled pairs against the exact
@@ -169,7 +171,8 @@ def paper_inner_products(md, torch, steps=5):
         Ys = np.ascontiguousarray(np.transpose(Y16[:m, pairs, :], (0, 2, 1)))
         row = {"paper_cpu_ms_ordinary": PAPER_TABLE2_MS[m][0],
                "paper_cpu_ms_vectorized": PAPER_TABLE2_MS[m][1]}
-        for label, kw in (("int8", dict(form="int8")), ("fp64", dict(form="fp64")),
+        for label, kw in (("int8bal", dict(form="int8bal")), ("int8", dict(form="int8")),
+                          ("fp64", dict(form="fp64")),
                           ("fp64_paper_params", dict(form="fp64", force_S=4 * m, force_beta=13))):
             md.dot_ex(X, Y, **kw)
             torch.cuda.synchronize()
@@ -219,13 +222,16 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--sm-steps", type=int, default=3,
+                    help="timed calls of the sign-magnitude INT8 form (7-bit digits)")
     ap.add_argument("--ordinary-steps", type=int, default=1,
                     help="timed calls of the ordinary quad-double product (0 skips it)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-dot", action="store_true",
                     help="skip the paper's inner-product workload (m = 1..16)")
-    ap.add_argument("--forms", default="int8,fp64",
-                    help="slice forms to run (int8 is the headline; fp64 runs beside it)")
+    ap.add_argument("--forms", default="int8bal,int8,fp64",
+                    help="slice forms to run (int8bal, the balanced 8-bit digits, is the "
+                         "headline; the sign-magnitude int8 and the fp64 forms run beside it)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="before the timed region, copy 1 GiB device to device once: a plain "
                          "kernel of known traffic for scaling hardware byte counters")
@@ -256,12 +262,19 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    C8, info8, ms8, kern8 = run_form(md, torch, A, B, "int8", args.steps, args.warmup)
+    head = "int8bal" if "int8bal" in forms else "int8"
+    C8, info8, ms8, kern8 = run_form(md, torch, A, B, head, args.steps, args.warmup)
     if "fp64" not in forms:
-        out = {"metric": "QD-GEMM 4096^3 effective GFLOP/s (INT8-slice form only)",
-               "ms_per_call": round(ms8, 4), "gemm_kernel_ms": round(kern8, 4), "S": info8["S"]}
+        out = {"metric": f"QD-GEMM 4096^3 effective GFLOP/s ({head} form only)",
+               "ms_per_call": round(ms8, 4), "gemm_kernel_ms": round(kern8, 4), "S": info8["S"],
+               "kernel": int8_kernel_name(info8, K)}
         print(json.dumps(out))
         return
+    sm = None
+    if head == "int8bal" and "int8" in forms and args.sm_steps > 0:
+        Csm, infosm, mssm, kernsm = run_form(md, torch, A, B, "int8", args.sm_steps, 1)
+        sm = (Csm.cpu().numpy(), infosm, mssm, kernsm)
+        del Csm
     C64, info64, ms64, kern64 = run_form(md, torch, A, B, "fp64", args.fp64_steps, 1)
 
     # the ordinary (classical) quad-double product on the same inputs, the
@@ -296,6 +309,20 @@ def main():
     err8 = accuracy_sample(Ah, Bh, C8h)
     err64 = accuracy_sample(Ah, Bh, C64h)
 
+    def int8_summary(info, ms, kern, err, steps):
+        S = info["S"]
+        ops = flop * S * (S + 1) / 2
+        return {"S": S, "beta": info["beta"], "kc": info["kc"], "band": info["band"],
+                "steps": steps, "ms_per_call": round(ms, 4), "gemm_kernel_ms": round(kern, 4),
+                "kernel": int8_kernel_name(info, K),
+                "effective_gflops": round(flop / (ms * 1e-3) / 1e9, 3),
+                "mfma_int8_tops": round(ops / (kern * 1e-3) / 1e12, 3),
+                "max_log2_err_sampled": round(err, 2),
+                "certified_log2_bound": round(info["log2_bound"], 2)}
+
+    head_form = int8_summary(info8, ms8, kern8, err8, args.steps)
+    head_form["digits"] = ("balanced 8-bit digits in [-128, 127] on the grid 2^(E+2)" if head == "int8bal"
+                           else "7-bit sign-magnitude digits")
     out = {
         "metric": "QD-GEMM 4096^3 effective GFLOP/s: INT8-slice vs FP64-slice MFMA, same error",
         "value": round(eff8, 3),
@@ -313,11 +340,8 @@ def main():
                                "U(-1,1), trailing words 2^-53 U(-1,1)",
                    "M": M, "N": N, "K": K, "m": m, "target_bits": info8["target_bits"],
                    "s_rule": info8.get("rule", "rho")},
-        "int8_form": {"S": S8, "beta": info8["beta"], "kc": info8["kc"], "band": info8["band"],
-                      "ms_per_call": round(ms8, 4), "gemm_kernel_ms": round(kern8, 4),
-                      "effective_gflops": round(eff8, 3),
-                      "max_log2_err_sampled": round(err8, 2),
-                      "certified_log2_bound": round(info8["log2_bound"], 2)},
+        "headline_form": head,
+        f"{head}_form": head_form,
         "fp64_form": {"S": S64, "beta": info64["beta"], "kc": info64["kc"], "band": info64["band"],
                       "steps": args.fp64_steps, "ms_per_call": round(ms64, 4),
                       "gemm_kernel_ms": round(kern64, 4), "effective_gflops": round(eff64, 3),
@@ -325,12 +349,16 @@ def main():
                       "max_log2_err_sampled": round(err64, 2),
                       "certified_log2_bound": round(info64["log2_bound"], 2)},
         "int8_over_fp64": round(eff8 / eff64, 3),
+        "int8_sign_magnitude_form": None if sm is None else dict(
+            int8_summary(sm[1], sm[2], sm[3], accuracy_sample(Ah, Bh, sm[0]), args.sm_steps),
+            digits="7-bit sign-magnitude digits (the paper's bit-field cut)",
+            headline_speedup=round(sm[2] / ms8, 3)),
         "ordinary_form": None if ord_ms is None else {
             "arithmetic": "classical quad-double, every multiply and add renormalised (md_gemm_ordinary)",
             "steps": args.ordinary_steps, "ms_per_call": round(ord_ms, 3),
             "effective_gflops": round(flop / (ord_ms * 1e-3) / 1e9, 3),
             "max_log2_err_sampled": round(accuracy_sample(Ah, Bh, Coh), 2),
-            "int8_form_speedup": round(ord_ms / ms8, 2)},
+            "headline_form_speedup": round(ord_ms / ms8, 2)},
         "roofline": {"bound": "mfma", "kernel": kname8,
                      "achieved": round(ach8, 3), "peak": PEAK_INT8_TOPS, "unit": "TFLOP/s",
                      "frac": round(ach8 / PEAK_INT8_TOPS, 4), "traffic": traffic8,
