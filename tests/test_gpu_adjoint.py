@@ -10,8 +10,9 @@ dA* = W B^T and dB* = A^T W (bilinear).  Checks:
   against quad-double central differences with step 2^-40 (the perturbed
   row or column of C recomputed as a quad-double product; the loss sums
   exact);
-* octo-double 1024^3 (INT8 form): 64 sampled entries of each gradient within
-  2^-400 of the exact gradient (central differences cannot resolve 2^-400).
+* octo-double 1024^3 (both INT8 forms): 64 sampled entries of each gradient
+  within 2^-400 of the exact gradient (central differences cannot resolve
+  2^-400).
 """
 from fractions import Fraction
 
@@ -53,7 +54,8 @@ def tr(X):
 
 
 @pytest.mark.parametrize("form,name", [("fp64", "dd64"), ("int8", "dd64"), ("int8", "qd1024"),
-                                       ("fp64", "od1024")])
+                                       ("fp64", "od1024"), ("int8bal", "qd1024"),
+                                       ("int8bal", "od1024")])
 def test_adjoint_small_bitexact(form, name):
     A, B, W = mdinputs.workload(name, M=23, N=31, K=40, with_w=True)
     m = A.shape[0]
@@ -63,10 +65,11 @@ def test_adjoint_small_bitexact(form, name):
     C = md.MDGemm.apply(tA, tB, form)
     C.backward(dev(W))
     dA, dB = host(tA.grad), host(tB.grad)
+    bal = form == "int8bal"
     beta, S = rule_params(W, tr(B), form, T)
-    np.testing.assert_array_equal(dA, ox.method_product(W, tr(B), beta, S)["C"])
+    np.testing.assert_array_equal(dA, ox.method_product(W, tr(B), beta, S, balanced=bal)["C"])
     beta, S = rule_params(tr(A), W, form, T)
-    np.testing.assert_array_equal(dB, ox.method_product(tr(A), W, beta, S)["C"])
+    np.testing.assert_array_equal(dB, ox.method_product(tr(A), W, beta, S, balanced=bal)["C"])
     # and within 2^-T of the exact gradients
     (ga, La), (gb, Lb) = ox.exact_gradients(A, B, W)
     ab, _ = ox.abs_product(W, tr(B))
@@ -141,13 +144,14 @@ def test_dd2048_forward_adjoint_fp64():
         assert diff <= Fraction(abs_b[e]) * Fraction(1, 1 << 99), (k, j)
 
 
-def test_od1024_forward_adjoint_int8():
+@pytest.mark.parametrize("form", ["int8", "int8bal"])
+def test_od1024_forward_adjoint_int8(form):
     A, B, W = mdinputs.workload("od1024", with_w=True)
     M, K = A.shape[1], A.shape[2]
     N = B.shape[2]
     tA = dev(A).requires_grad_(True)
     tB = dev(B).requires_grad_(True)
-    C = md.MDGemm.apply(tA, tB, "int8")
+    C = md.MDGemm.apply(tA, tB, form)
     C.backward(dev(W))
     Ch, dA, dB = host(C), host(tA.grad), host(tB.grad)
     ii, jj = sample(64, M, 7), sample(64, N, 8)

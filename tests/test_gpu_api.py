@@ -19,7 +19,7 @@ def host(t):
     return t.cpu().numpy()
 
 
-@pytest.mark.parametrize("form", ["int8", "fp64"])
+@pytest.mark.parametrize("form", ["int8", "int8bal", "fp64"])
 def test_caller_workspace(form):
     """With a workspace of md_workspace_size bytes the library allocates
     nothing and gives the same words; a workspace too small is MD_ENOMEM."""
@@ -48,6 +48,18 @@ def test_workspace_covers_the_global_fold():
     assert nbytes >= info["S"] * 24 * 20 * 8
     ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     C, _ = md.gemm_ex(dev(A), dev(B), form="fp64", workspace=ws)
+    np.testing.assert_array_equal(host(C), host(ref))
+
+
+def test_workspace_covers_the_int8_sum_buffer():
+    """Octo-double balanced INT8 (S > 32, bands): the diagonal-sum buffer of
+    the banded kernels is part of md_workspace_size."""
+    A, B = mdinputs.workload("od1024", M=70, N=36, K=90)
+    ref, info = md.gemm_ex(dev(A), dev(B), form="int8bal")
+    assert info["S"] > 32
+    nbytes = md.lib().md_workspace_size(md._FORMS["int8bal"], 70, 36, 90, info["S"])
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    C, _ = md.gemm_ex(dev(A), dev(B), form="int8bal", workspace=ws)
     np.testing.assert_array_equal(host(C), host(ref))
 
 
