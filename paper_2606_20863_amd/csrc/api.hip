@@ -507,13 +507,13 @@ int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, c
     int64_t* gD = nullptr;
     const int gR = is_i8(o.form) ? 2 : 1;   // row blocks per wave of the banded kernels
     if (global_fold) {
+        // every slot is written by the first exactness chunk of its band:
+        // no clearing
         const int64_t n = gd_elements(M, N, S, gR);
         void* p;
         if ((rc = scr.get((size_t)n * sizeof(int64_t), &p)))
             return rc;
         gD = (int64_t*)p;
-        if ((e = launch_fill_zero_i64(gD, n, st)) != hipSuccess)
-            return hip_fail(e);
     }
     GemmArgs ga;
     ga.A = dA;

@@ -51,9 +51,10 @@ struct GemmArgs {
     int S, beta, band, nbands, m;
     int ncol;               // 32-bit columns of the exact fold accumulator
     int64_t* dbgD;          // optional [S][M][N]
-    // Diagonal-sum buffer, zeroed: when set, the banded kernels add their
-    // diagonal sums here instead of folding in LDS, and launch_gemm_final
-    // folds and rounds afterwards.  Tile-private layout: wave w of workgroup
+    // Diagonal-sum buffer: when set, the banded kernels add their diagonal
+    // sums here instead of folding in LDS (the first exactness chunk masks
+    // the old contents to zero; every slot belongs to one band, so it needs
+    // no clearing), and launch_gemm_final folds and rounds afterwards.  Tile-private layout: wave w of workgroup
     // tile (ty, tx) (gx = ceil(N/32) tiles per row, tiles of 32 gR rows)
     // keeps per diagonal t its 64 lanes x 4 gR consecutive int64, slot
     // r*4 + o holding output o of the lane in its row block r:

@@ -453,10 +453,12 @@ __device__ __forceinline__ int64_t* gd_lane(const GemmArgs& a, const WaveTile& w
 // also add them into the debug buffer (a separate instantiation, so that the
 // production kernels carry no debug addressing).  GLOBAL kernels (one row
 // block per wave) only add them into the lane's slots of a.gD (private to
-// the lane, so the read-modify-writes do not race) and keep no LDS fold.
+// the lane, so the read-modify-writes do not race) and keep no LDS fold; the
+// first exactness chunk (first) masks the old contents to zero, and as every
+// slot belongs to one band the buffer needs no clearing.
 template <class Form, int G, bool DBG, bool GLOBAL = false>
 __device__ __forceinline__ void fold_chunk(const typename Form::acc (&acc)[G], int t0,
-                                           const GemmArgs& a, const WaveTile& w)
+                                           const GemmArgs& a, const WaveTile& w, bool first = false)
 {
 #pragma unroll
     for (int g = 0; g < G; ++g) {
@@ -466,7 +468,8 @@ __device__ __forceinline__ void fold_chunk(const typename Form::acc (&acc)[G], i
         for (int o = 0; o < 4; ++o) {
             const int64_t v = Form::value(acc[g], o);
             if constexpr (GLOBAL) {
-                gd_lane(a, w)[(int64_t)t * 256 + o] += v;
+                int64_t* d = gd_lane(a, w) + (int64_t)t * 256 + o;
+                *d = (*d & (first ? 0 : -1)) + v;
             } else {
                 fold_add(w.cols, o, v, p);
                 if constexpr (DBG) {

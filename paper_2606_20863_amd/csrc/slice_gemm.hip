@@ -35,49 +35,11 @@ __global__ __launch_bounds__(256, 1) void k_slice_gemm(GemmArgs a)
                 for (int64_t kc = c0; kc < c1; ++kc)
                     band_chunk<Form, G>(acc, Ab + kc * fstride, Bb + kc * fstride, t0);
             }
-            fold_chunk<Form, G, DBG, GLOBAL>(acc, t0, a, w);
+            fold_chunk<Form, G, DBG, GLOBAL>(acc, t0, a, w, c0 == 0);
         }
     }
     if constexpr (!GLOBAL)
         write_outputs<Form>(a, w);
-}
-
-// Fold and round every output from the diagonal sums in a.gD: one thread per
-// entry, its fold columns in LDS (ncol x 256).  The entry's place in the
-// buffer's layout: tile (i / 32R, j / 32); wave (row half, column half); row
-// block r within the wave; lane and accumulator element o from the matrix
-// cores' row mapping (INT8: row 4 (lane/16) + o; FP64: row 4 o + lane/16).
-// With a debug buffer the sums are also written there as [S][M][N].
-__global__ __launch_bounds__(256) void k_gemm_final(GemmArgs a)
-{
-    extern __shared__ int64_t lds[];
-    const int t = threadIdx.x;
-    const int64_t e = (int64_t)blockIdx.x * 256 + t;
-    const int64_t MN = a.M * a.N;
-    const bool ok = e < MN;
-    const int64_t i = ok ? e / a.N : 0, j = ok ? e % a.N : 0;
-    const int R = a.gR;
-    const int64_t gx = (a.N + kTile - 1) / kTile;
-    const int64_t ty = i / (kTile * R), tx = j / kTile;
-    const int ir = (int)(i % (kTile * R)), jc = (int)(j % kTile);
-    const int wave = (ir / (16 * R)) * 2 + jc / 16;
-    const int r = (ir % (16 * R)) / 16, i16 = ir % 16;
-    const int lane = (jc % 16) + 16 * (a.gI8 ? i16 / 4 : i16 % 4);
-    const int o = a.gI8 ? i16 % 4 : i16 / 4;
-    const int64_t* src = a.gD + ((((ty * gx + tx) * 4 + wave) * (int64_t)a.S) * 64 + lane) * (4 * R) +
-                         r * 4 + o;
-    int64_t* cols = lds + t;
-    for (int q = 0; q < a.ncol; ++q)
-        cols[q * 256] = 0;
-    if (ok)
-        for (int s = 0; s < a.S; ++s) {
-            const int64_t v = src[(int64_t)s * 256 * R];
-            fold_add(cols, 0, v, a.beta * (a.S - 1 - s));
-            if (a.dbgD)
-                a.dbgD[(int64_t)s * MN + e] = v;
-        }
-    const int scale = ok ? a.E[i] + a.F[j] - a.beta * (a.S + 1) : 0;
-    renormalise(cols, a.ncol, scale, a.m, ok ? a.C + i * a.ldc + j : nullptr, a.psc, ok);
 }
 
 // INT8 bands with R row blocks of op(A) sharing one window of B fragments
@@ -216,7 +178,9 @@ __device__ __forceinline__ void band_run_r(v4i (&acc)[R][G], const FragStream (&
 
 // Banded INT8 contraction (S > 32 diagonals, bands of G) with two row blocks
 // per wave, 64 x 32 workgroup tiles; the diagonal sums of every exactness
-// chunk are added into a.gD, which launch_gemm_final folds and rounds.
+// chunk are added into a.gD (the first chunk masks the old contents to zero:
+// every slot belongs to exactly one band, so the buffer needs no clearing),
+// and launch_gemm_final folds and rounds.
 template <int G>
 __global__ __launch_bounds__(256, 1) void k_band2_i8(GemmArgs a)
 {
@@ -242,13 +206,14 @@ __global__ __launch_bounds__(256, 1) void k_band2_i8(GemmArgs a)
             // the lane's eight slots of each diagonal (private, padded: no
             // bounds checks), one diagonal at a time
             int64_t* D = gd_lane(a, w) + (int64_t)t0 * 512;
+            const int64_t keep = c0 == 0 ? 0 : -1;   // the first chunk overwrites
 #pragma unroll
             for (int g = 0; g < G; ++g) {
 #pragma unroll
                 for (int r = 0; r < 2; ++r)
 #pragma unroll
                     for (int o = 0; o < 4; ++o)
-                        D[r * 4 + o] += acc[r][g][o];
+                        D[r * 4 + o] = (D[r * 4 + o] & keep) + acc[r][g][o];
                 D += 512;
                 __builtin_amdgcn_sched_barrier(0);
             }
@@ -321,18 +286,5 @@ hipError_t launch_gemm_f64(const GemmArgs& a, hipStream_t st)
     return Dispatch<FormF64, kGmaxF64>::run(a, st);
 }
 
-hipError_t launch_gemm_final(const GemmArgs& a, hipStream_t st)
-{
-    const size_t lds = (size_t)a.ncol * 256 * sizeof(int64_t);
-    if (lds > 64 * 1024) {
-        const hipError_t e = hipFuncSetAttribute((const void*)k_gemm_final,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess)
-            return e;
-    }
-    const int64_t blocks = (a.M * a.N + 255) / 256;
-    hipLaunchKernelGGL(k_gemm_final, dim3((unsigned)blocks), dim3(256), lds, st, a);
-    return hipGetLastError();
-}
 
 }  // namespace mdg
