@@ -271,3 +271,25 @@ def test_qd1024_workload_sampled(form):
     _, absab, err = coracle.exact_entries(A, B, ii, jj, Cq)
     rel = np.abs(err) / absab
     assert np.all(rel <= 2.0 ** -200), np.log2(rel.max())
+
+
+@pytest.mark.parametrize("form", ["int8", "fp64"])
+def test_qd4096_benchmark_workload_sampled(form):
+    """The quad-double 4096^3 benchmark product in the launch configuration
+    the benchmark times for these two forms: a 16 x 16 grid of entries
+    bit-exact against the C oracle's method layer and within 2^-200 of the
+    exact product."""
+    A, B = mdinputs.workload("qd4096")
+    C, info = md.gemm_ex(dev(A), dev(B), form=form)
+    C = host(C)
+    assert info["S"] == (30 if form == "int8" else 10)
+    rows = np.linspace(0, 4095, 16).astype(np.int64)
+    cols = np.linspace(0, 4095, 16).astype(np.int64)
+    _, _, _, Cref = coracle.method_entries(A, B, info["beta"], info["S"], rows, cols)
+    np.testing.assert_array_equal(C[:, rows][:, :, cols], Cref)
+    ii, jj = np.meshgrid(rows, cols, indexing="ij")
+    ii, jj = ii.ravel(), jj.ravel()
+    Cq = np.ascontiguousarray(np.transpose(C[:, ii, jj], (1, 0)))
+    _, absab, err = coracle.exact_entries(A, B, ii, jj, Cq)
+    rel = np.abs(err) / absab
+    assert np.all(rel <= 2.0 ** -200), np.log2(rel.max())
