@@ -91,16 +91,17 @@ def test_dot_equals_gemm_diagonal(form, S, beta):
     np.testing.assert_array_equal(host(out), C[:, np.arange(40), np.arange(40)])
 
 
+@pytest.mark.parametrize("form", ["int8", "int8bal"])
 @pytest.mark.parametrize("m,nb", [(4, 1024), (16, 256)])
-def test_dot_paper_workload_sampled(m, nb):
+def test_dot_paper_workload_sampled(m, nb, form):
     """Inner products of length 6,144 on the bit pattern (the paper's Table 2
     workload: 1,024 pairs; 256 at m = 16 to bound the generator's host
-    memory), INT8 form: 16 sampled pairs bit-exact against the C oracle's
-    method and within 2^-T of the exact products."""
+    memory), both INT8 forms: 16 sampled pairs bit-exact against the C
+    oracle's method and within 2^-T of the exact products."""
     r = rng(400 + m)
     X, _, _ = mdinputs.paper_pattern(r, m, (nb, 6144))
     Y, _, _ = mdinputs.paper_pattern(r, m, (nb, 6144))
-    out, info = md.dot_ex(dev(X), dev(Y), form="int8")
+    out, info = md.dot_ex(dev(X), dev(Y), form=form)
     out = host(out)
     pairs = np.linspace(0, nb - 1, 16).astype(np.int64)
     Xs = np.ascontiguousarray(X[:, pairs, :])
@@ -108,7 +109,7 @@ def test_dot_paper_workload_sampled(m, nb):
     idx = np.arange(len(pairs), dtype=np.int64)
     for a in idx:
         _, _, _, Cref = coracle.method_entries(Xs, Ys, info["beta"], info["S"], idx[a:a + 1],
-                                               idx[a:a + 1])
+                                               idx[a:a + 1], balanced=form == "int8bal")
         np.testing.assert_array_equal(out[:, pairs[a]], Cref[:, 0, 0])
     Cq = np.ascontiguousarray(out[:, pairs].T)
     _, absab, err = coracle.exact_entries(Xs, Ys, idx, idx, Cq)
