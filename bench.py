@@ -20,6 +20,10 @@ ordinary_form: the same product in classical quad-double arithmetic (every
 operation renormalised; the paper's comparison baseline), its time, error
 and the headline form's speedup over it.
 
+configs (skip with --no-configs): the other workloads of the scope, quad-double
+1024^3, double-double 2048^3 and octo-double 1024^3 with the adjoint (three
+products per step), hexa-double 1024^3, in the slice forms that apply.
+
 paper_inner_products (skip with --no-dot): the paper's own experiment
 (Section 3, Table 2), 1,024 m-double inner products of length 6,144 on its
 bit pattern for m = 1, 2, 4, 8, 16, through the batched inner-product entry
@@ -198,6 +202,80 @@ def paper_inner_products(md, torch, steps=5):
             "target_bits": "50 m", "results": rows}
 
 
+def other_configs(md, torch, steps=3):
+    """The scope's other workloads, each timed as whole steps (inputs
+    resident): quad-double 1024^3 forward; double-double 2048^3 and
+    octo-double 1024^3 forward + adjoint (C = A B, dA = W B^T, dB = A^T W:
+    three products per step); hexa-double 1024^3 forward (leading words
+    2^U(-6,6), seed 16).  Per form: milliseconds per step, effective GFLOP/s
+    (2 M N K per product), the slice contractions with their folds from HIP
+    events, their fraction of the matrix-core peak (algorithmic work
+    2 M N K S(S+1)/2 per product), and the largest error of 64 sampled
+    forward entries against the exact product (C oracle)."""
+    import numpy as np
+    import mdinputs
+    hip, _ = hip_events(1)
+    r16 = np.random.Generator(np.random.PCG64(16))
+    cases = [
+        ("qd1024", "quad-double 1024^3, forward", lambda: mdinputs.workload("qd1024", with_w=True),
+         False, ("int8bal", "int8", "fp64")),
+        ("dd2048", "double-double 2048^3, forward + adjoint", lambda: mdinputs.workload("dd2048", with_w=True),
+         True, ("fp64", "int8bal")),
+        ("od1024", "octo-double 1024^3, forward + adjoint", lambda: mdinputs.workload("od1024", with_w=True),
+         True, ("int8bal", "int8", "fp64")),
+        ("hd1024", "hexa-double 1024^3 (leading words 2^U(-6,6)), forward",
+         lambda: (mdinputs.mdouble(r16, 16, (1024, 1024), ("log2uniform", 6.0)),
+                  mdinputs.mdouble(r16, 16, (1024, 1024), ("log2uniform", 6.0)), None),
+         False, ("int8bal", "int8", "fp64")),
+    ]
+    res = {}
+    for name, label, make, adjoint, forms in cases:
+        Ah, Bh, Wh = make()
+        A = torch.from_numpy(Ah).cuda()
+        B = torch.from_numpy(Bh).cuda()
+        W = torch.from_numpy(Wh).cuda() if adjoint else None
+        calls = [dict(A=A, B=B)]
+        if adjoint:
+            calls += [dict(A=W, B=B, transB=True), dict(A=A, B=W, transA=True)]
+        m, M, K = Ah.shape
+        N = Bh.shape[2]
+        flop = 2.0 * M * N * K * len(calls)
+        row = {"label": label, "m": m}
+        for form in forms:
+            for c in calls:
+                C, _ = md.gemm_ex(c["A"], c["B"], transA=c.get("transA", False),
+                                  transB=c.get("transB", False), form=form)
+            torch.cuda.synchronize()
+            _, evs = hip_events(steps * len(calls))
+            t0 = time.perf_counter()
+            infos = []
+            for st in range(steps):
+                for q, c in enumerate(calls):
+                    Cq, info = md.gemm_ex(c["A"], c["B"], transA=c.get("transA", False),
+                                          transB=c.get("transB", False), form=form,
+                                          events=evs[st * len(calls) + q])
+                    if q == 0:
+                        C = Cq
+                    infos.append(info)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / steps
+            kern = sum(elapsed_ms(hip, e) for e in evs) / steps
+            for a, b in evs:
+                hip.hipEventDestroy(ctypes.c_void_p(a))
+                hip.hipEventDestroy(ctypes.c_void_p(b))
+            ops = sum(2.0 * M * N * K * i["S"] * (i["S"] + 1) / 2 for i in infos[:len(calls)])
+            peak = PEAK_FP64_TFLOPS if form == "fp64" else PEAK_INT8_TOPS
+            row[form] = {"S": [i["S"] for i in infos[:len(calls)]], "beta": infos[0]["beta"],
+                         "ms_per_step": round(ms, 4), "effective_gflops": round(flop / (ms * 1e-3) / 1e9, 2),
+                         "contraction_fold_ms": round(kern, 4),
+                         "frac_peak": round(ops / (kern * 1e-3) / 1e12 / peak, 4),
+                         "max_log2_err_sampled": round(accuracy_sample(Ah, Bh, C.cpu().numpy()), 2)}
+        res[name] = row
+        del A, B, W, calls, C
+        torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(A, B, K):
     """The exact C oracle on whole output rows of the same product."""
     import numpy as np
@@ -229,6 +307,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-dot", action="store_true",
                     help="skip the paper's inner-product workload (m = 1..16)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other workloads (qd1024, dd2048 and od1024 with the adjoint, hd1024)")
     ap.add_argument("--forms", default="int8bal,int8,fp64",
                     help="slice forms to run (int8bal, the balanced 8-bit digits, is the "
                          "headline; the sign-magnitude int8 and the fp64 forms run beside it)")
@@ -369,6 +449,11 @@ def main():
         del A, B, C8, C64
         torch.cuda.empty_cache()
         out["paper_inner_products"] = paper_inner_products(md, torch)
+    if not args.no_configs:
+        if args.no_dot:
+            del A, B, C8, C64
+            torch.cuda.empty_cache()
+        out["configs"] = other_configs(md, torch)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(Ah, Bh, K)
     print(json.dumps(out))
