@@ -182,9 +182,10 @@ int md_dot(int m, int64_t batch, int64_t n, const double *X, const double *Y, do
  * The comparison baseline (paper, Section 1, Table 1, and the "ordinary"
  * columns of Table 2): C = A B in ordinary m-double arithmetic, every
  * multiplication and addition renormalised to m words, each entry
- * accumulated over k in increasing order from zero.  m = 2 (accurate
- * double-double addition, Dekker-product multiplication) or 4 (quad-double
- * operations grouped by order, one renormalisation each); no fused
+ * accumulated over k in increasing order from zero.  m = 1 (plain double
+ * arithmetic), 2 (accurate double-double addition, Dekker-product
+ * multiplication) or 4 (quad-double operations grouped by order, one
+ * renormalisation each); no fused
  * multiply-add.  Not error-free: the error grows with K.  Dense planes as
  * md_gemm; C must not overlap A or B.  M = 0 or N = 0 is a no-op; K = 0
  * writes zeros.  Return codes as md_gemm (MD_EINVAL_M for other m).

@@ -177,11 +177,21 @@ def qd_mul(c: Counter, x, y):
     return renorm5(c, p0, r1, r2, r3, 0.0)
 
 
-ORDINARY = {2: (dd_add, dd_mul), 4: (qd_add, qd_mul)}
+def d_add(c: Counter, x, y):
+    """Ordinary 1-double addition: one IEEE rounding."""
+    return (c.add(x[0], y[0]),)
+
+
+def d_mul(c: Counter, x, y):
+    """Ordinary 1-double multiplication: one IEEE rounding."""
+    return (c.mul(x[0], y[0]),)
+
+
+ORDINARY = {1: (d_add, d_mul), 2: (dd_add, dd_mul), 4: (qd_add, qd_mul)}
 
 
 def ordinary_dot(c: Counter, xs, ys, m: int):
-    """sum_k x_k * y_k in ordinary m-double arithmetic (m = 2, 4): the
+    """sum_k x_k * y_k in ordinary m-double arithmetic (m = 1, 2, 4): the
     accumulator starts at zero and takes add(acc, mul(x_k, y_k)) for k in
     increasing order, each operation renormalised."""
     add, mul = ORDINARY[m]

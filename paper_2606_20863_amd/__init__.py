@@ -252,7 +252,7 @@ def dot(X: torch.Tensor, Y: torch.Tensor, form: str = "fp64", stream=None) -> to
 
 
 def gemm_ordinary(A: torch.Tensor, B: torch.Tensor, stream=None) -> torch.Tensor:
-    """C = A B in ordinary m-double arithmetic (m = 2, 4), every operation
+    """C = A B in ordinary m-double arithmetic (m = 1, 2, 4), every operation
     renormalised: the comparison baseline, not error-free."""
     _check_planes(A, "A")
     _check_planes(B, "B")

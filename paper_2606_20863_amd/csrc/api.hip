@@ -801,7 +801,7 @@ int md_gemm_ordinary(int m, int64_t M, int64_t N, int64_t K, const double* A, co
                      double* C, void* stream)
 {
     g_last_hip = 0;
-    if (m != 2 && m != 4)
+    if (m != 1 && m != 2 && m != 4)
         return MD_EINVAL_M;
     if (M < 0 || N < 0 || K < 0)
         return MD_EINVAL_DIM;

@@ -4,7 +4,7 @@
 //
 //   C_ij = add(...add(add(0, mul(a_i0, b_0j)), mul(a_i1, b_1j))..., mul(a_i,K-1, b_K-1,j))
 //
-// accumulated in increasing k.  The building blocks are the published
+// accumulated in increasing k (m = 1: plain double arithmetic).  The building blocks are the published
 // error-free transformations: Knuth's TwoSum, Dekker's Fast2Sum, Veltkamp's
 // split and Dekker's product (no fused multiply-add: the library is built
 // with contraction off, so every operation is one IEEE rounding).
@@ -69,6 +69,21 @@ __device__ __forceinline__ void three_sum(double a, double b, double d, double& 
 
 template <int MW>
 struct Ordinary;
+
+// m = 1: plain IEEE double arithmetic
+template <>
+struct Ordinary<1> {
+    static __device__ __forceinline__ void add(const double (&x)[1], const double (&y)[1],
+                                               double (&r)[1])
+    {
+        r[0] = x[0] + y[0];
+    }
+    static __device__ __forceinline__ void mul(const double (&x)[1], const double (&y)[1],
+                                               double (&r)[1])
+    {
+        r[0] = x[0] * y[0];
+    }
+};
 
 template <>
 struct Ordinary<2> {
@@ -217,7 +232,9 @@ hipError_t launch_ordinary(int m, const double* A, const double* B, double* C, i
                            int64_t N, int64_t K, hipStream_t st)
 {
     const dim3 grid((unsigned)(((N + kOrdTile - 1) / kOrdTile) * ((M + kOrdTile - 1) / kOrdTile)));
-    if (m == 2)
+    if (m == 1)
+        hipLaunchKernelGGL(k_ordinary<1>, grid, dim3(256), 0, st, A, M * K, B, K * N, C, M * N, M, N, K);
+    else if (m == 2)
         hipLaunchKernelGGL(k_ordinary<2>, grid, dim3(256), 0, st, A, M * K, B, K * N, C, M * N, M, N, K);
     else if (m == 4)
         hipLaunchKernelGGL(k_ordinary<4>, grid, dim3(256), 0, st, A, M * K, B, K * N, C, M * N, M, N, K);

@@ -83,7 +83,7 @@ def test_qd_ops_on_double_doubles():
         assert abs(val(p) - val(q)) <= Fraction(2) ** -100 * ref
 
 
-@pytest.mark.parametrize("m", [2, 4])
+@pytest.mark.parametrize("m", [1, 2, 4])
 def test_ordinary_dot_bound(m):
     r = rng(10 + m)
     K = 64
@@ -100,6 +100,21 @@ def test_ordinary_dot_bound(m):
     c = ma.Counter()
     two = add(c, add(c, (0.0,) * m, mul(c, xs[0], ys[0])), mul(c, xs[1], ys[1]))
     assert ma.ordinary_dot(ma.Counter(), xs[:2], ys[:2], m) == two
+
+
+def test_ordinary_doubles_are_ieee():
+    """m = 1: the ordinary product is plain double arithmetic, summed left to
+    right (numpy's float64 scalars give the same IEEE roundings)."""
+    r = rng(30)
+    A = mdinputs.mdouble(r, 1, (3, 40), ("log2uniform", 6.0))
+    B = mdinputs.mdouble(r, 1, (40, 2), ("log2uniform", 6.0))
+    C = ma.ordinary_gemm(A, B)
+    for i in range(3):
+        for j in range(2):
+            acc = np.float64(0.0)
+            for k in range(40):
+                acc = acc + np.float64(A[0, i, k]) * np.float64(B[0, k, j])
+            assert C[0, i, j] == acc
 
 
 def test_ordinary_gemm_entries():
