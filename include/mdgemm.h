@@ -185,8 +185,8 @@ int md_dot(int m, int64_t batch, int64_t n, const double *X, const double *Y, do
  * accumulated over k in increasing order from zero.  m = 1 (plain double
  * arithmetic), 2 (accurate double-double addition, Dekker-product
  * multiplication) or 4 (quad-double operations grouped by order, one
- * renormalisation each); no fused
- * multiply-add.  Not error-free: the error grows with K.  Dense planes as
+ * renormalisation each); no fused multiply-add.  Not error-free: the error
+ * grows with K.  Dense planes as
  * md_gemm; C must not overlap A or B.  M = 0 or N = 0 is a no-op; K = 0
  * writes zeros.  Return codes as md_gemm (MD_EINVAL_M for other m).
  */
