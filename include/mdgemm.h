@@ -35,7 +35,10 @@
  * Data layout: component planes.  Word w of entry (r, c) of a matrix X is at
  * X[w * plane_stride + r * ld + c]; all pointers are DEVICE pointers to
  * doubles; the words of an entry must be nonoverlapping (decreasing, with
- * disjoint bit ranges; zero words only at the tail) and finite.
+ * disjoint bit ranges; zero words only at the tail) and finite, and a
+ * nonzero leading word must lie in [2^-900, 2^900).  These preconditions are
+ * checked only when opts->validate is set (MD_EINPUT otherwise undetected:
+ * outputs of inputs that break them are unspecified).
  *
  * Every call is ordered on `stream` (a hipStream_t; NULL = the null stream).
  * Choosing S from the data needs the exponent spans on the host, so the
@@ -68,6 +71,7 @@ extern "C" {
 #define MD_EHIP 6          /* a HIP runtime call failed; md_last_hip_error() has the code */
 #define MD_EINVAL_OPT 7    /* unknown form or rule, or forced S / beta out of range */
 #define MD_ERANGE 8        /* no exact slice parameters exist for this size and target */
+#define MD_EINPUT 9        /* validation mode: an input entry breaks the preconditions */
 
 /* slice forms */
 #define MD_FORM_FP64 0
@@ -96,6 +100,8 @@ typedef struct md_info {
     int G_rho;          /* magnitude bound (-1: not computed or not certifiable) */
     int target_bits;    /* T */
     double log2_bound;  /* certified log2 of the max relative error vs (|A||B|)_ij */
+    int input_flags;    /* validation mode: OR over the entries of 1 (a word not finite),
+                           2 (not weakly nonoverlapping), 4 (leading word out of range) */
 } md_info;
 
 /* Debug dump (small shapes): every non-NULL pointer is a device buffer the
@@ -121,6 +127,9 @@ typedef struct md_opts {
     md_info *info;         /* optional: receives the chosen parameters */
     void *ev_gemm_begin;   /* optional hipEvent_t pair (caller-owned), recorded on */
     void *ev_gemm_end;     /*   `stream` right before / after the slice contraction */
+    int validate;          /* nonzero: check the input preconditions first (one read of
+                              the inputs and one synchronisation); MD_EINPUT, with C
+                              untouched and md_info.input_flags set, if any fails */
 } md_opts;
 
 /*

@@ -388,6 +388,30 @@ def is_nonoverlapping(words, strong: bool = True) -> bool:
     return True
 
 
+# Preconditions of the method's inputs, as flags (0: all hold).
+PRE_NONFINITE = 1   # a word is an infinity or a NaN
+PRE_OVERLAP = 2     # not weakly nonoverlapping (a zero word before a nonzero one included)
+PRE_RANGE = 4       # a nonzero leading word outside [2^-900, 2^900)
+
+
+def precondition_flags(words) -> int:
+    """The preconditions an m-double entry must meet: finite words, weakly
+    nonoverlapping (``is_nonoverlapping(strong=False)``), and a leading word
+    that is zero or has 2^-900 <= |w_0| < 2^900 (so that the digit grids and
+    the fold scale stay inside the double range).  Returns the OR of the
+    PRE_* flags that fail."""
+    words = [float(w) for w in words]
+    if any(math.isinf(w) or math.isnan(w) for w in words):
+        return PRE_NONFINITE
+    f = 0
+    if not is_nonoverlapping(words, strong=False):
+        f |= PRE_OVERLAP
+    w0 = words[0]
+    if w0 != 0.0 and not (Fraction(2) ** -900 <= Fraction(abs(w0)) < Fraction(2) ** 900):
+        f |= PRE_RANGE
+    return f
+
+
 def log2_fraction(x: Fraction) -> float:
     """log2 of a positive Fraction, accurate to a few ulps, any magnitude."""
     p, q = x.numerator, x.denominator

@@ -35,7 +35,7 @@ _RULES = {"rho": 0, "span": 1}
 
 ERRORS = {
     0: "MD_OK", 1: "MD_EINVAL_M", 2: "MD_EINVAL_DIM", 3: "MD_ENULL", 4: "MD_EALIAS",
-    5: "MD_ENOMEM", 6: "MD_EHIP", 7: "MD_EINVAL_OPT", 8: "MD_ERANGE",
+    5: "MD_ENOMEM", 6: "MD_EHIP", 7: "MD_EINVAL_OPT", 8: "MD_ERANGE", 9: "MD_EINPUT",
 }
 
 
@@ -43,7 +43,8 @@ class MDInfo(ctypes.Structure):
     _fields_ = [("S", ctypes.c_int), ("beta", ctypes.c_int), ("kc", ctypes.c_int),
                 ("band", ctypes.c_int), ("span_A", ctypes.c_int), ("span_B", ctypes.c_int),
                 ("G", ctypes.c_int), ("G_span", ctypes.c_int), ("G_rho", ctypes.c_int),
-                ("target_bits", ctypes.c_int), ("log2_bound", ctypes.c_double)]
+                ("target_bits", ctypes.c_int), ("log2_bound", ctypes.c_double),
+                ("input_flags", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -59,7 +60,8 @@ class MDOpts(ctypes.Structure):
                 ("force_S", ctypes.c_int), ("force_beta", ctypes.c_int),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
                 ("dbg", ctypes.POINTER(MDDebug)), ("info", ctypes.POINTER(MDInfo)),
-                ("ev_gemm_begin", ctypes.c_void_p), ("ev_gemm_end", ctypes.c_void_p)]
+                ("ev_gemm_begin", ctypes.c_void_p), ("ev_gemm_end", ctypes.c_void_p),
+                ("validate", ctypes.c_int)]
 
 
 class MDError(RuntimeError):
@@ -105,13 +107,17 @@ def lib():
     return L
 
 
-def _check(rc: int):
+def _check(rc: int, info: "MDInfo | None" = None):
     if rc != 0:
         L = lib()
         msg = L.md_strerror(rc).decode()
         if rc == 6:
             msg += f" (hipError {L.md_last_hip_error()})"
-        raise MDError(rc, msg)
+        err = MDError(rc, msg)
+        if info is not None and rc == 9:
+            err.input_flags = info.input_flags
+            err.args = (f"{msg} (flags {info.input_flags})",)
+        raise err
 
 
 def choose_params(form: str, K: int, T: int, G: int):
@@ -139,7 +145,8 @@ def _check_planes(X: torch.Tensor, name: str):
 
 def gemm_ex(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None, *, transA=False,
             transB=False, form="fp64", rule="rho", target_bits=0, force_S=0, force_beta=0,
-            debug=None, workspace: torch.Tensor | None = None, events=None, stream=None):
+            debug=None, workspace: torch.Tensor | None = None, events=None, stream=None,
+            validate=False):
     """C = op(A) op(B) in m-double arithmetic.
 
     A is (m, M, K) (or (m, K, M) with transA), B is (m, K, N) (or (m, N, K)
@@ -147,6 +154,8 @@ def gemm_ex(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None, *, 
     ``debug`` may be a dict of preallocated device tensors with keys E, F,
     digits_A, digits_B, D (see ``md_debug``).  ``events`` may be a pair of
     raw hipEvent_t handles recorded around the slice contraction.
+    ``validate``: check the input preconditions first (MDError MD_EINPUT,
+    C untouched, when an entry breaks them).
     """
     _check_planes(A, "A")
     _check_planes(B, "B")
@@ -170,6 +179,7 @@ def gemm_ex(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None, *, 
     opts.target_bits = target_bits
     opts.force_S = force_S
     opts.force_beta = force_beta
+    opts.validate = 1 if validate else 0
     opts.info = ctypes.pointer(info)
     if workspace is not None:
         opts.workspace = ctypes.c_void_p(workspace.data_ptr())
@@ -189,7 +199,7 @@ def gemm_ex(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None, *, 
     rc = lib().md_gemm_ex(m, int(transA), int(transB), M, N, K, _ptr(A), lda, A.shape[1] * A.shape[2],
                           _ptr(B), ldb, B.shape[1] * B.shape[2], _ptr(C), N, M * N,
                           ctypes.byref(opts), _stream_handle(stream))
-    _check(rc)
+    _check(rc, info)
     return C, info.as_dict()
 
 
@@ -211,12 +221,14 @@ def gemm(A: torch.Tensor, B: torch.Tensor, form: str = "fp64", stream=None) -> t
 
 
 def dot_ex(X: torch.Tensor, Y: torch.Tensor, out: torch.Tensor | None = None, *, form="fp64",
-           rule="rho", target_bits=0, force_S=0, force_beta=0, events=None, stream=None):
+           rule="rho", target_bits=0, force_S=0, force_beta=0, events=None, stream=None,
+           validate=False):
     """Batched m-double inner products out_b = sum_k X[:, b, k] Y[:, b, k].
 
     X and Y are (m, batch, n) float64 planes on the HIP device (m = 1, 2, 4,
-    8 or 16); out is (m, batch).  Returns (out, info dict); ``events`` as in
-    ``gemm_ex`` (recorded around the contraction and the fold).
+    8 or 16); out is (m, batch).  Returns (out, info dict); ``events`` and
+    ``validate`` as in ``gemm_ex`` (events recorded around the contraction
+    and the fold).
     """
     _check_planes(X, "X")
     _check_planes(Y, "Y")
@@ -236,13 +248,14 @@ def dot_ex(X: torch.Tensor, Y: torch.Tensor, out: torch.Tensor | None = None, *,
     opts.target_bits = target_bits
     opts.force_S = force_S
     opts.force_beta = force_beta
+    opts.validate = 1 if validate else 0
     opts.info = ctypes.pointer(info)
     if events is not None:
         opts.ev_gemm_begin = ctypes.c_void_p(events[0])
         opts.ev_gemm_end = ctypes.c_void_p(events[1])
     rc = lib().md_dot_ex(m, batch, n, _ptr(X), n, batch * n, _ptr(Y), n, batch * n, _ptr(out), batch,
                          ctypes.byref(opts), _stream_handle(stream))
-    _check(rc)
+    _check(rc, info)
     return out, info.as_dict()
 
 

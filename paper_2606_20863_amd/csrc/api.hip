@@ -253,6 +253,30 @@ struct Scratch {
     }
 };
 
+// Validation mode: the OR of the precondition flags of both operands, on
+// the host (one synchronisation).  Returns MD_OK, MD_EINPUT or an error.
+int validate_inputs(Scratch& scr, const Operand& a, const Operand& b, int m, md_info* info,
+                    hipStream_t st)
+{
+    void* p;
+    int rc = scr.get(256, &p);
+    if (rc)
+        return rc;
+    int32_t* flags = (int32_t*)p;
+    hipError_t e;
+    if ((e = launch_fill_zero_i64((int64_t*)flags, 1, st)) != hipSuccess) return hip_fail(e);
+    if ((e = launch_validate(a, m, flags, st)) != hipSuccess) return hip_fail(e);
+    if ((e = launch_validate(b, m, flags, st)) != hipSuccess) return hip_fail(e);
+    int32_t h = 0;
+    if ((e = hipMemcpyAsync(&h, flags, sizeof(h), hipMemcpyDeviceToHost, st)) != hipSuccess)
+        return hip_fail(e);
+    if ((e = hipStreamSynchronize(st)) != hipSuccess)
+        return hip_fail(e);
+    if (info)
+        info->input_flags = h;
+    return h ? MD_EINPUT : MD_OK;
+}
+
 size_t digits_bytes(int form, int64_t R, int64_t K, int S)
 {
     const int64_t Rp = round_up(std::max<int64_t>(R, 1), kTile);
@@ -282,6 +306,7 @@ const char* md_strerror(int code)
     case MD_EHIP: return "HIP runtime error (see md_last_hip_error)";
     case MD_EINVAL_OPT: return "invalid option";
     case MD_ERANGE: return "no exact slice parameters for this size and target";
+    case MD_EINPUT: return "an input entry breaks the preconditions (validation mode)";
     default: return "unknown error";
     }
 }
@@ -387,6 +412,11 @@ int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, c
     if (o.workspace) {
         scr.user = (char*)o.workspace;
         scr.user_bytes = o.workspace_bytes;
+    }
+    if (o.validate) {
+        const int rc = validate_inputs(scr, opA, opB, m, o.info, st);
+        if (rc)
+            return rc;
     }
     int32_t *hiA, *loA, *hiB, *loB, *E, *F, *stats;
     {
@@ -559,6 +589,8 @@ int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, c
         in->G_span = G_span;
         in->G_rho = G_rho;
         in->target_bits = T;
+        if (!o.validate)
+            in->input_flags = 0;
         // certified bound of the method plus the final rounding
         const double lb = o.form == MD_FORM_INT8_BAL
                               ? (double)(G + 2 - 8 * S) + __builtin_log2((double)S + 3.0)
@@ -635,6 +667,11 @@ int md_dot_ex(int m, int64_t batch, int64_t n, const double* X, int64_t ldx, int
     if (o.workspace) {
         scr.user = (char*)o.workspace;
         scr.user_bytes = o.workspace_bytes;
+    }
+    if (o.validate) {
+        const int rc = validate_inputs(scr, opX, opY, m, o.info, st);
+        if (rc)
+            return rc;
     }
     int32_t *hiX, *loX, *hiY, *loY, *E, *F, *stats;
     {
@@ -784,6 +821,8 @@ int md_dot_ex(int m, int64_t batch, int64_t n, const double* X, int64_t ldx, int
         in->G_span = G_span;
         in->G_rho = G_rho;
         in->target_bits = T;
+        if (!o.validate)
+            in->input_flags = 0;
         const double lb = o.form == MD_FORM_INT8_BAL
                               ? (double)(G + 2 - 8 * S) + __builtin_log2((double)S + 3.0)
                               : (double)(G - beta * S) + __builtin_log2((double)S + 2.0);

@@ -86,6 +86,9 @@ hipError_t launch_exp_final(const int32_t* hi, const int32_t* lo, int64_t R, int
 // shared exponent + 2)
 hipError_t launch_split_i8(const Operand& op, int m, const int32_t* E, int S, int64_t nrb,
                            int64_t nkc, int8_t* out, int32_t* dbg, bool balanced, hipStream_t st);
+// OR of the input-precondition flags of every entry of op into *flags
+// (1 not finite, 2 not weakly nonoverlapping, 4 leading word out of range)
+hipError_t launch_validate(const Operand& op, int m, int32_t* flags, hipStream_t st);
 // one INT8 slice of leading-word magnitudes (ratio certificate); E holds
 // the shared exponent + eoff
 hipError_t launch_split_mag(const Operand& op, const int32_t* E, int eoff, int64_t nrb, int64_t nkc,

@@ -147,6 +147,60 @@ __global__ void k_exp_final(const int32_t* hi, const int32_t* lo, int64_t R, int
     atomicMax(span_max, span);
 }
 
+// Input preconditions of one entry (flags: 1 a word not finite, 2 not
+// weakly nonoverlapping, 4 a nonzero leading word outside [2^-900, 2^900)).
+// Weak nonoverlap: the highest set bit of every nonzero word lies below the
+// lowest set bit of the nonzero word before it, and no nonzero word follows
+// a zero one.
+template <int MW>
+__device__ __forceinline__ int entry_flags(const Operand& op, int64_t r, int64_t k)
+{
+    int f = 0, prev_low = 0;
+    bool have_prev = false, seen_zero = false;
+#pragma unroll
+    for (int w = 0; w < MW; ++w) {
+        const uint64_t b = (uint64_t)__double_as_longlong(op.p[w * op.ps + r * op.sr + k * op.sk]);
+        const int eb = (int)((b >> 52) & 0x7ff);
+        const uint64_t f52 = b & ((1ull << 52) - 1);
+        if (eb == 0x7ff) {
+            f |= 1;
+            continue;
+        }
+        if (eb == 0 && f52 == 0) {
+            seen_zero = true;
+            continue;
+        }
+        const uint64_t mant = eb ? (f52 | (1ull << 52)) : f52;
+        const int ex = eb ? eb - 1075 : -1074;                // |x| = mant 2^ex
+        const int low = ex + __builtin_ctzll(mant);
+        const int high = ex + 63 - __builtin_clzll(mant);
+        if (seen_zero || (have_prev && !(high < prev_low)))
+            f |= 2;
+        if (w == 0 && !(high >= -900 && high < 900))      // 2^-900 <= |x| < 2^900
+            f |= 4;
+        prev_low = low;
+        have_prev = true;
+    }
+    return (f & 1) ? 1 : f;
+}
+
+// OR of the flags of every entry into *flags; entries in the order of the
+// contiguous dimension.
+template <int MW>
+__global__ __launch_bounds__(256) void k_validate(Operand op, int rows_fast, int32_t* flags)
+{
+    const int64_t n = op.R * op.K;
+    int f = 0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = rows_fast ? e % op.R : e / op.K;
+        const int64_t k = rows_fast ? e / op.R : e % op.K;
+        f |= entry_flags<MW>(op, r, k);
+    }
+    if (f)
+        atomicOr(flags, f);
+}
+
 // Gather limb j (digits [D j, D j + D)) of the positive and the negative
 // words of one entry.
 template <int MW>
@@ -502,6 +556,28 @@ hipError_t launch_split_i8(const Operand& op, int m, const int32_t* E, int S, in
     case 4: return split_i8_m<4>(op, E, S, nrb, nkc, out, dbg, balanced, st);
     case 8: return split_i8_m<8>(op, E, S, nrb, nkc, out, dbg, balanced, st);
     case 16: return split_i8_m<16>(op, E, S, nrb, nkc, out, dbg, balanced, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int MW>
+hipError_t validate_m(const Operand& op, int32_t* flags, hipStream_t st)
+{
+    const int rows_fast = (op.sr == 1 && op.sk != 1) ? 1 : 0;
+    const int64_t n = op.R * op.K;
+    const int64_t blocks = std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 16384);
+    hipLaunchKernelGGL((k_validate<MW>), dim3((unsigned)blocks), dim3(256), 0, st, op, rows_fast, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate(const Operand& op, int m, int32_t* flags, hipStream_t st)
+{
+    switch (m) {
+    case 1: return validate_m<1>(op, flags, st);
+    case 2: return validate_m<2>(op, flags, st);
+    case 4: return validate_m<4>(op, flags, st);
+    case 8: return validate_m<8>(op, flags, st);
+    case 16: return validate_m<16>(op, flags, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -410,3 +410,27 @@ def test_generated_inputs_strongly_nonoverlapping(name):
             assert ox.is_nonoverlapping(P[(slice(None),) + idx], strong=True)
     A2, _ = mdinputs.workload(name, M=16, N=12, K=20)
     np.testing.assert_array_equal(A, A2)
+
+
+def test_precondition_flags():
+    """The input preconditions on hand-made entries: finite words, weak
+    nonoverlap (disjoint bit ranges, decreasing, zeros only at the tail) and
+    the range of the leading word."""
+    pf = ox.precondition_flags
+    ok = [1.5, 2.0 ** -60, -(2.0 ** -120), 0.0]
+    assert pf(ok) == 0
+    assert pf([0.0, 0.0]) == 0
+    # weak but not strong: the second word touches the first's last bit range
+    w = [1.0 + 2.0 ** -40, 2.0 ** -41]
+    assert pf(w) == 0 and not ox.is_nonoverlapping(w, strong=True)
+    assert pf([1.0 + 2.0 ** -40, 2.0 ** -40]) == ox.PRE_OVERLAP       # same bit
+    assert pf([1.0, 3.0]) == ox.PRE_OVERLAP                          # increasing
+    assert pf([1.0, 0.0, 2.0 ** -80]) == ox.PRE_OVERLAP              # zero gap
+    assert pf([float("nan"), 0.0]) == ox.PRE_NONFINITE
+    assert pf([1.0, float("inf")]) == ox.PRE_NONFINITE
+    assert pf([2.0 ** 900, 0.0]) == ox.PRE_RANGE
+    assert pf([2.0 ** 899 * 1.5, 0.0]) == 0
+    assert pf([2.0 ** -900, 0.0]) == 0
+    assert pf([2.0 ** -901, 0.0]) == ox.PRE_RANGE
+    assert pf([-(2.0 ** -1070), 0.0]) == ox.PRE_RANGE                 # subnormal lead
+    assert pf([2.0 ** 950, 2.0 ** 950]) == ox.PRE_OVERLAP | ox.PRE_RANGE
