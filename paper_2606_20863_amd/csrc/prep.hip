@@ -88,14 +88,17 @@ __global__ void k_exp_init(int32_t* hi, int32_t* lo, int64_t R, int32_t* stats)
         *reinterpret_cast<unsigned long long*>(stats + 2) = ~0ull;
 }
 
-// Block: 16 rows x 1024 depth, 256 threads; each row's 16 threads reduce
-// through shuffles-free LDS and one pair of atomics per row.
+// Block: 16 rows x 1024 depth, 256 threads, 16 threads per row.  Each row's
+// threads reduce with wavefront shuffles: in row order (the depth
+// contiguous) they are 16 adjacent lanes (xor 1, 2, 4, 8); in column order
+// (rows_fast: the rows contiguous, as for the columns of B) they are lanes
+// 16 apart in each of the four waves (xor 16, 32), and every wave adds its
+// partial row result by atomics.
 constexpr int kExpRows = 16, kExpDepth = 1024;
 
 __global__ __launch_bounds__(256) void k_exp_partial(Operand op, int32_t* hi, int32_t* lo,
                                                      int rows_fast)
 {
-    __shared__ int s_hi[256], s_lo[256];
     const int t = threadIdx.x;
     const int tr = rows_fast ? (t & 15) : (t >> 4);
     const int tk = rows_fast ? (t >> 4) : (t & 15);
@@ -114,19 +117,23 @@ __global__ __launch_bounds__(256) void k_exp_partial(Operand op, int32_t* hi, in
             }
         }
     }
-    s_hi[t] = h;
-    s_lo[t] = l;
-    __syncthreads();
-    if (tk == 0 && r < op.R) {
-        for (int q = 1; q < 16; ++q) {
-            const int o = rows_fast ? (t + 16 * q) : (t + q);
-            h = max(h, s_hi[o]);
-            l = min(l, s_lo[o]);
+    bool lead;
+    if (rows_fast) {
+        for (int o = 16; o < 64; o <<= 1) {
+            h = max(h, __shfl_xor(h, o));
+            l = min(l, __shfl_xor(l, o));
         }
-        if (h != INT_MIN) {
-            atomicMax(hi + r, h);
-            atomicMin(lo + r, l);
+        lead = (t & 63) < 16;
+    } else {
+        for (int o = 1; o < 16; o <<= 1) {
+            h = max(h, __shfl_xor(h, o));
+            l = min(l, __shfl_xor(l, o));
         }
+        lead = tk == 0;
+    }
+    if (lead && r < op.R && h != INT_MIN) {
+        atomicMax(hi + r, h);
+        atomicMin(lo + r, l);
     }
 }
 
