@@ -125,3 +125,15 @@ def test_parameter_rule_exactness_and_budget():
             assert beta == 8 and S * kc * 128 ** 2 < 2 ** 31
             assert S % band == 0 and (band <= 16 or band == S <= 32)
             assert 8 * S >= T + G + ox.ceil_log2(S + 3) + 3
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU: --gpus above 1 exits with status 2 and a
+    message, before touching any device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    res = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=120)
+    assert res.returncode == 2
+    assert "one GPU only" in res.stderr
