@@ -638,6 +638,53 @@ def method_product(A: np.ndarray, B: np.ndarray, beta: int, S: int,
 
 
 # ---------------------------------------------------------------------------
+# exact fixed-point results ("multiple integers", Section 1)
+# ---------------------------------------------------------------------------
+
+def fixed_product(A: np.ndarray, B: np.ndarray, beta: int, S: int, E=None, F=None,
+                  balanced: bool = False):
+    """The method's exact sum before rounding, as integers: for every entry
+    X_ij = sum_t D_t 2^(beta (S-1-t)) and scale_ij = E_i + F_j + 2h -
+    beta (S+1) (h = 2 for the balanced digits, else 0), so that the fold
+    is C~_ij = X_ij 2^scale_ij.  E, F: shared exponents to use instead of
+    those of A's rows and B's columns (a product over part of the depth
+    then uses the full rows' and columns' grids).  Returns (X, scale) as
+    object and int64 arrays of shape (M, N)."""
+    M, K = A.shape[1], A.shape[2]
+    N = B.shape[2]
+    if E is None:
+        E, _ = row_exponents(A[0])
+    if F is None:
+        F, _ = row_exponents(B[0].T)
+    E = [int(e) for e in E]
+    F = [int(f) for f in F]
+    h = BAL_HEADROOM if balanced else 0
+    if balanced:
+        dA = split_planes_balanced(A, E, S, by_columns=False)
+        dB = split_planes_balanced(B, F, S, by_columns=True)
+    else:
+        dA = split_planes(A, E, beta, S, by_columns=False)
+        dB = split_planes(B, F, beta, S, by_columns=True)
+    D = diagonal_sums(dA, dB, S)
+    X = np.zeros((M, N), dtype=object)
+    scale = np.zeros((M, N), dtype=np.int64)
+    for i in range(M):
+        for j in range(N):
+            X[i, j] = sum(int(D[t, i, j]) << (beta * (S - 1 - t)) for t in range(S))
+            scale[i, j] = E[i] + F[j] + 2 * h - beta * (S + 1)
+    return X, scale
+
+
+def fixed_limbs(X: int, nlimb: int):
+    """Two's complement 32-bit limbs of X, least significant first
+    (ValueError if X does not fit in 32 nlimb bits)."""
+    if not -(1 << (32 * nlimb - 1)) <= X < (1 << (32 * nlimb - 1)):
+        raise ValueError("does not fit")
+    u = X % (1 << (32 * nlimb))
+    return [(u >> (32 * k)) & 0xffffffff for k in range(nlimb)]
+
+
+# ---------------------------------------------------------------------------
 # batched inner products (the paper's experiment, Section 3)
 # ---------------------------------------------------------------------------
 

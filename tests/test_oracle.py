@@ -434,3 +434,33 @@ def test_precondition_flags():
     assert pf([2.0 ** -901, 0.0]) == ox.PRE_RANGE
     assert pf([-(2.0 ** -1070), 0.0]) == ox.PRE_RANGE                 # subnormal lead
     assert pf([2.0 ** 950, 2.0 ** 950]) == ox.PRE_OVERLAP | ox.PRE_RANGE
+
+
+@pytest.mark.parametrize("balanced", [False, True])
+def test_fixed_product_rounds_to_the_method_and_splits_over_depth(balanced):
+    """The exact fixed-point sum rounds (greedy, to nearest) to the method's
+    output; over a depth split with the full rows' and columns' exponents
+    the two partial integers add up exactly to the whole product's (the
+    diagonal sums are sums over k), and the scales agree."""
+    A, B = mdinputs.workload("qd1024", M=5, N=4, K=40)
+    beta, S = (8, 27) if balanced else (7, 30)
+    X, sc = ox.fixed_product(A, B, beta, S, balanced=balanced)
+    ref = ox.method_product(A, B, beta, S, balanced=balanced)
+    for i in range(5):
+        for j in range(4):
+            x = Fraction(X[i, j]) * Fraction(2) ** int(sc[i, j])
+            assert tuple(ox.renorm_rn(x, 4)) == tuple(ref["C"][:, i, j])
+    E, _ = ox.row_exponents(A[0])
+    F, _ = ox.row_exponents(B[0].T)
+    X1, s1 = ox.fixed_product(A[:, :, :17], B[:, :17, :], beta, S, E, F, balanced)
+    X2, s2 = ox.fixed_product(A[:, :, 17:], B[:, 17:, :], beta, S, E, F, balanced)
+    assert np.array_equal(s1, sc) and np.array_equal(s2, sc)
+    assert all(X1[i, j] + X2[i, j] == X[i, j] for i in range(5) for j in range(4))
+
+
+def test_fixed_limbs():
+    assert ox.fixed_limbs(0, 2) == [0, 0]
+    assert ox.fixed_limbs(-1, 2) == [0xffffffff, 0xffffffff]
+    assert ox.fixed_limbs((1 << 40) + 5, 2) == [5, 256]
+    with pytest.raises(ValueError):
+        ox.fixed_limbs(1 << 63, 2)
