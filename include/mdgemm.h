@@ -101,7 +101,8 @@ typedef struct md_info {
     int target_bits;    /* T */
     double log2_bound;  /* certified log2 of the max relative error vs (|A||B|)_ij */
     int input_flags;    /* validation mode: OR over the entries of 1 (a word not finite),
-                           2 (not weakly nonoverlapping), 4 (leading word out of range) */
+                           2 (not weakly nonoverlapping), 4 (leading word out of range);
+                           md_gemm_fixed: 8 (a given shared exponent not taken) */
 } md_info;
 
 /* Debug dump (small shapes): every non-NULL pointer is a device buffer the
@@ -201,6 +202,82 @@ int md_dot(int m, int64_t batch, int64_t n, const double *X, const double *Y, do
  */
 int md_gemm_ordinary(int m, int64_t M, int64_t N, int64_t K, const double *A, const double *B,
                      double *C, void *stream);
+
+/*
+ * Exact fixed-point results (paper, Section 1: multiword integers; the
+ * splitting of Section 2).  The product's exact sum before its one
+ * rounding is an integer X_ij at a power-of-two scale:
+ *   X_ij = sum_t D_t 2^(beta (S-1-t)),  C~_ij = X_ij 2^scale_ij,
+ *   scale_ij = E_i + F_j + 2h - beta (S+1)  (h = 2 for MD_FORM_INT8_BAL, else 0).
+ * When every depth block of a product is split on the same shared
+ * exponents (those of the full rows of A and columns of B, md_exponents),
+ * the blocks' integers add up exactly to the whole product's (md_fixed_add),
+ * and md_fixed_round of the sum returns what md_gemm_ex returns for the
+ * whole product with the same form, S and beta: a depth-split product
+ * (across streams or devices) reduced without any intermediate rounding.
+ *
+ * Integer layout: limb planes.  Limb k (32-bit two's complement, least
+ * significant first) of entry e is X[k * count + e]; for an M x N result
+ * count = M N and e = i N + j.  All pointers are device pointers.
+ */
+
+/* Limbs that hold X for any product of depth up to K with this beta and S
+ * (|X| < K 2^(beta (S+1) + 1)), or -1 if beta is not in [1, 24], S not in
+ * [1, 512] or K < 0.  Host only. */
+int md_fixed_limbs(int beta, int S, int64_t K);
+
+/*
+ * Shared exponents of the rows of A (M x K, row-major, leading dimension
+ * lda >= K; leading words only, plane 0) into E[M], and of the columns of B
+ * (K x N, row-major, ldb >= N) into F[N]: the largest frexp exponent of
+ * the nonzero leading words, 0 for an all-zero row or column (or K = 0).
+ * E or F may be NULL to skip that operand.  Returns MD_OK, MD_EINVAL_DIM,
+ * MD_ENULL, MD_ENOMEM or MD_EHIP.
+ */
+int md_exponents(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda, const double *B,
+                 int64_t ldb, int32_t *E, int32_t *F, void *stream);
+
+/*
+ * X (nlimb limb planes of M N entries) and scale[M N] (int32) of the exact
+ * product A B, m-double planes as md_gemm_ex without transposition: A is
+ * m planes of M x K (leading dimension lda, plane stride plane_stride_A),
+ * B m planes of K x N (ldb, plane_stride_B) -- so a depth block of larger
+ * matrices is addressed in place.
+ *   opts:  required, with force_S and force_beta set (the slices are fixed
+ *          by the caller so that every block shares them); form as
+ *          md_gemm_ex; dbg must be NULL; workspace, if given, serves the
+ *          product's own scratch.
+ *   E, F:  shared exponents of the rows of A and columns of B (device, M and
+ *          N int32) or NULL for the data's own.  Each given one must be at
+ *          least the data's own and at most 1100; otherwise the call
+ *          returns MD_EINPUT with md_info.input_flags bit 8 (if opts->info),
+ *          X and scale unspecified.  Given E or F make the call synchronise
+ *          `stream` once to check them.
+ *   nlimb: at least md_fixed_limbs(force_beta, force_S, K), at most 80
+ *          (MD_ERANGE otherwise).
+ * X and scale must not overlap each other (MD_EALIAS).  K must be at least
+ * 1 (MD_EINVAL_DIM); M = 0 or N = 0 is a no-op.  Besides the product's
+ * scratch, the call allocates S M N int64 diagonal sums and m M N doubles
+ * on `stream` (freed on return, stream-ordered).
+ */
+int md_gemm_fixed(int m, int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
+                  int64_t plane_stride_A, const double *B, int64_t ldb, int64_t plane_stride_B,
+                  const int32_t *E, const int32_t *F, int32_t *X, int nlimb, int32_t *scale,
+                  const md_opts *opts, void *stream);
+
+/* Z = X + Y modulo 2^(32 nlimb) for count entries of nlimb limb planes
+ * each (Z may be X or Y).  Both must be at the same scale (same E, F, S,
+ * beta); md_fixed_limbs of the total depth keeps the sum in range.
+ * nlimb in [1, 80] (MD_ERANGE otherwise). */
+int md_fixed_add(int64_t count, int nlimb, const int32_t *X, const int32_t *Y, int32_t *Z,
+                 void *stream);
+
+/* C = X 2^scale rounded greedily to nearest into m nonoverlapping words
+ * (word w of entry e at C[w * plane_stride_C + e], plane_stride_C >= count),
+ * the product's own final rounding.  m in {1, 2, 4, 8, 16}; nlimb in
+ * [1, 80]; C must not overlap X or scale (MD_EALIAS). */
+int md_fixed_round(int m, int64_t count, int nlimb, const int32_t *X, const int32_t *scale, double *C,
+                   int64_t plane_stride_C, void *stream);
 
 /*
  * Parameter rule alone (host only, no device work): (beta, S, kc, band) for

@@ -99,6 +99,17 @@ def lib():
     L.md_choose_params.restype = i32
     L.md_workspace_size.argtypes = [i32, i64, i64, i64, i32]
     L.md_workspace_size.restype = ctypes.c_size_t
+    L.md_fixed_limbs.argtypes = [i32, i32, i64]
+    L.md_fixed_limbs.restype = i32
+    L.md_exponents.argtypes = [i64, i64, i64, p, i64, p, i64, p, p, p]
+    L.md_exponents.restype = i32
+    L.md_gemm_fixed.argtypes = [i32, i64, i64, i64, p, i64, i64, p, i64, i64, p, p, p, i32, p,
+                                ctypes.POINTER(MDOpts), p]
+    L.md_gemm_fixed.restype = i32
+    L.md_fixed_add.argtypes = [i64, i32, p, p, p, p]
+    L.md_fixed_add.restype = i32
+    L.md_fixed_round.argtypes = [i32, i64, i32, p, p, p, i64, p]
+    L.md_fixed_round.restype = i32
     L.md_strerror.argtypes = [i32]
     L.md_strerror.restype = ctypes.c_char_p
     L.md_last_hip_error.restype = i32
@@ -277,6 +288,107 @@ def gemm_ordinary(A: torch.Tensor, B: torch.Tensor, stream=None) -> torch.Tensor
         raise ValueError("shape mismatch")
     C = torch.empty((m, M, N), dtype=torch.float64, device=A.device)
     _check(lib().md_gemm_ordinary(m, M, N, K, _ptr(A), _ptr(B), _ptr(C), _stream_handle(stream)))
+    return C
+
+
+def fixed_limbs(beta: int, S: int, K: int) -> int:
+    """32-bit limbs that hold the exact integer of any product of depth up
+    to K with these slices (host only)."""
+    n = lib().md_fixed_limbs(beta, S, K)
+    if n < 0:
+        raise ValueError(f"no limb count for beta={beta}, S={S}, K={K}")
+    return n
+
+
+def _strided_planes(X: torch.Tensor, name: str):
+    """(pointer, leading dimension, plane stride) of float64 planes whose
+    rows are contiguous (a column block of larger planes is allowed)."""
+    _check_planes(X, name)
+    if X.stride(2) != 1 and X.shape[2] > 1:
+        raise ValueError(f"{name} must have contiguous rows")
+    return _ptr(X), max(X.stride(1), X.shape[2]), max(X.stride(0), 1)
+
+
+def exponents(A: torch.Tensor, B: torch.Tensor, stream=None):
+    """Shared exponents (int32 device tensors) of the rows of A (m, M, K)
+    and the columns of B (m, K, N): the largest exponent of the nonzero
+    leading words, 0 where there is none."""
+    pa, lda, _ = _strided_planes(A, "A")
+    pb, ldb, _ = _strided_planes(B, "B")
+    M, K = A.shape[1], A.shape[2]
+    N = B.shape[2]
+    if B.shape[1] != K:
+        raise ValueError(f"inner sizes differ: {K} vs {B.shape[1]}")
+    E = torch.empty(M, dtype=torch.int32, device=A.device)
+    F = torch.empty(N, dtype=torch.int32, device=A.device)
+    _check(lib().md_exponents(M, N, K, pa, lda, pb, ldb, _ptr(E), _ptr(F), _stream_handle(stream)))
+    return E, F
+
+
+def gemm_fixed(A: torch.Tensor, B: torch.Tensor, E: torch.Tensor | None = None,
+               F: torch.Tensor | None = None, *, S: int, beta: int, form="fp64", nlimb=None,
+               stream=None):
+    """Exact integer X (nlimb, M, N) int32 limb planes and scale (M, N) of
+    the product A B before its rounding, C~ = X 2^scale.
+
+    A (m, M, K) and B (m, K, N) may be depth blocks of larger planes (views
+    with contiguous rows); E, F: the shared exponents to split on (those of
+    the full matrices for a depth-split product), None for the data's own.
+    nlimb defaults to the limbs of a depth-K product.  Returns (X, scale,
+    info dict)."""
+    pa, lda, psa = _strided_planes(A, "A")
+    pb, ldb, psb = _strided_planes(B, "B")
+    m, M, K = A.shape
+    N = B.shape[2]
+    if B.shape[:2] != (m, K):
+        raise ValueError("shape mismatch")
+    if nlimb is None:
+        nlimb = fixed_limbs(beta, S, K)
+    X = torch.empty((nlimb, M, N), dtype=torch.int32, device=A.device)
+    scale = torch.empty((M, N), dtype=torch.int32, device=A.device)
+    for T, name, n in ((E, "E", M), (F, "F", N)):
+        if T is not None and (T.dtype != torch.int32 or T.shape != (n,) or not T.is_cuda
+                              or not T.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous int32 device vector of {n} entries")
+    info = MDInfo()
+    opts = MDOpts()
+    opts.form = _FORMS[form]
+    opts.force_S = S
+    opts.force_beta = beta
+    opts.info = ctypes.pointer(info)
+    rc = lib().md_gemm_fixed(m, M, N, K, pa, lda, psa, pb, ldb, psb,
+                             None if E is None else _ptr(E), None if F is None else _ptr(F),
+                             _ptr(X), nlimb, _ptr(scale), ctypes.byref(opts), _stream_handle(stream))
+    _check(rc, info)
+    return X, scale, info.as_dict()
+
+
+def fixed_add(X: torch.Tensor, Y: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+    """out = X + Y for int32 limb planes (nlimb, ...) at the same scale."""
+    if X.dtype != torch.int32 or Y.dtype != torch.int32 or X.shape != Y.shape or X.dim() < 1:
+        raise ValueError("X and Y must be int32 limb planes of one shape")
+    X = X.contiguous()
+    Y = Y.contiguous()
+    if out is None:
+        out = torch.empty_like(X)
+    elif out.shape != X.shape or out.dtype != torch.int32 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous int32 tensor of X's shape")
+    nlimb = X.shape[0]
+    count = X.numel() // max(nlimb, 1)
+    _check(lib().md_fixed_add(count, nlimb, _ptr(X), _ptr(Y), _ptr(out), _stream_handle(stream)))
+    return out
+
+
+def fixed_round(X: torch.Tensor, scale: torch.Tensor, m: int, stream=None) -> torch.Tensor:
+    """X 2^scale rounded greedily to nearest into m words: (m, *scale.shape)."""
+    if X.dtype != torch.int32 or scale.dtype != torch.int32 or X.shape[1:] != scale.shape:
+        raise ValueError("X must be int32 limb planes (nlimb, *scale.shape), scale int32")
+    X = X.contiguous()
+    scale = scale.contiguous()
+    count = scale.numel()
+    C = torch.empty((m,) + tuple(scale.shape), dtype=torch.float64, device=X.device)
+    _check(lib().md_fixed_round(m, count, X.shape[0], _ptr(X), _ptr(scale), _ptr(C), count,
+                                _stream_handle(stream)))
     return C
 
 

@@ -345,10 +345,21 @@ size_t md_workspace_size(int form, int64_t M, int64_t N, int64_t K, int S)
     return bytes;
 }
 
-int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, const double* A,
-               int64_t lda, int64_t plane_stride_A, const double* B, int64_t ldb,
-               int64_t plane_stride_B, double* C, int64_t ldc, int64_t plane_stride_C,
-               const md_opts* opts, void* stream)
+}  // extern "C"
+
+namespace {
+
+// md_gemm_ex; E_in / F_in (optional, device, M and N entries): shared
+// exponents that replace those of op(A)'s rows and op(B)'s columns (a
+// forced S is then required: the rule's certificates hold for the data's
+// own exponents only).  An override below the data's own exponent, or above
+// 1100, is not taken: bit 8 goes into *exp_flags (device, zeroed by the
+// caller) and the data's own exponent stays.
+int gemm_impl(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, const double* A,
+              int64_t lda, int64_t plane_stride_A, const double* B, int64_t ldb,
+              int64_t plane_stride_B, double* C, int64_t ldc, int64_t plane_stride_C,
+              const md_opts* opts, void* stream, const int32_t* E_in, const int32_t* F_in,
+              int32_t* exp_flags)
 {
     g_last_hip = 0;
     if (m != 1 && m != 2 && m != 4 && m != 8 && m != 16)
@@ -389,6 +400,8 @@ int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, c
     if (o.force_S < 0 || o.force_S > 512 || (o.force_S > 0 && (o.force_beta < 1 || o.force_beta > 24)) ||
         (o.force_S > 0 && o.form == MD_FORM_INT8 && o.force_beta != 7) ||
         (o.force_S > 0 && o.form == MD_FORM_INT8_BAL && o.force_beta != 8))
+        return MD_EINVAL_OPT;
+    if ((E_in || F_in) && (o.force_S == 0 || !exp_flags))
         return MD_EINVAL_OPT;
 
     hipStream_t st = (hipStream_t)stream;
@@ -443,6 +456,8 @@ int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, c
     const int eoff = grid_offset(o.form);
     if ((e = launch_exp_final(hiA, loA, M, E, stats, dbg ? dbg->E : nullptr, eoff, st)) != hipSuccess) return hip_fail(e);
     if ((e = launch_exp_final(hiB, loB, N, F, stats + 1, dbg ? dbg->F : nullptr, eoff, st)) != hipSuccess) return hip_fail(e);
+    if (E_in && (e = launch_exp_set(E_in, M, eoff, E, exp_flags, st)) != hipSuccess) return hip_fail(e);
+    if (F_in && (e = launch_exp_set(F_in, N, eoff, F, exp_flags, st)) != hipSuccess) return hip_fail(e);
 
     int32_t spans[4] = {0, 0, 0, 0};   // span_A, span_B, minimum magnitude product (uint64)
     int beta, S, band;
@@ -598,6 +613,19 @@ int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, c
         in->log2_bound = o.force_S > 0 ? 0.0 : __builtin_log2(__builtin_exp2(lb) + __builtin_exp2(-53.0 * m + 0.1));
     }
     return MD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, const double* A,
+               int64_t lda, int64_t plane_stride_A, const double* B, int64_t ldb,
+               int64_t plane_stride_B, double* C, int64_t ldc, int64_t plane_stride_C,
+               const md_opts* opts, void* stream)
+{
+    return gemm_impl(m, transA, transB, M, N, K, A, lda, plane_stride_A, B, ldb, plane_stride_B, C, ldc,
+                     plane_stride_C, opts, stream, nullptr, nullptr, nullptr);
 }
 
 int md_dot_ex(int m, int64_t batch, int64_t n, const double* X, int64_t ldx, int64_t plane_stride_X,
@@ -864,6 +892,173 @@ int md_gemm(int m, int64_t M, int64_t N, int64_t K, const double* A, const doubl
             void* stream)
 {
     return md_gemm_ex(m, 0, 0, M, N, K, A, K, M * K, B, N, K * N, C, N, M * N, nullptr, stream);
+}
+
+int md_fixed_limbs(int beta, int S, int64_t K)
+{
+    if (beta < 1 || beta > 24 || S < 1 || S > 512 || K < 0)
+        return -1;
+    // |X| < K 2^(beta (S+1) + 1): two's complement with one bit to spare
+    return (beta * (S + 1) + ceil_log2(std::max<int64_t>(K, 1)) + 3 + 31) / 32;
+}
+
+int md_exponents(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B,
+                 int64_t ldb, int32_t* E, int32_t* F, void* stream)
+{
+    g_last_hip = 0;
+    if (M < 0 || N < 0 || K < 0 || M > (INT64_C(1) << 40) || N > (INT64_C(1) << 40) ||
+        K > (INT64_C(1) << 40))
+        return MD_EINVAL_DIM;
+    const bool doE = E && M > 0, doF = F && N > 0;
+    if (!doE && !doF)
+        return MD_OK;
+    if ((doE && K > 0 && !A) || (doF && K > 0 && !B))
+        return MD_ENULL;
+    if ((doE && K > 0 && (lda < K || !mul_ok(M, lda))) || (doF && K > 0 && (ldb < N || !mul_ok(K, ldb))))
+        return MD_EINVAL_DIM;
+    hipStream_t st = (hipStream_t)stream;
+    Scratch scr;
+    scr.st = st;
+    void* p;
+    int rc = scr.get(small_bytes(M, N), &p);
+    if (rc)
+        return rc;
+    int32_t* q = (int32_t*)p;
+    int32_t* stats = q;
+    q += 64;
+    hipError_t e;
+    if (doE) {
+        int32_t *hi = q, *lo = q + round_up(M + 64, 64);
+        const Operand op{A, 1, lda, 1, M, K};
+        if ((e = launch_exp_init(hi, lo, M, stats, st)) != hipSuccess) return hip_fail(e);
+        if (K > 0 && (e = launch_exp_partial(op, hi, lo, st)) != hipSuccess) return hip_fail(e);
+        if ((e = launch_exp_final(hi, lo, M, E, stats, nullptr, 0, st)) != hipSuccess) return hip_fail(e);
+        q = lo + round_up(M + 64, 64);
+    }
+    if (doF) {
+        int32_t *hi = q, *lo = q + round_up(N + 64, 64);
+        const Operand op{B, 1, 1, ldb, N, K};
+        if ((e = launch_exp_init(hi, lo, N, stats, st)) != hipSuccess) return hip_fail(e);
+        if (K > 0 && (e = launch_exp_partial(op, hi, lo, st)) != hipSuccess) return hip_fail(e);
+        if ((e = launch_exp_final(hi, lo, N, F, stats + 1, nullptr, 0, st)) != hipSuccess) return hip_fail(e);
+    }
+    return MD_OK;
+}
+
+int md_gemm_fixed(int m, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
+                  int64_t plane_stride_A, const double* B, int64_t ldb, int64_t plane_stride_B,
+                  const int32_t* E, const int32_t* F, int32_t* X, int nlimb, int32_t* scale,
+                  const md_opts* opts, void* stream)
+{
+    g_last_hip = 0;
+    if (m != 1 && m != 2 && m != 4 && m != 8 && m != 16)
+        return MD_EINVAL_M;
+    if (!opts || opts->force_S <= 0 || opts->dbg)
+        return MD_EINVAL_OPT;
+    if (M < 0 || N < 0 || K < 1)
+        return MD_EINVAL_DIM;
+    if (M == 0 || N == 0)
+        return MD_OK;
+    if (!A || !B || !X || !scale)
+        return MD_ENULL;
+    const int S = opts->force_S, beta = opts->force_beta;
+    const int need = md_fixed_limbs(beta, S, K);
+    if (need < 0)
+        return MD_EINVAL_OPT;
+    if (nlimb < need || nlimb > 80)
+        return MD_ERANGE;
+    if (!mul_ok(M, N) || !mul_ok(M * N, (int64_t)S * 8) || !mul_ok(M * N, (int64_t)nlimb * 4) ||
+        !mul_ok(M * N, (int64_t)m * 8) || M * N > (INT64_C(1) << 40))
+        return MD_EINVAL_DIM;
+    const uintptr_t x0 = (uintptr_t)X, x1 = x0 + (uintptr_t)(M * N * nlimb) * 4;
+    const uintptr_t s0 = (uintptr_t)scale, s1 = s0 + (uintptr_t)(M * N) * 4;
+    if (x0 < s1 && s0 < x1)
+        return MD_EALIAS;
+
+    hipStream_t st = (hipStream_t)stream;
+    Scratch scr;
+    scr.st = st;
+    void *pD, *pC, *pE;
+    int rc = scr.get((size_t)(M * N) * S * sizeof(int64_t), &pD);
+    if (!rc)
+        rc = scr.get((size_t)(M * N) * m * sizeof(double), &pC);
+    if (!rc)
+        rc = scr.get((size_t)(M + N + 64) * sizeof(int32_t), &pE);
+    if (rc)
+        return rc;
+    int32_t* flags = (int32_t*)pE;   // an int64 slot: bit 8 = an exponent override not taken
+    int32_t* Eown = flags + 64;
+    int32_t* Fown = Eown + M;
+    hipError_t e;
+    if ((e = launch_fill_zero_i64((int64_t*)flags, 1, st)) != hipSuccess)
+        return hip_fail(e);
+    md_debug d;
+    memset(&d, 0, sizeof(d));
+    d.D = (int64_t*)pD;
+    d.E = E ? nullptr : Eown;
+    d.F = F ? nullptr : Fown;
+    md_opts o = *opts;
+    o.dbg = &d;
+    rc = gemm_impl(m, 0, 0, M, N, K, A, lda, plane_stride_A, B, ldb, plane_stride_B, (double*)pC, N, M * N,
+                   &o, stream, E, F, flags);
+    if (rc)
+        return rc;
+    const int kcg = is_i8(o.form) ? kKcI8 : kKcF64;
+    const int ncol = fold_columns(beta, S, round_up(K, kcg));
+    if ((e = launch_fixed_from_D((const int64_t*)pD, S, beta, M, N, E ? E : Eown, F ? F : Fown,
+                                 grid_offset(o.form), ncol, X, nlimb, scale, st)) != hipSuccess)
+        return hip_fail(e);
+    if (E || F) {
+        int32_t fl = 0;
+        if ((e = hipMemcpyAsync(&fl, flags, sizeof(fl), hipMemcpyDeviceToHost, st)) != hipSuccess)
+            return hip_fail(e);
+        if ((e = hipStreamSynchronize(st)) != hipSuccess)
+            return hip_fail(e);
+        if (fl) {
+            if (opts->info)
+                opts->info->input_flags = fl;
+            return MD_EINPUT;
+        }
+    }
+    return MD_OK;
+}
+
+int md_fixed_add(int64_t count, int nlimb, const int32_t* X, const int32_t* Y, int32_t* Z, void* stream)
+{
+    g_last_hip = 0;
+    if (count < 0 || nlimb < 1 || nlimb > 80 || count > (INT64_C(1) << 40))
+        return count < 0 || count > (INT64_C(1) << 40) ? MD_EINVAL_DIM : MD_ERANGE;
+    if (count == 0)
+        return MD_OK;
+    if (!X || !Y || !Z)
+        return MD_ENULL;
+    const hipError_t e = launch_fixed_add(count, nlimb, X, Y, Z, (hipStream_t)stream);
+    return e == hipSuccess ? MD_OK : hip_fail(e);
+}
+
+int md_fixed_round(int m, int64_t count, int nlimb, const int32_t* X, const int32_t* scale, double* C,
+                   int64_t plane_stride_C, void* stream)
+{
+    g_last_hip = 0;
+    if (m != 1 && m != 2 && m != 4 && m != 8 && m != 16)
+        return MD_EINVAL_M;
+    if (count < 0 || count > (INT64_C(1) << 40))
+        return MD_EINVAL_DIM;
+    if (nlimb < 1 || nlimb > 80)
+        return MD_ERANGE;
+    if (count == 0)
+        return MD_OK;
+    if (!X || !scale || !C)
+        return MD_ENULL;
+    if (plane_stride_C < count || !mul_ok(plane_stride_C, (int64_t)m * 8))
+        return MD_EINVAL_DIM;
+    const Span sc = extent(C, m, 1, count, count, 1, plane_stride_C);
+    const uintptr_t x0 = (uintptr_t)X, x1 = x0 + (uintptr_t)(count * nlimb) * 4;
+    const uintptr_t s0 = (uintptr_t)scale, s1 = s0 + (uintptr_t)count * 4;
+    if (overlap(sc, Span{x0, x1}) || overlap(sc, Span{s0, s1}))
+        return MD_EALIAS;
+    const hipError_t e = launch_fixed_round(m, count, nlimb, X, scale, C, plane_stride_C, (hipStream_t)stream);
+    return e == hipSuccess ? MD_OK : hip_fail(e);
 }
 
 }  // extern "C"

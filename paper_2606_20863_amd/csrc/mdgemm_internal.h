@@ -82,6 +82,11 @@ hipError_t launch_exp_partial(const Operand& op, int32_t* hi, int32_t* lo, hipSt
 hipError_t launch_exp_final(const int32_t* hi, const int32_t* lo, int64_t R, int32_t* E,
                             int32_t* span_max, int32_t* dbgE, int eoff, hipStream_t st);
 
+// E[r] = Ein[r] + eoff where Ein[r] is at least the shared exponent (E[r] -
+// eoff) and at most 1100; else E[r] is kept and *flags |= 8
+hipError_t launch_exp_set(const int32_t* Ein, int64_t R, int eoff, int32_t* E, int32_t* flags,
+                          hipStream_t st);
+
 // INT8 digits: 7-bit sign-magnitude, or balanced 8-bit (E then holds the
 // shared exponent + 2)
 hipError_t launch_split_i8(const Operand& op, int m, const int32_t* E, int S, int64_t nrb,
@@ -132,6 +137,20 @@ hipError_t launch_fill_zero_i64(int64_t* p, int64_t n, hipStream_t st);
 hipError_t launch_dot_final(const int64_t* D, const int32_t* E, const int32_t* F, int64_t batch,
                             int S, int beta, int ncol, int m, double* out, int64_t pso,
                             hipStream_t st);
+// Fixed-point results.  X [nlimb][M N] (two's complement 32-bit limbs,
+// least significant first) and scale [M N] of sum_t D_t 2^(beta (S-1-t)),
+// D [S][M N]; scale = E_i + F_j + 2 eoff - beta (S+1); ncol: the fold width
+// in 32-bit columns (registers); E, F unshifted.
+hipError_t launch_fixed_from_D(const int64_t* D, int S, int beta, int64_t M, int64_t N,
+                               const int32_t* E, const int32_t* F, int eoff, int ncol, int32_t* X,
+                               int nlimb, int32_t* scale, hipStream_t st);
+// Z = X + Y mod 2^(32 nlimb), limb planes of count entries
+hipError_t launch_fixed_add(int64_t count, int nlimb, const int32_t* X, const int32_t* Y, int32_t* Z,
+                            hipStream_t st);
+// greedy round to nearest of X 2^scale into m words (plane stride psc)
+hipError_t launch_fixed_round(int m, int64_t count, int nlimb, const int32_t* X, const int32_t* scale,
+                              double* C, int64_t psc, hipStream_t st);
+
 // ordinary m-double product (m = 2, 4) of dense planes
 hipError_t launch_ordinary(int m, const double* A, const double* B, double* C, int64_t M,
                            int64_t N, int64_t K, hipStream_t st);

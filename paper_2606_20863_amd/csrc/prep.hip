@@ -532,6 +532,32 @@ hipError_t launch_exp_final(const int32_t* hi, const int32_t* lo, int64_t R, int
     return hipGetLastError();
 }
 
+// Caller-given shared exponents: E[r] (the data's own + eoff) becomes
+// Ein[r] + eoff when Ein[r] lies in [own, kExpMax]; otherwise E[r] stays and
+// bit 8 is set in *flags (a coarser grid keeps every word below 2^E; a
+// finer one would not).
+constexpr int kExpMax = 1100;
+
+__global__ void k_exp_set(const int32_t* Ein, int64_t R, int eoff, int32_t* E, int32_t* flags)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R)
+        return;
+    const int own = E[r] - eoff, want = Ein[r];
+    if (want >= own && want <= kExpMax)
+        E[r] = want + eoff;
+    else
+        atomicOr(flags, 8);
+}
+
+hipError_t launch_exp_set(const int32_t* Ein, int64_t R, int eoff, int32_t* E, int32_t* flags,
+                          hipStream_t st)
+{
+    const int64_t blocks = std::max<int64_t>((R + 255) / 256, 1);
+    hipLaunchKernelGGL(k_exp_set, dim3((unsigned)blocks), dim3(256), 0, st, Ein, R, eoff, E, flags);
+    return hipGetLastError();
+}
+
 // Entries per thread of the splits: fewer when an entry has more words.
 constexpr int split_ept(int m) { return m <= 4 ? 4 : (m == 8 ? 2 : 1); }
 

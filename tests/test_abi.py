@@ -137,3 +137,72 @@ def test_bench_refuses_several_gpus():
                          capture_output=True, text=True, timeout=120)
     assert res.returncode == 2
     assert "one GPU only" in res.stderr
+
+
+def test_fixed_limbs_hold_the_largest_sums():
+    """md_fixed_limbs against the largest integer a depth-K product can
+    reach: every digit at its largest magnitude (sign-magnitude INT8 127,
+    balanced -128, FP64 digits 2^beta - 1), so D_t = (t+1) K dmax^2 and X
+    = sum_t D_t 2^(beta (S-1-t)) must fit the limbs in two's complement."""
+    L = md.lib()
+    for beta, dmax in ((7, 127), (8, 128), (12, (1 << 12) - 1), (24, (1 << 24) - 1)):
+        for S in (1, 2, 5, 27, 64, 200):
+            for K in (1, 3, 1000, 1 << 20, (1 << 31) + 5):
+                n = L.md_fixed_limbs(beta, S, K)
+                X = K * dmax * dmax * sum((t + 1) << (beta * (S - 1 - t)) for t in range(S))
+                ox.fixed_limbs(X, n)
+                ox.fixed_limbs(-X, n)
+                # and no more than two limbs of slack
+                assert n <= 2 or X >= 1 << (32 * (n - 2) - 1), (beta, S, K, n)
+    assert L.md_fixed_limbs(0, 4, 10) == -1 and L.md_fixed_limbs(8, 0, 10) == -1
+    assert L.md_fixed_limbs(8, 513, 10) == -1 and L.md_fixed_limbs(8, 4, -1) == -1
+    assert md.fixed_limbs(8, 27, 4096) == L.md_fixed_limbs(8, 27, 4096)
+
+
+def test_fixed_argument_errors_before_device_work():
+    L = md.lib()
+    a = ctypes.c_void_p(0x100000)
+    b = ctypes.c_void_p(0x900000)
+    x = ctypes.c_void_p(0x500000)
+    sc = ctypes.c_void_p(0x700000)
+    opts = md.MDOpts()
+    opts.form = 2
+    opts.force_S = 4
+    opts.force_beta = 8
+    n = L.md_fixed_limbs(8, 4, 16)
+
+    def gf(m=2, M=4, N=4, K=16, nl=n, X=x, S=sc, o=opts):
+        return L.md_gemm_fixed(m, M, N, K, a, K, M * K, b, N, K * N, None, None, X, nl, S,
+                               ctypes.byref(o) if o is not None else None, None)
+
+    assert gf(m=3) == 1
+    assert gf(o=None) == 7
+    unforced = md.MDOpts()
+    assert gf(o=unforced) == 7
+    assert gf(K=0) == 2
+    assert gf(M=0) == 0 and gf(N=0) == 0
+    assert gf(nl=n - 1) == 8 and gf(nl=81) == 8
+    assert gf(X=None) == 3
+    assert gf(S=ctypes.c_void_p(0x500000 + 4 * 16)) == 4       # scale inside X's limbs
+    dbg_opts = md.MDOpts()
+    dbg_opts.form, dbg_opts.force_S, dbg_opts.force_beta = 2, 4, 8
+    dbg = md.MDDebug()
+    dbg_opts.dbg = ctypes.pointer(dbg)
+    assert gf(o=dbg_opts) == 7
+    # exponents: nothing to do, bad sizes, NULL data
+    assert L.md_exponents(0, 0, 4, None, 4, None, 4, None, None, None) == 0
+    assert L.md_exponents(4, 4, 4, a, 4, b, 4, None, None, None) == 0
+    assert L.md_exponents(-1, 4, 4, a, 4, b, 4, x, sc, None) == 2
+    assert L.md_exponents(4, 4, 4, None, 4, b, 4, x, None, None) == 3
+    assert L.md_exponents(4, 4, 8, a, 4, b, 4, x, None, None) == 2      # lda < K
+    # add and round
+    assert L.md_fixed_add(-1, 4, x, x, x, None) == 2
+    assert L.md_fixed_add(16, 0, x, x, x, None) == 8
+    assert L.md_fixed_add(0, 4, None, None, None, None) == 0
+    assert L.md_fixed_add(16, 4, None, x, x, None) == 3
+    c = ctypes.c_void_p(0x300000)
+    assert L.md_fixed_round(3, 16, 4, x, sc, c, 16, None) == 1
+    assert L.md_fixed_round(2, 16, 81, x, sc, c, 16, None) == 8
+    assert L.md_fixed_round(2, 16, 4, x, sc, c, 15, None) == 2
+    assert L.md_fixed_round(2, 16, 4, x, sc, ctypes.c_void_p(0x500000 + 64), 16, None) == 4
+    assert L.md_fixed_round(2, 0, 4, None, None, None, 0, None) == 0
