@@ -464,3 +464,29 @@ def test_fixed_limbs():
     assert ox.fixed_limbs((1 << 40) + 5, 2) == [5, 256]
     with pytest.raises(ValueError):
         ox.fixed_limbs(1 << 63, 2)
+
+
+@pytest.mark.parametrize("form,beta,shift", [("int8", 7, 7), ("int8bal", 8, 6), ("fp64", 20, 20)])
+def test_fixed_product_one_slice_closed_form(form, beta, shift):
+    """With one word and one slice the integer is a plain truncated
+    product: X_ij = sum_k t(a_ik) t(b_kj), t(x) = sgn(x) floor(|x|
+    2^(shift - E)) with shift = beta (balanced: 8 - 2, the grid starting
+    2^2 above E), and scale = E_i + F_j - 2 shift."""
+    r = np.random.Generator(np.random.PCG64(77))
+    A = np.ldexp(r.uniform(-1, 1, (1, 4, 9)), r.integers(-8, 9, (1, 4, 9)))
+    B = np.ldexp(r.uniform(-1, 1, (1, 9, 3)), r.integers(-8, 9, (1, 9, 3)))
+    A[0, 1, :] = 0.0
+    X, sc = ox.fixed_product(A, B, beta, 1, balanced=form == "int8bal")
+    for i in range(4):
+        nz = [abs(v) for v in A[0, i] if v != 0]
+        Ei = int(max(np.frexp(v)[1] for v in nz)) if nz else 0
+        for j in range(3):
+            Fj = int(max(np.frexp(abs(v))[1] for v in B[0, :, j] if v != 0))
+
+            def t(x, e):
+                q = Fraction(abs(float(x))) * Fraction(2) ** (shift - e)
+                return (1 if x >= 0 else -1) * (q.numerator // q.denominator)
+
+            want = sum(t(A[0, i, k], Ei) * t(B[0, k, j], Fj) for k in range(9))
+            assert X[i, j] == want, (i, j)
+            assert sc[i, j] == Ei + Fj - 2 * shift
