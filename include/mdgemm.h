@@ -154,6 +154,12 @@ int md_gemm(int m, int64_t M, int64_t N, int64_t K, const double *A, const doubl
  *   B[j*ldb + k] (transB = 1), word w at + w*plane_stride_B.
  *   C: element (i, j) word w at C[w*plane_stride_C + i*ldc + j].
  *   opts may be NULL (FP64 form, MD_S_RHO rule, T = 50 m).
+ * Graph capture: with opts->force_S set, opts->validate and opts->dbg
+ * clear and a workspace of at least md_workspace_size bytes, the call only
+ * launches kernels on `stream` (no allocation, copy, memset or
+ * synchronisation), so it can be captured into a HIP graph and replayed.
+ * Replays reuse the workspace: replays (or calls) that share one must not
+ * run concurrently.
  */
 int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, const double *A,
                int64_t lda, int64_t plane_stride_A, const double *B, int64_t ldb,

@@ -10,6 +10,44 @@
 
 using namespace mdg;
 
+namespace mdg {
+
+namespace {
+std::mutex g_attr_mu;
+struct AttrSet {
+    int dev;
+    const void* kernel;
+    size_t bytes;
+};
+AttrSet g_attr[256];
+int g_nattr = 0;
+}  // namespace
+
+hipError_t ensure_dynamic_lds(const void* kernel, size_t bytes)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    std::lock_guard<std::mutex> lk(g_attr_mu);
+    int slot = -1;
+    for (int q = 0; q < g_nattr; ++q)
+        if (g_attr[q].dev == dev && g_attr[q].kernel == kernel) {
+            if (g_attr[q].bytes >= bytes)
+                return hipSuccess;
+            slot = q;
+        }
+    if ((e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)) != hipSuccess)
+        return e;
+    if (slot < 0 && g_nattr < 256)
+        slot = g_nattr++;
+    if (slot >= 0)
+        g_attr[slot] = AttrSet{dev, kernel, bytes};
+    return hipSuccess;
+}
+
+}  // namespace mdg
+
 namespace {
 
 thread_local int g_last_hip = 0;

@@ -325,8 +325,7 @@ hipError_t launch_dot_final(const int64_t* D, const int32_t* E, const int32_t* F
 {
     const size_t lds = (size_t)ncol * 256 * sizeof(int64_t);
     if (lds > 64 * 1024) {
-        const hipError_t e = hipFuncSetAttribute((const void*)k_dot_final,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        const hipError_t e = ensure_dynamic_lds((const void*)k_dot_final, lds);
         if (e != hipSuccess)
             return e;
     }

@@ -71,6 +71,11 @@ inline int64_t gd_elements(int64_t M, int64_t N, int S, int gR)
     return gy * gx * 4 * (int64_t)S * 64 * 4 * gR;
 }
 
+// Raise the kernel's dynamic LDS limit to at least `bytes` on the current
+// device (once per kernel and device: later launches, also under stream
+// capture, make no runtime call)
+hipError_t ensure_dynamic_lds(const void* kernel, size_t bytes);
+
 hipError_t launch_fill_zero(double* C, int m, int64_t M, int64_t N, int64_t ldc, int64_t psc,
                             hipStream_t st);
 

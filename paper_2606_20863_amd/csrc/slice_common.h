@@ -502,8 +502,7 @@ hipError_t launch_kernel(Kernel k, const GemmArgs& a, hipStream_t st, bool lds_f
 {
     const size_t lds = lds_fold ? (size_t)4 * a.ncol * 256 * sizeof(int64_t) : 0;
     if (lds) {
-        const hipError_t e = hipFuncSetAttribute(
-            (const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        const hipError_t e = ensure_dynamic_lds((const void*)k, lds);
         if (e != hipSuccess)
             return e;
     }
