@@ -13,8 +13,13 @@ and the same 2^-200 target.  Prints one JSON line.
 roofline: the dominant kernel is the slice contraction of the headline form;
 its algorithmic work per launch is 2 M N K S(S+1)/2 int8 operations (S(S+1)/2
 slice multiply-adds per m-double multiply-add), timed with HIP events on the
-call's stream around that kernel.  cpu_baseline: the exact C oracle on this
-host's cores over a bounded sample of output entries.
+call's stream around that kernel.
+
+The CPU leg, after all GPU work (skip with --no-cpu), is the only user of
+the oracle: cpu_baseline times the exact C oracle on this host's cores over
+a bounded sample of output entries, and every "max_log2_err_sampled" field
+is the largest error of a grid of sampled GPU outputs against the exact
+product (null when the leg is skipped).
 
 ordinary_form: the same product in classical quad-double arithmetic (every
 operation renormalised; the paper's comparison baseline), its time, error
@@ -114,6 +119,11 @@ def elapsed_ms(hip, ev):
     return float(ms.value)
 
 
+def progress(msg):
+    """One line per finished phase on stderr (the JSON line goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def run_form(md, torch, A, B, form, steps, warmup):
     hip, evs = hip_events(steps)
     for _ in range(warmup):
@@ -133,17 +143,46 @@ def run_form(md, torch, A, B, form, steps, warmup):
     return C, info, ms, sum(kern) / len(kern)
 
 
-def accuracy_sample(A, B, C, n=8):
-    """max log2(|C - C*| / (|A||B|)) over a few entries (exact C oracle)."""
+# Sampled outputs of the GPU runs, kept for the CPU leg: the oracle runs
+# only there, after all GPU work (with --no-cpu the error fields stay null).
+_ERROR_CHECKS = []
+
+
+def defer_error(target, key, A, B, C, n=8):
+    """Keep an n x n grid of outputs of C = A B (numpy or device planes)
+    with the rows of A and the columns of B they need; the CPU leg writes
+    max log2(|C - C*| / (|A||B|)) over them into target[key]."""
+    import numpy as np
+    M, N = C.shape[1], C.shape[2]
+    ri = np.linspace(0, M - 1, n).astype(np.int64)
+    ci = np.linspace(0, N - 1, n).astype(np.int64)
+    ii = np.arange(n, dtype=np.int64).repeat(n)
+    jj = np.tile(np.arange(n, dtype=np.int64), n)
+    if hasattr(C, "cpu"):
+        import torch
+        Cq = C[:, torch.from_numpy(ri[ii]).to(C.device), torch.from_numpy(ci[jj]).to(C.device)].cpu().numpy()
+    else:
+        Cq = C[:, ri[ii], ci[jj]]
+    defer_entries(target, key, np.ascontiguousarray(A[:, ri, :]), np.ascontiguousarray(B[:, :, ci]),
+                  ii, jj, np.ascontiguousarray(Cq.T))
+
+
+def defer_entries(target, key, A, B, ii, jj, Cq):
+    """Entries (ii[q], jj[q]) of A B computed as Cq[q] (m words), checked
+    by the CPU leg."""
+    target[key] = None
+    _ERROR_CHECKS.append((target, key, A, B, ii, jj, Cq))
+
+
+def resolve_errors():
+    """The CPU leg's error check of every deferred sample (exact C oracle)."""
     import numpy as np
     from oracle import coracle
-    M, N = C.shape[1], C.shape[2]
-    ii = np.linspace(0, M - 1, n).astype(np.int64).repeat(n)
-    jj = np.tile(np.linspace(0, N - 1, n).astype(np.int64), n)
-    Cq = np.ascontiguousarray(C[:, ii, jj].T)
-    _, absab, err = coracle.exact_entries(A, B, ii, jj, Cq)
-    rel = np.abs(err) / absab
-    return float(np.log2(max(rel.max(), 2.0 ** -1074)))
+    for target, key, A, B, ii, jj, Cq in _ERROR_CHECKS:
+        _, absab, err = coracle.exact_entries(A, B, ii, jj, Cq)
+        rel = np.abs(err) / absab
+        target[key] = round(float(np.log2(max(rel.max(), 2.0 ** -1074))), 2)
+    _ERROR_CHECKS.clear()
 
 
 # Table 2 of the paper: one CPU core, 1,024 inner products of length 6,144,
@@ -159,10 +198,9 @@ def paper_inner_products(md, torch, steps=5):
     paper's own parameters (FP64 form, beta = 13, S = 4m).  Whole-call
     milliseconds (inputs resident), the contraction and fold alone from HIP
     events, and the largest error over 8 sampled pairs against the exact
-    products (C oracle) relative to sum |x||y|."""
+    products (checked by the CPU leg) relative to sum |x||y|."""
     import numpy as np
     import mdinputs
-    from oracle import coracle
     X16, Y16 = mdinputs.paper_dot_workload(16)
     hip, _ = hip_events(1)
     pairs = np.linspace(0, X16.shape[1] - 1, 8).astype(np.int64)
@@ -192,11 +230,11 @@ def paper_inner_products(md, torch, steps=5):
                 hip.hipEventDestroy(ctypes.c_void_p(a))
                 hip.hipEventDestroy(ctypes.c_void_p(b))
             Cq = np.ascontiguousarray(out.cpu().numpy()[:, pairs].T)
-            _, absab, err = coracle.exact_entries(Xs, Ys, idx, idx, Cq)
-            rel = float(np.log2(max((np.abs(err) / absab).max(), 2.0 ** -1074)))
             row[label] = {"S": info["S"], "beta": info["beta"], "ms_per_call": round(ms, 4),
-                          "contraction_fold_ms": round(kern, 4), "max_log2_err_sampled": round(rel, 2)}
+                          "contraction_fold_ms": round(kern, 4)}
+            defer_entries(row[label], "max_log2_err_sampled", Xs, Ys, idx, idx, Cq)
         rows[f"m{m}"] = row
+        progress(f"inner products m={m} done")
         del X, Y
     return {"workload": "1024 inner products of length 6144, the paper's bit pattern (Section 2), "
                         "m-double inputs, one md_dot_ex call each",
@@ -205,14 +243,15 @@ def paper_inner_products(md, torch, steps=5):
 
 def other_configs(md, torch, steps=3):
     """The scope's other workloads, each timed as whole steps (inputs
-    resident): quad-double 1024^3 forward; double-double 2048^3 and
+    resident): double-double 64^3 (per-call microseconds, eager and as a
+    HIP graph replay); quad-double 1024^3 forward; double-double 2048^3 and
     octo-double 1024^3 forward + adjoint (C = A B, dA = W B^T, dB = A^T W:
     three products per step); hexa-double 1024^3 forward (leading words
     2^U(-6,6), seed 16).  Per form: milliseconds per step, effective GFLOP/s
     (2 M N K per product), the slice contractions with their folds from HIP
     events, their fraction of the matrix-core peak (algorithmic work
     2 M N K S(S+1)/2 per product), and the largest error of 64 sampled
-    forward entries against the exact product (C oracle)."""
+    forward entries against the exact product (checked by the CPU leg)."""
     import numpy as np
     import mdinputs
     hip, _ = hip_events(1)
@@ -229,7 +268,8 @@ def other_configs(md, torch, steps=3):
                   mdinputs.mdouble(r16, 16, (1024, 1024), ("log2uniform", 6.0)), None),
          False, ("int8bal", "int8", "fp64")),
     ]
-    res = {}
+    res = {"dd64": small_case(md, torch)}
+    progress("workload dd64 done")
     for name, label, make, adjoint, forms in cases:
         Ah, Bh, Wh = make()
         A = torch.from_numpy(Ah).cuda()
@@ -269,12 +309,63 @@ def other_configs(md, torch, steps=3):
             row[form] = {"S": [i["S"] for i in infos[:len(calls)]], "beta": infos[0]["beta"],
                          "ms_per_step": round(ms, 4), "effective_gflops": round(flop / (ms * 1e-3) / 1e9, 2),
                          "contraction_fold_ms": round(kern, 4),
-                         "frac_peak": round(ops / (kern * 1e-3) / 1e12 / peak, 4),
-                         "max_log2_err_sampled": round(accuracy_sample(Ah, Bh, C.cpu().numpy()), 2)}
+                         "frac_peak": round(ops / (kern * 1e-3) / 1e12 / peak, 4)}
+            defer_error(row[form], "max_log2_err_sampled", Ah, Bh, C)
         res[name] = row
+        progress(f"workload {name} done")
         del A, B, W, calls, C
         torch.cuda.empty_cache()
     return res
+
+
+def small_case(md, torch, reps=200):
+    """Double-double 64^3, the smallest workload, where launches and the
+    host round trip dominate: microseconds per product (a) eager with the
+    slice rule (one host synchronisation for the exponent spans), (b) eager
+    with the rule's S forced and a caller workspace (kernel launches only),
+    (c) replays of a HIP graph holding (b), whose output must equal (a)'s."""
+    import mdinputs
+    Ah, Bh = mdinputs.workload("dd64")
+    A = torch.from_numpy(Ah).cuda()
+    B = torch.from_numpy(Bh).cuda()
+    m, M, K = Ah.shape
+    N = Bh.shape[2]
+    row = {"label": "double-double 64^3 (launch-bound)", "m": m}
+
+    def per_call_us(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return round((time.perf_counter() - t0) * 1e6 / reps, 2)
+
+    for form in ("fp64", "int8bal", "int8"):
+        C, info = md.gemm_ex(A, B, form=form)
+        kw = dict(form=form, force_S=info["S"], force_beta=info["beta"])
+        ws = torch.empty(md.lib().md_workspace_size(md._FORMS[form], M, N, K, info["S"]),
+                         dtype=torch.uint8, device="cuda")
+        Cg = torch.empty_like(C)
+        us_rule = per_call_us(lambda: md.gemm_ex(A, B, C, form=form))
+        us_forced = per_call_us(lambda: md.gemm_ex(A, B, C, workspace=ws, **kw))
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            md.gemm_ex(A, B, Cg, workspace=ws, **kw)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            md.gemm_ex(A, B, Cg, workspace=ws, **kw)
+        Cg.zero_()
+        us_graph = per_call_us(g.replay)
+        row[form] = {"S": info["S"], "beta": info["beta"], "eager_rule_us": us_rule,
+                     "eager_forced_us": us_forced, "graph_replay_us": us_graph,
+                     "graph_equals_eager": bool(torch.equal(Cg, C))}
+        defer_error(row[form], "max_log2_err_sampled", Ah, Bh, C)
+        del g
+    return row
 
 
 def cpu_baseline(A, B, K):
@@ -344,7 +435,9 @@ def main():
         del src, dst
 
     head = "int8bal" if "int8bal" in forms else "int8"
+    progress(f"{WORKLOAD} inputs resident")
     C8, info8, ms8, kern8 = run_form(md, torch, A, B, head, args.steps, args.warmup)
+    progress(f"{head} form: {ms8:.3f} ms per call")
     if "fp64" not in forms:
         out = {"metric": f"QD-GEMM 4096^3 effective GFLOP/s ({head} form only)",
                "ms_per_call": round(ms8, 4), "gemm_kernel_ms": round(kern8, 4), "S": info8["S"],
@@ -357,6 +450,7 @@ def main():
         sm = (Csm.cpu().numpy(), infosm, mssm, kernsm)
         del Csm
     C64, info64, ms64, kern64 = run_form(md, torch, A, B, "fp64", args.fp64_steps, 1)
+    progress(f"fp64 form: {ms64:.3f} ms per call")
 
     # the ordinary (classical) quad-double product on the same inputs, the
     # paper's comparison baseline; one warm-up and args.ordinary_steps timed
@@ -371,6 +465,7 @@ def main():
         ord_ms = (time.perf_counter() - t0) * 1e3 / args.ordinary_steps
         Coh = Co.cpu().numpy()
         del Co
+        progress(f"ordinary form: {ord_ms:.1f} ms per call")
 
     flop = 2.0 * M * N * K
     eff8 = flop / (ms8 * 1e-3) / 1e9
@@ -385,12 +480,7 @@ def main():
     traffic8 = measured_traffic(kname8)
     traffic8 = None if traffic8 is None else int(traffic8)
 
-    C8h = C8.cpu().numpy()
-    C64h = C64.cpu().numpy()
-    err8 = accuracy_sample(Ah, Bh, C8h)
-    err64 = accuracy_sample(Ah, Bh, C64h)
-
-    def int8_summary(info, ms, kern, err, steps):
+    def int8_summary(info, ms, kern, steps):
         S = info["S"]
         ops = flop * S * (S + 1) / 2
         return {"S": S, "beta": info["beta"], "kc": info["kc"], "band": info["band"],
@@ -398,10 +488,10 @@ def main():
                 "kernel": int8_kernel_name(info, K),
                 "effective_gflops": round(flop / (ms * 1e-3) / 1e9, 3),
                 "mfma_int8_tops": round(ops / (kern * 1e-3) / 1e12, 3),
-                "max_log2_err_sampled": round(err, 2),
+                "max_log2_err_sampled": None,
                 "certified_log2_bound": round(info["log2_bound"], 2)}
 
-    head_form = int8_summary(info8, ms8, kern8, err8, args.steps)
+    head_form = int8_summary(info8, ms8, kern8, args.steps)
     head_form["digits"] = ("balanced 8-bit digits in [-128, 127] on the grid 2^(E+2)" if head == "int8bal"
                            else "7-bit sign-magnitude digits")
     out = {
@@ -427,18 +517,18 @@ def main():
                       "steps": args.fp64_steps, "ms_per_call": round(ms64, 4),
                       "gemm_kernel_ms": round(kern64, 4), "effective_gflops": round(eff64, 3),
                       "mfma_tflops": round(ach64, 3), "frac_fp64_peak": round(ach64 / PEAK_FP64_TFLOPS, 4),
-                      "max_log2_err_sampled": round(err64, 2),
+                      "max_log2_err_sampled": None,
                       "certified_log2_bound": round(info64["log2_bound"], 2)},
         "int8_over_fp64": round(eff8 / eff64, 3),
         "int8_sign_magnitude_form": None if sm is None else dict(
-            int8_summary(sm[1], sm[2], sm[3], accuracy_sample(Ah, Bh, sm[0]), args.sm_steps),
+            int8_summary(sm[1], sm[2], sm[3], args.sm_steps),
             digits="7-bit sign-magnitude digits (the paper's bit-field cut)",
             headline_speedup=round(sm[2] / ms8, 3)),
         "ordinary_form": None if ord_ms is None else {
             "arithmetic": "classical quad-double, every multiply and add renormalised (md_gemm_ordinary)",
             "steps": args.ordinary_steps, "ms_per_call": round(ord_ms, 3),
             "effective_gflops": round(flop / (ord_ms * 1e-3) / 1e9, 3),
-            "max_log2_err_sampled": round(accuracy_sample(Ah, Bh, Coh), 2),
+            "max_log2_err_sampled": None,
             "headline_form_speedup": round(ord_ms / ms8, 2)},
         "roofline": {"bound": "mfma", "kernel": kname8,
                      "achieved": round(ach8, 3), "peak": PEAK_INT8_TOPS, "unit": "TFLOP/s",
@@ -446,6 +536,12 @@ def main():
                      "work_per_launch": f"2*M*N*K*S(S+1)/2 = {ops8:.4e} int8 ops (unit: int8 TOP/s)",
                      "algorithmic_bytes_per_launch": int(2 * S8 * M * K + 8 * m * M * N)},
     }
+    defer_error(head_form, "max_log2_err_sampled", Ah, Bh, C8)
+    defer_error(out["fp64_form"], "max_log2_err_sampled", Ah, Bh, C64)
+    if sm is not None:
+        defer_error(out["int8_sign_magnitude_form"], "max_log2_err_sampled", Ah, Bh, sm[0])
+    if ord_ms is not None:
+        defer_error(out["ordinary_form"], "max_log2_err_sampled", Ah, Bh, Coh)
     if not args.no_dot:
         del A, B, C8, C64
         torch.cuda.empty_cache()
@@ -455,8 +551,12 @@ def main():
             del A, B, C8, C64
             torch.cuda.empty_cache()
         out["configs"] = other_configs(md, torch)
+    # the CPU leg: every use of the oracle, after all GPU work
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(Ah, Bh, K)
+        progress("cpu baseline timed")
+        resolve_errors()
+        progress("sampled errors checked")
     print(json.dumps(out))
 
 

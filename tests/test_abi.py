@@ -139,6 +139,31 @@ def test_bench_refuses_several_gpus():
     assert "one GPU only" in res.stderr
 
 
+def test_bench_defers_the_error_check_to_the_cpu_leg():
+    """bench.py keeps sampled outputs during the GPU runs and checks them
+    with the oracle only in its CPU leg: an exact product reads as the
+    floor 2^-1074, a perturbed sampled entry as a large error."""
+    import sys
+    import numpy as np
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, root)
+    import bench
+    r = np.random.Generator(np.random.PCG64(3))
+    A = r.integers(1, 8, (1, 10, 12)).astype(np.float64)
+    B = r.integers(1, 8, (1, 12, 9)).astype(np.float64)
+    C = (A[0] @ B[0])[None]
+    C2 = C.copy()
+    C2[0, 0, 0] += 1.0
+    t, u = {}, {}
+    bench.defer_error(t, "err", A, B, C, n=4)
+    bench.defer_error(u, "err", A, B, C2, n=4)
+    assert t["err"] is None and u["err"] is None
+    bench.resolve_errors()
+    assert t["err"] == -1074.0
+    assert -12 < u["err"] < 0
+    assert not bench._ERROR_CHECKS
+
+
 def test_fixed_limbs_hold_the_largest_sums():
     """md_fixed_limbs against the largest integer a depth-K product can
     reach: every digit at its largest magnitude (sign-magnitude INT8 127,
