@@ -5,7 +5,8 @@ limb planes and a scale.  Checks, on ragged sizes (several tiles and a
 tail) for the three slice forms, the whole-triangle and banded INT8
 kernels (S up to 32 and beyond) and m = 1, 2, 4, 8:
 
-* every limb and scale equals the oracle's fixed_product / fixed_limbs;
+* every limb and scale equals the oracle's fixed_product / fixed_limbs,
+  also where the depth spans several exactness chunks;
 * md_fixed_round of it equals md_gemm_ex with the same S and beta (and
   the oracle's method) word for word;
 * a depth-split product: md_exponents of the full matrices equals the
@@ -74,6 +75,29 @@ def test_fixed_product_matches_oracle_and_rounds_to_the_product(form, beta, S, m
     np.testing.assert_array_equal(C.cpu().numpy(), Cg.cpu().numpy())
     ref = ox.method_product(A, B, beta, S, balanced=form == "int8bal")
     np.testing.assert_array_equal(C.cpu().numpy(), ref["C"])
+
+
+@pytest.mark.parametrize("form,beta,S,K,kc", [("int8bal", 8, 27, 5000, 4800), ("int8", 7, 30, 4500, 4416),
+                                               ("int8bal", 8, 36, 3700, 3584), ("fp64", 20, 10, 900, 816)])
+def test_fixed_product_over_several_exactness_chunks(form, beta, S, K, kc):
+    """Depths beyond one exactness chunk (kc: the oracle's chunk depth for
+    this S and beta): the captured diagonal sums accumulate over the chunks
+    (whole-triangle, banded and FP64 kernels), the integer equals the
+    oracle's and rounds to md_gemm_ex's output."""
+    assert ox.chunk_depth(S, beta, K, 1 << (53 if form == "fp64" else 31), 16 if form == "fp64" else 64,
+                          128 if form == "int8bal" else 0) == kc < K
+    m, M, N = 2, 20, 24
+    A, B = operands(K + S, m, M, N, K)
+    X, scale, info = md.gemm_fixed(dev(A), dev(B), S=S, beta=beta, form=form)
+    torch.cuda.synchronize()
+    assert info["kc"] == kc
+    Xo, so = ox.fixed_product(A, B, beta, S, balanced=form == "int8bal")
+    np.testing.assert_array_equal(X.cpu().numpy(), limbs_of(Xo, X.shape[0]))
+    np.testing.assert_array_equal(scale.cpu().numpy(), so.astype(np.int32))
+    C = md.fixed_round(X, scale, m)
+    Cg, _ = md.gemm_ex(dev(A), dev(B), form=form, force_S=S, force_beta=beta)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(C.cpu().numpy(), Cg.cpu().numpy())
 
 
 @pytest.mark.parametrize("form,beta,S", [("fp64", 20, 6), ("int8", 7, 16), ("int8bal", 8, 13),
