@@ -351,7 +351,7 @@ const char* md_strerror(int code)
 
 int md_last_hip_error(void) { return g_last_hip; }
 
-int md_version(void) { return 100; }
+int md_version(void) { return 200; }
 
 int md_choose_params(int form, int64_t K, int T, int G, int* beta, int* S, int* kc, int* band)
 {

@@ -235,3 +235,40 @@ def test_exponent_below_the_data_is_refused():
     with pytest.raises(md.MDError) as ei:
         md.gemm_fixed(Ad, Bd, E, F, S=6, beta=8, form="int8bal")
     assert ei.value.input_flags == 8
+
+
+def test_depth_split_at_the_benchmark_size():
+    """The quad-double 4096^3 benchmark product in the balanced INT8 form
+    (S = 27, the rule's choice) cut into four uneven depth blocks: the
+    blocks' integers on the full matrices' exponents add up to the whole
+    product's integer in every entry, that rounds to md_gemm_ex's output in
+    every entry, and an 8 x 8 grid of the integers equals the oracle's
+    fixed product of those rows and columns."""
+    A, B = mdinputs.workload("qd4096")
+    Ad, Bd = dev(A), dev(B)
+    Cg, info = md.gemm_ex(Ad, Bd, form="int8bal")
+    S, beta, K = info["S"], info["beta"], 4096
+    assert (S, beta) == (27, 8)
+    E, F = md.exponents(Ad, Bd)
+    nlimb = md.fixed_limbs(beta, S, K)
+    cuts = [0, 1000, 2048, 3001, K]
+    acc = sc = None
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        Xb, sc, _ = md.gemm_fixed(Ad[:, :, a:b], Bd[:, a:b, :], E, F, S=S, beta=beta, form="int8bal",
+                                  nlimb=nlimb)
+        acc = Xb if acc is None else md.fixed_add(acc, Xb)
+        del Xb
+    Xw, scw, _ = md.gemm_fixed(Ad, Bd, S=S, beta=beta, form="int8bal")
+    assert torch.equal(acc, Xw) and torch.equal(sc, scw)
+    del acc
+    assert torch.equal(md.fixed_round(Xw, scw, 4), Cg)
+    rows = np.linspace(0, 4095, 8).astype(np.int64)
+    cols = np.linspace(0, 4095, 8).astype(np.int64)
+    Eh, Fh = E.cpu().numpy(), F.cpu().numpy()
+    assert list(Eh[rows]) == ox.row_exponents(A[0][rows])[0]
+    assert list(Fh[cols]) == ox.row_exponents(B[0][:, cols].T)[0]
+    Xo, so = ox.fixed_product(np.ascontiguousarray(A[:, rows, :]), np.ascontiguousarray(B[:, :, cols]),
+                              beta, S, E=list(Eh[rows]), F=list(Fh[cols]), balanced=True)
+    ti, tj = torch.from_numpy(rows).cuda(), torch.from_numpy(cols).cuda()
+    np.testing.assert_array_equal(Xw[:, ti][:, :, tj].cpu().numpy(), limbs_of(Xo, nlimb))
+    np.testing.assert_array_equal(scw[ti][:, tj].cpu().numpy(), so.astype(np.int32))
