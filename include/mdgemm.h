@@ -66,12 +66,13 @@ extern "C" {
 #define MD_EINVAL_M 1      /* m not in {1, 2, 4, 8, 16} */
 #define MD_EINVAL_DIM 2    /* negative size, bad leading dimension or stride, overflow */
 #define MD_ENULL 3         /* NULL data pointer with a nonzero size */
-#define MD_EALIAS 4        /* C overlaps A or B */
+#define MD_EALIAS 4        /* an output overlaps an input (C and A or B) or another output */
 #define MD_ENOMEM 5        /* scratch allocation failed, or the given workspace is too small */
 #define MD_EHIP 6          /* a HIP runtime call failed; md_last_hip_error() has the code */
 #define MD_EINVAL_OPT 7    /* unknown form or rule, or forced S / beta out of range */
 #define MD_ERANGE 8        /* no exact slice parameters exist for this size and target */
-#define MD_EINPUT 9        /* validation mode: an input entry breaks the preconditions */
+#define MD_EINPUT 9        /* validation mode: an input entry breaks the preconditions;
+                              md_gemm_fixed: a given shared exponent was not taken */
 
 /* slice forms */
 #define MD_FORM_FP64 0

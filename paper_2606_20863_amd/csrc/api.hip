@@ -339,12 +339,12 @@ const char* md_strerror(int code)
     case MD_EINVAL_M: return "m must be 1, 2, 4, 8 or 16";
     case MD_EINVAL_DIM: return "invalid size, leading dimension or plane stride";
     case MD_ENULL: return "NULL data pointer";
-    case MD_EALIAS: return "C overlaps A or B";
+    case MD_EALIAS: return "an output overlaps an input or another output";
     case MD_ENOMEM: return "scratch allocation failed or workspace too small";
     case MD_EHIP: return "HIP runtime error (see md_last_hip_error)";
     case MD_EINVAL_OPT: return "invalid option";
     case MD_ERANGE: return "no exact slice parameters for this size and target";
-    case MD_EINPUT: return "an input entry breaks the preconditions (validation mode)";
+    case MD_EINPUT: return "an input breaks the preconditions (validation mode) or a given shared exponent was not taken";
     default: return "unknown error";
     }
 }
