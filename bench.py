@@ -29,6 +29,10 @@ configs (skip with --no-configs): the other workloads of the scope, quad-double
 1024^3, double-double 2048^3 and octo-double 1024^3 with the adjoint (three
 products per step), hexa-double 1024^3, in the slice forms that apply.
 
+depth_split (skip with --no-split): the benchmark product as exact fixed-point
+integers, whole and cut into four depth blocks on the full matrices' exponents,
+summed exactly and rounded once; must equal the product's output.
+
 paper_inner_products (skip with --no-dot): the paper's own experiment
 (Section 3, Table 2), 1,024 m-double inner products of length 6,144 on its
 bit pattern for m = 1, 2, 4, 8, 16, through the batched inner-product entry
@@ -318,6 +322,49 @@ def other_configs(md, torch, steps=3):
     return res
 
 
+def depth_split(md, torch, A, B, C, info, blocks=4, steps=2):
+    """The benchmark product as exact fixed-point integers: the whole
+    product's integer (md_gemm_fixed), and the depth cut into equal blocks
+    split on the full matrices' exponents (md_exponents), their integers
+    summed (md_fixed_add) and rounded once (md_fixed_round) -- one GPU's
+    share of a depth-split product and its exact reduction.  Milliseconds
+    per step of each, and whether the rounded sum equals C (md_gemm_ex's
+    output for the same S) in every entry."""
+    form = "int8bal" if info["beta"] == 8 else ("int8" if info["beta"] == 7 else "fp64")
+    S, beta = info["S"], info["beta"]
+    m, M, K = A.shape
+    N = B.shape[2]
+    nlimb = md.fixed_limbs(beta, S, K)
+    cuts = [K * q // blocks for q in range(blocks + 1)]
+
+    def whole():
+        return md.gemm_fixed(A, B, S=S, beta=beta, form=form)[:2]
+
+    def split():
+        E, F = md.exponents(A, B)
+        acc = sc = None
+        for a, b in zip(cuts[:-1], cuts[1:]):
+            Xb, sc, _ = md.gemm_fixed(A[:, :, a:b], B[:, a:b, :], E, F, S=S, beta=beta, form=form,
+                                      nlimb=nlimb)
+            acc = Xb if acc is None else md.fixed_add(acc, Xb, out=acc)
+        return md.fixed_round(acc, sc, m)
+
+    res = {"form": form, "S": S, "beta": beta, "limbs": nlimb, "blocks": blocks}
+    for name, fn in (("whole_fixed_ms", whole), ("split_sum_round_ms", split)):
+        out = fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            out = fn()
+        torch.cuda.synchronize()
+        res[name] = round((time.perf_counter() - t0) * 1e3 / steps, 3)
+        if name == "split_sum_round_ms":
+            res["rounded_sum_equals_product"] = bool(torch.equal(out, C))
+        del out
+        torch.cuda.empty_cache()
+    return res
+
+
 def small_case(md, torch, reps=200):
     """Double-double 64^3, the smallest workload, where launches and the
     host round trip dominate: microseconds per product (a) eager with the
@@ -399,6 +446,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-dot", action="store_true",
                     help="skip the paper's inner-product workload (m = 1..16)")
+    ap.add_argument("--no-split", action="store_true",
+                    help="skip the fixed-point depth split of the benchmark product")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the other workloads (qd1024, dd2048 and od1024 with the adjoint, hd1024)")
     ap.add_argument("--forms", default="int8bal,int8,fp64",
@@ -536,6 +585,9 @@ def main():
                      "work_per_launch": f"2*M*N*K*S(S+1)/2 = {ops8:.4e} int8 ops (unit: int8 TOP/s)",
                      "algorithmic_bytes_per_launch": int(2 * S8 * M * K + 8 * m * M * N)},
     }
+    if not args.no_split:
+        out["depth_split"] = depth_split(md, torch, A, B, C8, info8)
+        progress("depth split done")
     defer_error(head_form, "max_log2_err_sampled", Ah, Bh, C8)
     defer_error(out["fp64_form"], "max_log2_err_sampled", Ah, Bh, C64)
     if sm is not None:

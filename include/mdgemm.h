@@ -263,9 +263,11 @@ int md_exponents(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda, 
  *   nlimb: at least md_fixed_limbs(force_beta, force_S, K), at most 80
  *          (MD_ERANGE otherwise).
  * X and scale must not overlap each other (MD_EALIAS).  K must be at least
- * 1 (MD_EINVAL_DIM); M = 0 or N = 0 is a no-op.  Besides the product's
- * scratch, the call allocates S M N int64 diagonal sums and m M N doubles
- * on `stream` (freed on return, stream-ordered).
+ * 1 (MD_EINVAL_DIM); M = 0 or N = 0 is a no-op.  The INT8 forms whose
+ * whole depth is one exactness chunk, and every banded contraction, write
+ * the integers from their own epilogue at the product's speed; the other
+ * cases (FP64 bands folded in LDS, INT8 triangles over several chunks)
+ * capture the S M N int64 diagonal sums in scratch and fold them after.
  */
 int md_gemm_fixed(int m, int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
                   int64_t plane_stride_A, const double *B, int64_t ldb, int64_t plane_stride_B,

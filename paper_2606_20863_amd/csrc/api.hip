@@ -387,17 +387,27 @@ size_t md_workspace_size(int form, int64_t M, int64_t N, int64_t K, int S)
 
 namespace {
 
+// Exact fixed-point output of a product: nlimb limb planes X and scale.
+struct FixedOut {
+    int32_t* X;
+    int32_t* scale;
+    int nlimb;
+};
+
 // md_gemm_ex; E_in / F_in (optional, device, M and N entries): shared
 // exponents that replace those of op(A)'s rows and op(B)'s columns (a
 // forced S is then required: the rule's certificates hold for the data's
 // own exponents only).  An override below the data's own exponent, or above
 // 1100, is not taken: bit 8 goes into *exp_flags (device, zeroed by the
-// caller) and the data's own exponent stays.
+// caller) and the data's own exponent stays.  fx (optional): write the exact
+// integers instead of C (C is then ignored): the whole-triangle INT8 kernels
+// with one exactness chunk and the buffer fold write them directly; the other
+// paths capture the diagonal sums in an [S][M][N] buffer and fold them after.
 int gemm_impl(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, const double* A,
               int64_t lda, int64_t plane_stride_A, const double* B, int64_t ldb,
               int64_t plane_stride_B, double* C, int64_t ldc, int64_t plane_stride_C,
               const md_opts* opts, void* stream, const int32_t* E_in, const int32_t* F_in,
-              int32_t* exp_flags)
+              int32_t* exp_flags, const FixedOut* fx)
 {
     g_last_hip = 0;
     if (m != 1 && m != 2 && m != 4 && m != 8 && m != 16)
@@ -414,20 +424,22 @@ int gemm_impl(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, co
         return MD_EINVAL_OPT;
     if (M == 0 || N == 0)
         return MD_OK;
-    if (!C || (K > 0 && (!A || !B)))
+    if ((!C && !fx) || (K > 0 && (!A || !B)))
         return MD_ENULL;
+    if (fx && (K == 0 || !fx->X || !fx->scale))
+        return MD_EINVAL_DIM;
     // leading dimensions and plane strides
-    if (ldc < N || plane_stride_C < 1)
+    if (!fx && (ldc < N || plane_stride_C < 1))
         return MD_EINVAL_DIM;
     if (K > 0) {
         if (lda < (transA ? M : K) || ldb < (transB ? K : N) || plane_stride_A < 1 || plane_stride_B < 1)
             return MD_EINVAL_DIM;
     }
-    if (!mul_ok(M, std::max<int64_t>(ldc, 1)) || !mul_ok(std::max<int64_t>(M, K), std::max<int64_t>(lda, 1)) ||
+    if (!mul_ok(M, std::max<int64_t>(fx ? N : ldc, 1)) || !mul_ok(std::max<int64_t>(M, K), std::max<int64_t>(lda, 1)) ||
         !mul_ok(std::max<int64_t>(K, N), std::max<int64_t>(ldb, 1)) || M > (INT64_C(1) << 40) ||
         N > (INT64_C(1) << 40) || K > (INT64_C(1) << 40))
         return MD_EINVAL_DIM;
-    const Span sc = extent(C, m, M, N, ldc, 1, plane_stride_C);
+    const Span sc = fx ? Span{0, 0} : extent(C, m, M, N, ldc, 1, plane_stride_C);
     if (K > 0) {
         const Span sa = transA ? extent(A, m, K, M, lda, 1, plane_stride_A) : extent(A, m, M, K, lda, 1, plane_stride_A);
         const Span sb = transB ? extent(B, m, N, K, ldb, 1, plane_stride_B) : extent(B, m, K, N, ldb, 1, plane_stride_B);
@@ -563,6 +575,29 @@ int gemm_impl(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, co
     if ((size_t)ncol * 256 * sizeof(int64_t) > 160 * 1024)
         return MD_ERANGE;
 
+    const int64_t kcc = std::max<int64_t>(kc / kcg, 1);
+    int64_t* fixD = nullptr;
+    md_debug fixdbg;
+    if (fx) {
+        const bool tri2 = is_i8(o.form) && band == S && S <= kTriMaxI8 && kcc >= nkc;
+        if (!global_fold && !tri2) {
+            // no direct fixed-point epilogue on this path: capture the
+            // diagonal sums (the debug dump's route) and fold them after
+            void *pD, *pC;
+            int rc = scr.get((size_t)(M * N) * S * sizeof(int64_t), &pD);
+            if (!rc)
+                rc = scr.get((size_t)(M * N) * m * sizeof(double), &pC);
+            if (rc)
+                return rc;
+            memset(&fixdbg, 0, sizeof(fixdbg));
+            fixdbg.D = fixD = (int64_t*)pD;
+            dbg = &fixdbg;
+            C = (double*)pC;
+            ldc = N;
+            plane_stride_C = M * N;
+        }
+    }
+
     void *dA, *dB;
     int rc = scr.get(digits_bytes(o.form, M, K, S), &dA);
     if (rc)
@@ -609,7 +644,7 @@ int gemm_impl(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, co
     ga.M = M;
     ga.N = N;
     ga.nkc = nkc;
-    ga.kcc = std::max<int64_t>(kc / kcg, 1);
+    ga.kcc = kcc;
     ga.S = S;
     ga.beta = beta;
     ga.band = band;
@@ -620,12 +655,19 @@ int gemm_impl(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, co
     ga.gD = gD;
     ga.gR = gR;
     ga.gI8 = is_i8(o.form);
+    ga.fixX = fx && !fixD ? fx->X : nullptr;
+    ga.fixScale = fx && !fixD ? fx->scale : nullptr;
+    ga.fixNL = fx ? fx->nlimb : 0;
     if (o.ev_gemm_begin && (e = hipEventRecord((hipEvent_t)o.ev_gemm_begin, st)) != hipSuccess)
         return hip_fail(e);
     e = is_i8(o.form) ? launch_gemm_i8(ga, st) : launch_gemm_f64(ga, st);
     if (e != hipSuccess)
         return hip_fail(e);
     if (global_fold && (e = launch_gemm_final(ga, st)) != hipSuccess)
+        return hip_fail(e);
+    // E and F hold the grid starts (shared exponent + offset): no offset here
+    if (fixD && (e = launch_fixed_from_D(fixD, S, beta, M, N, E, F, 0, ncol, fx->X, fx->nlimb, fx->scale,
+                                         st)) != hipSuccess)
         return hip_fail(e);
     if (o.ev_gemm_end && (e = hipEventRecord((hipEvent_t)o.ev_gemm_end, st)) != hipSuccess)
         return hip_fail(e);
@@ -663,7 +705,7 @@ int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, c
                const md_opts* opts, void* stream)
 {
     return gemm_impl(m, transA, transB, M, N, K, A, lda, plane_stride_A, B, ldb, plane_stride_B, C, ldc,
-                     plane_stride_C, opts, stream, nullptr, nullptr, nullptr);
+                     plane_stride_C, opts, stream, nullptr, nullptr, nullptr, nullptr);
 }
 
 int md_dot_ex(int m, int64_t batch, int64_t n, const double* X, int64_t ldx, int64_t plane_stride_X,
@@ -1016,37 +1058,24 @@ int md_gemm_fixed(int m, int64_t M, int64_t N, int64_t K, const double* A, int64
     hipStream_t st = (hipStream_t)stream;
     Scratch scr;
     scr.st = st;
-    void *pD, *pC, *pE;
-    int rc = scr.get((size_t)(M * N) * S * sizeof(int64_t), &pD);
-    if (!rc)
-        rc = scr.get((size_t)(M * N) * m * sizeof(double), &pC);
-    if (!rc)
-        rc = scr.get((size_t)(M + N + 64) * sizeof(int32_t), &pE);
-    if (rc)
-        return rc;
-    int32_t* flags = (int32_t*)pE;   // an int64 slot: bit 8 = an exponent override not taken
-    int32_t* Eown = flags + 64;
-    int32_t* Fown = Eown + M;
+    int32_t* flags = nullptr;   // an int64 slot: bit 8 = an exponent override not taken
     hipError_t e;
-    if ((e = launch_fill_zero_i64((int64_t*)flags, 1, st)) != hipSuccess)
-        return hip_fail(e);
-    md_debug d;
-    memset(&d, 0, sizeof(d));
-    d.D = (int64_t*)pD;
-    d.E = E ? nullptr : Eown;
-    d.F = F ? nullptr : Fown;
+    if (E || F) {
+        void* p;
+        const int rc = scr.get(sizeof(int64_t), &p);
+        if (rc)
+            return rc;
+        flags = (int32_t*)p;
+        if ((e = launch_fill_zero_i64((int64_t*)flags, 1, st)) != hipSuccess)
+            return hip_fail(e);
+    }
     md_opts o = *opts;
-    o.dbg = &d;
-    rc = gemm_impl(m, 0, 0, M, N, K, A, lda, plane_stride_A, B, ldb, plane_stride_B, (double*)pC, N, M * N,
-                   &o, stream, E, F, flags);
+    const FixedOut fo{X, scale, nlimb};
+    const int rc = gemm_impl(m, 0, 0, M, N, K, A, lda, plane_stride_A, B, ldb, plane_stride_B, nullptr, 0, 0,
+                             &o, stream, E, F, flags, &fo);
     if (rc)
         return rc;
-    const int kcg = is_i8(o.form) ? kKcI8 : kKcF64;
-    const int ncol = fold_columns(beta, S, round_up(K, kcg));
-    if ((e = launch_fixed_from_D((const int64_t*)pD, S, beta, M, N, E ? E : Eown, F ? F : Fown,
-                                 grid_offset(o.form), ncol, X, nlimb, scale, st)) != hipSuccess)
-        return hip_fail(e);
-    if (E || F) {
+    if (flags) {
         int32_t fl = 0;
         if ((e = hipMemcpyAsync(&fl, flags, sizeof(fl), hipMemcpyDeviceToHost, st)) != hipSuccess)
             return hip_fail(e);

@@ -27,8 +27,10 @@ constexpr int kRing = 8;   // diagonal sums in flight per thread
 // index is a runtime count, served from a ring of prefetched sums.  Then the
 // magnitude is rounded greedily, word by word (the triangle kernels'
 // register renormalisation).  With a debug buffer the sums are also written
-// there as [S][M][N].
-template <int NL>
+// there as [S][M][N].  FIX: the folded integer itself (two's complement
+// limbs, the window's sign past NL) and its scale go to a.fixX and
+// a.fixScale instead of rounded words.
+template <int NL, bool FIX>
 __global__ __launch_bounds__(256) void k_gemm_final(GemmArgs a)
 {
     const int R = a.gR;
@@ -77,6 +79,20 @@ __global__ __launch_bounds__(256) void k_gemm_final(GemmArgs a)
         L[k] = (uint32_t)(uint64_t)win;
         win >>= 32;
     }
+    if constexpr (FIX) {
+        if (!ok)
+            return;
+        const int64_t count = a.M * a.N, e = i * a.N + j;
+        for (int k = 0; k < a.fixNL; ++k) {
+            uint32_t v = win < 0 ? 0xffffffffu : 0u;
+#pragma unroll
+            for (int q = 0; q < NL; ++q)
+                v = q == k ? L[q] : v;
+            a.fixX[(int64_t)k * count + e] = (int32_t)v;
+        }
+        a.fixScale[e] = a.E[i] + a.F[j] - a.beta * (a.S + 1);
+        return;
+    }
     // magnitude (two's complement negation when X < 0)
     const bool neg = win < 0;
     uint64_t cy = 1;
@@ -99,7 +115,10 @@ __global__ __launch_bounds__(256) void k_gemm_final(GemmArgs a)
 template <int NL>
 hipError_t launch_final(const GemmArgs& a, unsigned blocks, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_gemm_final<NL>, dim3(blocks), dim3(256), 0, st, a);
+    if (a.fixX)
+        hipLaunchKernelGGL((k_gemm_final<NL, true>), dim3(blocks), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_gemm_final<NL, false>), dim3(blocks), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -62,6 +62,13 @@ struct GemmArgs {
     int64_t* gD;
     int gR;                 // row blocks per wave of that layout (1 or 2)
     int gI8;                // accumulator rows as in the INT8 (1) or FP64 (0) matrix cores
+    // Fixed-point output (optional): the whole-triangle fixed-point kernels
+    // and the buffer fold write the exact integers X (fixNL two's complement
+    // 32-bit limb planes of M N entries, least significant first) and their
+    // scales E_i + F_j - beta (S+1) instead of rounded words.
+    int32_t* fixX;
+    int32_t* fixScale;
+    int fixNL;
 };
 
 // int64 elements of the diagonal-sum buffer for an M x N product
@@ -122,6 +129,11 @@ hipError_t launch_tri_s29_32(const GemmArgs& a, hipStream_t st);
 hipError_t launch_tri8_s1_22(const GemmArgs& a, hipStream_t st);
 hipError_t launch_tri8_s23_28(const GemmArgs& a, hipStream_t st);
 hipError_t launch_tri8_s29_32(const GemmArgs& a, hipStream_t st);
+// their fixed-point variants (a.fixX set, one exactness chunk)
+hipError_t launch_trifix_s1_22(const GemmArgs& a, hipStream_t st);
+hipError_t launch_trifix_s23_32(const GemmArgs& a, hipStream_t st);
+hipError_t launch_trifix8_s1_22(const GemmArgs& a, hipStream_t st);
+hipError_t launch_trifix8_s23_32(const GemmArgs& a, hipStream_t st);
 
 // Batched inner products out_b = sum_k x_bk y_bk: both operands are split
 // with the vectors as rows (fragment layout of op(A)), so block rb of 16

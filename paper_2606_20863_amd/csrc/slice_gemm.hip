@@ -260,6 +260,13 @@ hipError_t launch_gemm_i8(const GemmArgs& a, hipStream_t st)
     // the triangle kernel's register fold holds |X| / 2^(4 beta ceil(S/4))
     // < K 2^9 in its signed top column
     if (a.nbands == 1 && a.S <= kTriMaxI8 && a.nkc * kKcI8 < ((int64_t)1 << 48)) {
+        if (a.fixX) {
+            if (a.beta == 8)
+                return a.S <= 22 ? launch_trifix8_s1_22(a, st) : launch_trifix8_s23_32(a, st);
+            if (a.beta != 7)
+                return hipErrorInvalidValue;
+            return a.S <= 22 ? launch_trifix_s1_22(a, st) : launch_trifix_s23_32(a, st);
+        }
         if (a.beta == 8) {
             if (a.S <= 22)
                 return launch_tri8_s1_22(a, st);

@@ -124,7 +124,10 @@ __device__ __forceinline__ void tri_fold(const v4i (&acc)[R][S], int64_t (&x)[4 
 }
 
 // Greedy renormalisation of the lane's 4 R outputs, their steps interleaved.
-template <int S, int R, int B>
+// FIX: instead, the exact integers as two's complement limb planes
+// (a.fixX[k * M N + i N + j], limbs past the register ones filled with the
+// sign) and their scales (a.fixScale[i N + j]).
+template <int S, int R, int B, bool FIX = false>
 __device__ __forceinline__ void tri_outputs(int64_t (&x)[4 * R][(Tri<S, B>::kCols)], const GemmArgs& a,
                                             int64_t rb0, int64_t cb, int lane)
 {
@@ -140,6 +143,32 @@ __device__ __forceinline__ void tri_outputs(int64_t (&x)[4 * R][(Tri<S, B>::kCol
         scale[n] = ok[n] ? a.E[i] + a.F[j] - B * (S + 1) : 0;
         out[n] = a.C + (ok[n] ? i * a.ldc + j : 0);
         sgn[n] = to_limbs<Tri<S, B>::kCW>(x[n], L[n]) ? -1.0 : 1.0;
+    }
+    if constexpr (FIX) {
+        const int64_t count = a.M * a.N;
+#pragma unroll
+        for (int n = 0; n < NO; ++n) {
+            const int64_t e = ((rb0 + n / 4) * 16 + FormI8::row(lane, n % 4)) * a.N + cb * 16 + (lane & 15);
+            const bool neg = sgn[n] < 0.0;
+            uint64_t cy = 1;
+#pragma unroll
+            for (int k = 0; k < NL; ++k) {
+                const uint64_t v = (uint64_t)(~L[n][k]) + cy;
+                cy = v >> 32;
+                L[n][k] = neg ? (uint32_t)v : L[n][k];
+            }
+            if (!ok[n])
+                continue;
+            for (int k = 0; k < a.fixNL; ++k) {
+                uint32_t v = neg ? 0xffffffffu : 0u;
+#pragma unroll
+                for (int q = 0; q < NL; ++q)
+                    v = q == k ? L[n][q] : v;
+                a.fixX[(int64_t)k * count + e] = (int32_t)v;
+            }
+            a.fixScale[e] = scale[n];
+        }
+        return;
     }
     for (int t = 0; t < a.m; ++t) {
 #pragma unroll
@@ -215,6 +244,38 @@ __global__ __launch_bounds__(256, 1) void k_tri2_i8(GemmArgs a)
     tri_outputs<S, 2, B>(x, a, w.rb, w.cb, w.lane);
 }
 
+// The same contraction returning the exact integers (a.fixX, a.fixScale)
+// instead of rounded words.  (Its own copy of the body: the rounding
+// kernel's code stays exactly as it is tuned.)
+template <int S, int B>
+__global__ __launch_bounds__(256, 1) void k_tri2_i8_fixed(GemmArgs a)
+{
+    const WaveTile w(a, 2);
+    const uint64_t bytes = (uint64_t)a.nkc * S * 1024;
+    const int64_t nrb = 2 * ((a.M + kTile - 1) / kTile);
+    FragStream LA[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+        LA[r] = frag_stream((const char*)a.A + (w.rb + r) * bytes, w.rb + r < nrb ? bytes : 0,
+                            w.lane);
+    const FragStream LB = frag_stream((const char*)a.B + w.cb * bytes, bytes, w.lane);
+    v4i acc[2][S];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int g = 0; g < S; ++g)
+            acc[r][g] = FormI8::zero();
+    tri_run_i8<S, 2, kLeadA>(acc, LA, LB, 0, a.nkc);
+    int64_t x[8][Tri<S, B>::kCols];
+#pragma unroll
+    for (int n = 0; n < 8; ++n)
+#pragma unroll
+        for (int j = 0; j < Tri<S, B>::kCols; ++j)
+            x[n][j] = 0;
+    tri_fold<S, 2, false, B>(acc, x, a, w.rb, w.cb, w.lane);
+    tri_outputs<S, 2, B, true>(x, a, w.rb, w.cb, w.lane);
+}
+
 // Launch the triangle kernel for a.S in [LO, S], B-bit digits: two row
 // blocks per wave when the whole depth is one exactness chunk (and no debug
 // dump is asked for), else one.
@@ -230,6 +291,22 @@ struct DispatchTriRange {
         }
         if constexpr (S > LO)
             return DispatchTriRange<S - 1, LO, B>::run(a, st);
+        return hipErrorInvalidValue;
+    }
+};
+
+// The fixed-point variant for a.S in [LO, S]: the whole depth must be one
+// exactness chunk.
+template <int S, int LO, int B>
+struct DispatchTriFixRange {
+    static hipError_t run(const GemmArgs& a, hipStream_t st)
+    {
+        if (a.kcc < a.nkc || !a.fixX || !a.fixScale)
+            return hipErrorInvalidValue;
+        if (a.S == S)
+            return launch_kernel(k_tri2_i8_fixed<S, B>, a, st, false, 2 * kTile);
+        if constexpr (S > LO)
+            return DispatchTriFixRange<S - 1, LO, B>::run(a, st);
         return hipErrorInvalidValue;
     }
 };

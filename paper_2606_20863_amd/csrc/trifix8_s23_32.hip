@@ -1,0 +1,12 @@
+// Whole-triangle INT8 slice contraction kernels returning exact fixed-point
+// integers, S = 23..32, balanced 8-bit digits.
+#include "tri.h"
+
+namespace mdg {
+
+hipError_t launch_trifix8_s23_32(const GemmArgs& a, hipStream_t st)
+{
+    return DispatchTriFixRange<32, 23, 8>::run(a, st);
+}
+
+}  // namespace mdg

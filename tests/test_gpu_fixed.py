@@ -26,9 +26,12 @@ from oracle import exact as ox
 
 pytestmark = pytest.mark.gpu
 
-# (form, beta, S): FP64 slices; INT8 whole triangle (7-bit, 8-bit);
-# INT8 bands with the diagonal-sum buffer (S > 32, equal bands of at most 16)
-CASES = [("fp64", 16, 7), ("int8", 7, 12), ("int8bal", 8, 9), ("int8bal", 8, 27),
+# (form, beta, S): FP64 slices folded in LDS (sums captured, folded after)
+# and through the sum buffer (beta (S+1) > 230 bits: the buffer fold writes
+# the integers); INT8 whole triangle (7-bit, 8-bit: the fixed-point triangle
+# kernels); INT8 bands with the diagonal-sum buffer (S > 32, equal bands of
+# at most 16: the buffer fold)
+CASES = [("fp64", 16, 7), ("fp64", 20, 12), ("int8", 7, 12), ("int8bal", 8, 9), ("int8bal", 8, 27),
          ("int8", 7, 42), ("int8bal", 8, 48)]
 
 
