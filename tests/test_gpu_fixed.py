@@ -275,3 +275,23 @@ def test_depth_split_at_the_benchmark_size():
     ti, tj = torch.from_numpy(rows).cuda(), torch.from_numpy(cols).cuda()
     np.testing.assert_array_equal(Xw[:, ti][:, :, tj].cpu().numpy(), limbs_of(Xo, nlimb))
     np.testing.assert_array_equal(scw[ti][:, tj].cpu().numpy(), so.astype(np.int32))
+
+
+@pytest.mark.parametrize("S", range(1, 33))
+@pytest.mark.parametrize("form", ["int8", "int8bal"])
+def test_fixed_triangle_kernel_every_S(form, S):
+    """Every instantiated fixed-point triangle kernel (S = 1..32, 7- and
+    8-bit digits) on ragged sizes (row and column tiles past M and N): the
+    integers equal the oracle's, and rounding them gives md_gemm_ex's
+    output."""
+    m, M, N, K = 2, 40, 36, 70
+    beta = 8 if form == "int8bal" else 7
+    A, B = operands(500 + S, m, M, N, K)
+    X, scale, info = md.gemm_fixed(dev(A), dev(B), S=S, beta=beta, form=form)
+    Cg, _ = md.gemm_ex(dev(A), dev(B), form=form, force_S=S, force_beta=beta)
+    torch.cuda.synchronize()
+    assert info["band"] == S
+    Xo, so = ox.fixed_product(A, B, beta, S, balanced=form == "int8bal")
+    np.testing.assert_array_equal(X.cpu().numpy(), limbs_of(Xo, X.shape[0]))
+    np.testing.assert_array_equal(scale.cpu().numpy(), so.astype(np.int32))
+    np.testing.assert_array_equal(md.fixed_round(X, scale, m).cpu().numpy(), Cg.cpu().numpy())
