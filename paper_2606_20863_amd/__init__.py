@@ -302,11 +302,28 @@ def fixed_limbs(beta: int, S: int, K: int) -> int:
 
 def _strided_planes(X: torch.Tensor, name: str):
     """(pointer, leading dimension, plane stride) of float64 planes whose
-    rows are contiguous (a column block of larger planes is allowed)."""
+    rows are contiguous (a column block of larger planes is allowed).  The
+    view's own strides are passed, so the library reads exactly the view's
+    elements; only a dimension of size 1 (whose stride is never used) gets
+    the dense value.  Rows or planes that overlap (a broadcast view) are
+    refused."""
     _check_planes(X, name)
-    if X.stride(2) != 1 and X.shape[2] > 1:
+    ld, ps = _plane_layout(tuple(X.shape), tuple(X.stride()), name)
+    return _ptr(X), ld, ps
+
+
+def _plane_layout(shape, strides, name="X"):
+    """(leading dimension, plane stride) for planes of the given shape and
+    element strides; ValueError for non-contiguous rows or overlapping rows
+    or planes."""
+    m, R, Cc = shape
+    if strides[2] != 1 and Cc > 1:
         raise ValueError(f"{name} must have contiguous rows")
-    return _ptr(X), max(X.stride(1), X.shape[2]), max(X.stride(0), 1)
+    ld = strides[1] if R > 1 else Cc
+    ps = strides[0] if m > 1 else R * ld
+    if (R > 1 and ld < Cc) or (m > 1 and ps < (R - 1) * ld + Cc):
+        raise ValueError(f"{name}: rows or planes overlap")
+    return ld, ps
 
 
 def exponents(A: torch.Tensor, B: torch.Tensor, stream=None):

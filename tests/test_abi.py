@@ -231,3 +231,22 @@ def test_fixed_argument_errors_before_device_work():
     assert L.md_fixed_round(2, 16, 4, x, sc, c, 15, None) == 2
     assert L.md_fixed_round(2, 16, 4, x, sc, ctypes.c_void_p(0x500000 + 64), 16, None) == 4
     assert L.md_fixed_round(2, 0, 4, None, None, None, 0, None) == 0
+
+
+def test_plane_layout_of_views():
+    """The binding passes a view's own strides (a depth block of larger
+    planes addresses the parent in place) and refuses broadcast or
+    transposed views, whose dense reading would leave the view."""
+    import torch
+    x = torch.zeros(2, 3, 5, dtype=torch.float64)
+    lay = lambda t: md._plane_layout(tuple(t.shape), tuple(t.stride()))
+    assert lay(x) == (5, 15)
+    assert lay(x[:, :, 1:4]) == (5, 15)
+    assert lay(x[:, 1:, :]) == (5, 15)
+    assert lay(x[:1]) == (5, 15) and lay(x[:, :1, :]) == (5, 15)
+    with pytest.raises(ValueError):
+        lay(torch.zeros(5, dtype=torch.float64).expand(2, 3, 5))
+    with pytest.raises(ValueError):
+        lay(torch.zeros(3, 5, dtype=torch.float64).expand(2, 3, 5))
+    with pytest.raises(ValueError):
+        lay(x.transpose(1, 2))

@@ -295,3 +295,14 @@ def test_fixed_triangle_kernel_every_S(form, S):
     np.testing.assert_array_equal(X.cpu().numpy(), limbs_of(Xo, X.shape[0]))
     np.testing.assert_array_equal(scale.cpu().numpy(), so.astype(np.int32))
     np.testing.assert_array_equal(md.fixed_round(X, scale, m).cpu().numpy(), Cg.cpu().numpy())
+
+
+def test_broadcast_views_are_refused():
+    """A broadcast view would be read past its storage if taken as dense
+    planes: the binding refuses it before any call."""
+    A = torch.zeros(64, dtype=torch.float64, device="cuda").expand(2, 16, 64)
+    B = torch.zeros(2, 64, 8, dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        md.gemm_fixed(A, B, S=4, beta=8, form="int8bal")
+    with pytest.raises(ValueError):
+        md.exponents(A, B)
