@@ -107,7 +107,9 @@ typedef struct md_info {
 } md_info;
 
 /* Debug dump (small shapes): every non-NULL pointer is a device buffer the
- * caller owns; the library writes it during the call. */
+ * caller owns, of at least the size shown; the library writes it during the
+ * call.  digits_A, digits_B and D are sized by S, so they need a forced S
+ * (opts->force_S; MD_EINVAL_OPT otherwise). */
 typedef struct md_debug {
     int32_t *E;         /* [M]      shared exponents of the rows of op(A) (the balanced
                                     digits' grid starts 2 above) */

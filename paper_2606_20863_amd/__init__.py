@@ -201,9 +201,19 @@ def gemm_ex(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None, *, 
     dbg = None
     if debug:
         dbg = MDDebug()
+        need = {"E": (M, torch.int32), "F": (N, torch.int32),
+                "digits_A": (force_S * M * K, torch.int32), "digits_B": (force_S * N * K, torch.int32),
+                "D": (force_S * M * N, torch.int64)}
         for key in ("E", "F", "digits_A", "digits_B", "D"):
-            if key in debug and debug[key] is not None:
-                setattr(dbg, key, debug[key].data_ptr())
+            t = debug.get(key)
+            if t is None:
+                continue
+            if key not in ("E", "F") and force_S <= 0:
+                raise ValueError(f"debug {key} is sized by S: pass force_S")
+            n, dt = need[key]
+            if t.dtype != dt or not t.is_cuda or not t.is_contiguous() or t.numel() < n:
+                raise ValueError(f"debug {key} must be a contiguous {dt} device tensor of >= {n} elements")
+            setattr(dbg, key, t.data_ptr())
         opts.dbg = ctypes.pointer(dbg)
     lda = A.shape[2]
     ldb = B.shape[2]

@@ -453,6 +453,9 @@ int gemm_impl(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, co
         return MD_EINVAL_OPT;
     if ((E_in || F_in) && (o.force_S == 0 || !exp_flags))
         return MD_EINVAL_OPT;
+    // the dumps sized by S need S fixed before the call
+    if (o.dbg && (o.dbg->digits_A || o.dbg->digits_B || o.dbg->D) && o.force_S == 0)
+        return MD_EINVAL_OPT;
 
     hipStream_t st = (hipStream_t)stream;
     if (K == 0) {

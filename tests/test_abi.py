@@ -250,3 +250,17 @@ def test_plane_layout_of_views():
         lay(torch.zeros(3, 5, dtype=torch.float64).expand(2, 3, 5))
     with pytest.raises(ValueError):
         lay(x.transpose(1, 2))
+
+
+def test_debug_dumps_sized_by_S_need_a_forced_S():
+    """Digit and diagonal-sum dumps are sized by S: with the rule choosing S
+    the call refuses them before any device work."""
+    L = md.lib()
+    a = ctypes.c_void_p(0x100000)
+    b = ctypes.c_void_p(0x900000)
+    opts = md.MDOpts()
+    dbg = md.MDDebug()
+    dbg.D = 0x700000
+    opts.dbg = ctypes.pointer(dbg)
+    assert L.md_gemm_ex(2, 0, 0, 4, 4, 4, a, 4, 16, b, 4, 16, ctypes.c_void_p(0x500000), 4, 16,
+                        ctypes.byref(opts), None) == 7
