@@ -88,13 +88,14 @@ __global__ void k_exp_init(int32_t* hi, int32_t* lo, int64_t R, int32_t* stats)
         *reinterpret_cast<unsigned long long*>(stats + 2) = ~0ull;
 }
 
-// Block: 16 rows x 1024 depth, 256 threads, 16 threads per row.  Each row's
+// Block: 16 rows x 256 depth, 256 threads, 16 threads per row (short
+// blocks: many waves in flight, each with its loads unrolled).  Each row's
 // threads reduce with wavefront shuffles: in row order (the depth
 // contiguous) they are 16 adjacent lanes (xor 1, 2, 4, 8); in column order
 // (rows_fast: the rows contiguous, as for the columns of B) they are lanes
 // 16 apart in each of the four waves (xor 16, 32), and every wave adds its
 // partial row result by atomics.
-constexpr int kExpRows = 16, kExpDepth = 1024;
+constexpr int kExpRows = 16, kExpDepth = 256;
 
 __global__ __launch_bounds__(256) void k_exp_partial(Operand op, int32_t* hi, int32_t* lo,
                                                      int rows_fast)
@@ -108,6 +109,7 @@ __global__ __launch_bounds__(256) void k_exp_partial(Operand op, int32_t* hi, in
     if (r < op.R) {
         const double* p = op.p + r * op.sr;
         const int64_t kend = min(k0 + (int64_t)kExpDepth, op.K);
+#pragma unroll 4
         for (int64_t k = k0 + tk; k < kend; k += 16) {
             const double x = p[k * op.sk];
             if (x != 0.0) {
