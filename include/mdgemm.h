@@ -134,6 +134,9 @@ typedef struct md_opts {
     int validate;          /* nonzero: check the input preconditions first (one read of
                               the inputs and one synchronisation); MD_EINPUT, with C
                               untouched and md_info.input_flags set, if any fails */
+    int32_t *exp_flags;    /* md_gemm_fixed with given E or F: optional device int32 into
+                              which bit 8 is ORed (never cleared) when a given exponent is
+                              not taken, instead of a synchronisation and MD_EINPUT */
 } md_opts;
 
 /*
@@ -261,7 +264,9 @@ int md_exponents(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda, 
  *          least the data's own and at most 1100; otherwise the call
  *          returns MD_EINPUT with md_info.input_flags bit 8 (if opts->info),
  *          X and scale unspecified.  Given E or F make the call synchronise
- *          `stream` once to check them.
+ *          `stream` once to check them, unless opts->exp_flags is set: then
+ *          bit 8 is ORed into that device word on the stream (one word can
+ *          collect every block of a split) and the call does not wait.
  *   nlimb: at least md_fixed_limbs(force_beta, force_S, K), at most 80
  *          (MD_ERANGE otherwise).
  * X and scale must not overlap each other (MD_EALIAS).  K must be at least

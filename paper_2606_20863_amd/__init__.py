@@ -61,7 +61,7 @@ class MDOpts(ctypes.Structure):
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
                 ("dbg", ctypes.POINTER(MDDebug)), ("info", ctypes.POINTER(MDInfo)),
                 ("ev_gemm_begin", ctypes.c_void_p), ("ev_gemm_end", ctypes.c_void_p),
-                ("validate", ctypes.c_int)]
+                ("validate", ctypes.c_int), ("exp_flags", ctypes.c_void_p)]
 
 
 class MDError(RuntimeError):
@@ -354,15 +354,17 @@ def exponents(A: torch.Tensor, B: torch.Tensor, stream=None):
 
 def gemm_fixed(A: torch.Tensor, B: torch.Tensor, E: torch.Tensor | None = None,
                F: torch.Tensor | None = None, *, S: int, beta: int, form="fp64", nlimb=None,
-               stream=None):
+               flags: torch.Tensor | None = None, stream=None):
     """Exact integer X (nlimb, M, N) int32 limb planes and scale (M, N) of
     the product A B before its rounding, C~ = X 2^scale.
 
     A (m, M, K) and B (m, K, N) may be depth blocks of larger planes (views
     with contiguous rows); E, F: the shared exponents to split on (those of
     the full matrices for a depth-split product), None for the data's own.
-    nlimb defaults to the limbs of a depth-K product.  Returns (X, scale,
-    info dict)."""
+    nlimb defaults to the limbs of a depth-K product.  ``flags``: an int32
+    device tensor into which bit 8 is ORed when a given exponent is not
+    taken, without synchronising (else the call waits and raises).  Returns
+    (X, scale, info dict)."""
     pa, lda, psa = _strided_planes(A, "A")
     pb, ldb, psb = _strided_planes(B, "B")
     m, M, K = A.shape
@@ -383,6 +385,10 @@ def gemm_fixed(A: torch.Tensor, B: torch.Tensor, E: torch.Tensor | None = None,
     opts.force_S = S
     opts.force_beta = beta
     opts.info = ctypes.pointer(info)
+    if flags is not None:
+        if flags.dtype != torch.int32 or not flags.is_cuda or flags.numel() < 1:
+            raise ValueError("flags must be an int32 device tensor")
+        opts.exp_flags = ctypes.c_void_p(flags.data_ptr())
     rc = lib().md_gemm_fixed(m, M, N, K, pa, lda, psa, pb, ldb, psb,
                              None if E is None else _ptr(E), None if F is None else _ptr(F),
                              _ptr(X), nlimb, _ptr(scale), ctypes.byref(opts), _stream_handle(stream))

@@ -1061,9 +1061,10 @@ int md_gemm_fixed(int m, int64_t M, int64_t N, int64_t K, const double* A, int64
     hipStream_t st = (hipStream_t)stream;
     Scratch scr;
     scr.st = st;
-    int32_t* flags = nullptr;   // an int64 slot: bit 8 = an exponent override not taken
+    int32_t* flags = opts->exp_flags;   // bit 8: an exponent override not taken
+    const bool wait = (E || F) && !flags;
     hipError_t e;
-    if (E || F) {
+    if (wait) {
         void* p;
         const int rc = scr.get(sizeof(int64_t), &p);
         if (rc)
@@ -1078,7 +1079,7 @@ int md_gemm_fixed(int m, int64_t M, int64_t N, int64_t K, const double* A, int64
                              &o, stream, E, F, flags, &fo);
     if (rc)
         return rc;
-    if (flags) {
+    if (wait) {
         int32_t fl = 0;
         if ((e = hipMemcpyAsync(&fl, flags, sizeof(fl), hipMemcpyDeviceToHost, st)) != hipSuccess)
             return hip_fail(e);

@@ -264,3 +264,26 @@ def test_debug_dumps_sized_by_S_need_a_forced_S():
     opts.dbg = ctypes.pointer(dbg)
     assert L.md_gemm_ex(2, 0, 0, 4, 4, 4, a, 4, 16, b, 4, 16, ctypes.c_void_p(0x500000), 4, 16,
                         ctypes.byref(opts), None) == 7
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The binding's ctypes structures against the header compiled by gcc:
+    size and every field's offset."""
+    import subprocess
+    structs = {"md_info": md.MDInfo, "md_debug": md.MDDebug, "md_opts": md.MDOpts}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

@@ -306,3 +306,37 @@ def test_broadcast_views_are_refused():
         md.gemm_fixed(A, B, S=4, beta=8, form="int8bal")
     with pytest.raises(ValueError):
         md.exponents(A, B)
+
+
+def test_exponent_flags_without_waiting():
+    """With a device flag word the fixed-point calls do not synchronise: two
+    depth blocks on two streams with one shared flag word sum to the whole
+    product, the word stays 0; an exponent below the data's own sets bit 8
+    in it instead of raising."""
+    m, M, N, K, k0, S, beta = 2, 30, 26, 140, 61, 10, 8
+    A, B = operands(8080, m, M, N, K)
+    Ad, Bd = dev(A), dev(B)
+    E, F = md.exponents(Ad, Bd)
+    flags = torch.zeros(1, dtype=torch.int32, device="cuda")
+    nlimb = md.fixed_limbs(beta, S, K)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    cur = torch.cuda.current_stream()
+    s1.wait_stream(cur)
+    s2.wait_stream(cur)
+    with torch.cuda.stream(s1):
+        X1, sc, _ = md.gemm_fixed(Ad[:, :, :k0], Bd[:, :k0, :], E, F, S=S, beta=beta, form="int8bal",
+                                  nlimb=nlimb, flags=flags, stream=s1)
+    with torch.cuda.stream(s2):
+        X2, _, _ = md.gemm_fixed(Ad[:, :, k0:], Bd[:, k0:, :], E, F, S=S, beta=beta, form="int8bal",
+                                 nlimb=nlimb, flags=flags, stream=s2)
+    cur.wait_stream(s1)
+    cur.wait_stream(s2)
+    Xs = md.fixed_add(X1, X2)
+    Xw, scw, _ = md.gemm_fixed(Ad, Bd, S=S, beta=beta, form="int8bal")
+    torch.cuda.synchronize()
+    assert int(flags.item()) == 0
+    assert torch.equal(Xs, Xw) and torch.equal(sc, scw)
+    E[2] -= 1
+    md.gemm_fixed(Ad, Bd, E, F, S=S, beta=beta, form="int8bal", flags=flags)
+    torch.cuda.synchronize()
+    assert int(flags.item()) == 8
