@@ -327,7 +327,8 @@ def depth_split(md, torch, A, B, C, info, blocks=4, steps=2):
     product's integer (md_gemm_fixed), and the depth cut into equal blocks
     split on the full matrices' exponents (md_exponents), their integers
     summed (md_fixed_add) and rounded once (md_fixed_round) -- one GPU's
-    share of a depth-split product and its exact reduction.  Milliseconds
+    share of a depth-split product and its exact reduction; the blocks
+    report refused exponents into a device word, so nothing waits.  Milliseconds
     per step of each, and whether the rounded sum equals C (md_gemm_ex's
     output for the same S) in every entry."""
     form = "int8bal" if info["beta"] == 8 else ("int8" if info["beta"] == 7 else "fp64")
@@ -340,12 +341,14 @@ def depth_split(md, torch, A, B, C, info, blocks=4, steps=2):
     def whole():
         return md.gemm_fixed(A, B, S=S, beta=beta, form=form)[:2]
 
+    flags = torch.zeros(1, dtype=torch.int32, device=A.device)
+
     def split():
         E, F = md.exponents(A, B)
         acc = sc = None
         for a, b in zip(cuts[:-1], cuts[1:]):
             Xb, sc, _ = md.gemm_fixed(A[:, :, a:b], B[:, a:b, :], E, F, S=S, beta=beta, form=form,
-                                      nlimb=nlimb)
+                                      nlimb=nlimb, flags=flags)
             acc = Xb if acc is None else md.fixed_add(acc, Xb, out=acc)
         return md.fixed_round(acc, sc, m)
 
@@ -360,6 +363,7 @@ def depth_split(md, torch, A, B, C, info, blocks=4, steps=2):
         res[name] = round((time.perf_counter() - t0) * 1e3 / steps, 3)
         if name == "split_sum_round_ms":
             res["rounded_sum_equals_product"] = bool(torch.equal(out, C))
+            res["exponents_all_taken"] = int(flags.item()) == 0
         del out
         torch.cuda.empty_cache()
     return res
