@@ -16,6 +16,19 @@ m-double gradients dA = dC B^T and dB = A^T dC through the same error-free
 product (the adjoint of a matrix product).  Torch sees the planes as
 independent floats, so call ``C.backward(gradient=W)`` with W in m-double
 planes rather than a plane-wise torch loss.
+
+Exact integers before the rounding, and a product cut along its depth:
+
+    E, F = exponents(A, B)                           # the full matrices' grids
+    X1, sc, _ = gemm_fixed(A[:, :, :k], B[:, :k], E, F, S=27, beta=8, form="int8bal",
+                           nlimb=fixed_limbs(8, 27, K))
+    X2, _, _ = gemm_fixed(A[:, :, k:], B[:, k:], E, F, S=27, beta=8, form="int8bal",
+                          nlimb=fixed_limbs(8, 27, K))
+    C = fixed_round(fixed_add(X1, X2), sc, m)       # = gemm_ex(A, B, ..., force_S=27)
+
+Other entry points: ``gemm_ex`` and ``dot_ex`` (options, events, validation),
+``dot`` (batched inner products), ``gemm_ordinary`` (the classical m-double
+baseline), ``choose_params``.
 """
 from __future__ import annotations
 
