@@ -14,7 +14,10 @@ kernels (S up to 32 and beyond) and m = 1, 2, 4, 8:
   computed on its own stream) equal the oracle's per block, md_fixed_add
   sums them to the whole product's integer bit for bit, and that rounds
   to md_gemm_ex's result for the whole product;
-* an exponent below the data's own is refused (MD_EINPUT, flag 8).
+* an exponent below the data's own is refused (MD_EINPUT, flag 8), or reported in a
+  device flag word without waiting;
+* a seeded sweep of depth splits over forms, word counts, sizes, forced S
+  and one to three random cuts.
 """
 import numpy as np
 import pytest
@@ -340,3 +343,56 @@ def test_exponent_flags_without_waiting():
     md.gemm_fixed(Ad, Bd, E, F, S=S, beta=beta, form="int8bal", flags=flags)
     torch.cuda.synchronize()
     assert int(flags.item()) == 8
+
+
+def draw_split_cases(n=24, seed=4096):
+    r = np.random.Generator(np.random.PCG64(seed))
+    cases = []
+    for c in range(n):
+        form = ("fp64", "int8", "int8bal")[c % 3]
+        m = int(r.choice([1, 2, 4, 8, 16]))
+        M, N = int(r.integers(1, 71)), int(r.integers(1, 71))
+        K = int(r.integers(2, 301))
+        if form == "fp64":
+            beta = int(r.integers(12, 23))
+            S = int(r.integers(2, 15))
+        else:
+            beta = 7 if form == "int8" else 8
+            S = int(r.integers(1, 33)) if r.random() < 0.7 else int(r.choice([36, 42, 48, 52, 60, 64]))
+        ncut = int(r.integers(1, 4))
+        cuts = sorted(set(int(v) for v in r.integers(1, K, ncut)))
+        cases.append((c, form, m, M, N, K, beta, S, cuts, int(r.integers(0, 2 ** 31))))
+    return cases
+
+
+@pytest.mark.parametrize("case", draw_split_cases(), ids=lambda c: f"split{c[0]}-{c[1]}-m{c[2]}-S{c[7]}")
+def test_random_depth_split(case):
+    """Seeded sweep: slice form, word count, ragged sizes, forced S (whole
+    triangles, bands, FP64 LDS and buffer folds), one to three random depth
+    cuts.  The blocks' integers on the full exponents sum to the whole
+    product's, which equals the oracle's; rounding the sum gives
+    md_gemm_ex's output."""
+    _, form, m, M, N, K, beta, S, cuts, seed = case
+    r = np.random.Generator(np.random.PCG64(seed))
+    lead = ("uniform",) if r.random() < 0.5 else ("log2uniform", float(r.integers(1, 12)))
+    A = mdinputs.mdouble(r, m, (M, K), lead)
+    B = mdinputs.mdouble(r, m, (K, N), lead)
+    Ad, Bd = dev(A), dev(B)
+    E, F = md.exponents(Ad, Bd)
+    nlimb = md.fixed_limbs(beta, S, K)
+    flags = torch.zeros(1, dtype=torch.int32, device="cuda")
+    acc = sc = None
+    for a, b in zip([0] + cuts, cuts + [K]):
+        Xb, sc, _ = md.gemm_fixed(Ad[:, :, a:b], Bd[:, a:b, :], E, F, S=S, beta=beta, form=form, nlimb=nlimb,
+                                  flags=flags)
+        acc = Xb if acc is None else md.fixed_add(acc, Xb)
+    Xw, scw, _ = md.gemm_fixed(Ad, Bd, S=S, beta=beta, form=form)
+    Cg, _ = md.gemm_ex(Ad, Bd, form=form, force_S=S, force_beta=beta)
+    C = md.fixed_round(acc, sc, m)
+    torch.cuda.synchronize()
+    assert int(flags.item()) == 0
+    assert torch.equal(acc, Xw) and torch.equal(sc, scw)
+    assert torch.equal(C, Cg)
+    Xo, so = ox.fixed_product(A, B, beta, S, balanced=form == "int8bal")
+    np.testing.assert_array_equal(Xw.cpu().numpy(), limbs_of(Xo, nlimb))
+    np.testing.assert_array_equal(scw.cpu().numpy(), so.astype(np.int32))
