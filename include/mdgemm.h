@@ -258,7 +258,9 @@ int md_exponents(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda, 
  *   opts:  required, with force_S and force_beta set (the slices are fixed
  *          by the caller so that every block shares them); form as
  *          md_gemm_ex; dbg must be NULL; workspace, if given, serves the
- *          product's own scratch.
+ *          product's own scratch and, on the paths that capture the
+ *          diagonal sums (below), also those sums (S M N int64) and the
+ *          rounded words they produce on the way (m M N doubles).
  *   E, F:  shared exponents of the rows of A and columns of B (device, M and
  *          N int32) or NULL for the data's own.  Each given one must be at
  *          least the data's own and at most 1100; otherwise the call
