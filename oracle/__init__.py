@@ -1,7 +1,8 @@
 """Exact CPU oracle for the m-double matrix product by error-free summation.
 
 TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
-the ``cpu_baseline`` leg of ``bench.py`` may import, call, link or execute
+the CPU leg of ``bench.py`` (its ``cpu_baseline`` and the error check of
+sampled GPU outputs, after all GPU work) may import, call, link or execute
 anything under ``oracle/``.  The product path (the HIP library and its Python
 binding) never does, and shares no code with it.
 

@@ -2,8 +2,8 @@
  * Exact CPU oracle for the m-double matrix product, plain C with OpenMP.
  *
  * TEST INFRASTRUCTURE ONLY: loaded by tests/, __graft_entry__.smoke() and the
- * cpu_baseline leg of bench.py; never by the product path, and sharing no
- * code with it.
+ * CPU leg of bench.py (cpu_baseline and the sampled error check); never by
+ * the product path, and sharing no code with it.
  *
  * Two layers, both exact:
  *

@@ -1,7 +1,8 @@
 """Exact oracle for the m-double matrix product by error-free summation.
 
 TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()``
-and the ``cpu_baseline`` leg of ``bench.py``; never by the product path.
+and the CPU leg of ``bench.py`` (``cpu_baseline`` and the sampled error
+check); never by the product path.
 
 Notation (paper Section 2, generalised from the double-double inner product
 to a matrix product):
