@@ -88,8 +88,9 @@ __global__ void k_exp_init(int32_t* hi, int32_t* lo, int64_t R, int32_t* stats)
         *reinterpret_cast<unsigned long long*>(stats + 2) = ~0ull;
 }
 
-// Block: 16 rows x 256 depth, 256 threads, 16 threads per row (short
-// blocks: many waves in flight, each with its loads unrolled).  Each row's
+// Block: 16 rows x `depth` (256, more only where the grid's second
+// dimension would exceed 65535 blocks), 256 threads, 16 threads per row
+// (short blocks: many waves in flight, each with its loads unrolled).  Each row's
 // threads reduce with wavefront shuffles: in row order (the depth
 // contiguous) they are 16 adjacent lanes (xor 1, 2, 4, 8); in column order
 // (rows_fast: the rows contiguous, as for the columns of B) they are lanes
@@ -98,17 +99,17 @@ __global__ void k_exp_init(int32_t* hi, int32_t* lo, int64_t R, int32_t* stats)
 constexpr int kExpRows = 16, kExpDepth = 256;
 
 __global__ __launch_bounds__(256) void k_exp_partial(Operand op, int32_t* hi, int32_t* lo,
-                                                     int rows_fast)
+                                                     int rows_fast, int64_t depth)
 {
     const int t = threadIdx.x;
     const int tr = rows_fast ? (t & 15) : (t >> 4);
     const int tk = rows_fast ? (t >> 4) : (t & 15);
     const int64_t r = (int64_t)blockIdx.x * kExpRows + tr;
-    const int64_t k0 = (int64_t)blockIdx.y * kExpDepth;
+    const int64_t k0 = (int64_t)blockIdx.y * depth;
     int h = INT_MIN, l = INT_MAX;
     if (r < op.R) {
         const double* p = op.p + r * op.sr;
-        const int64_t kend = min(k0 + (int64_t)kExpDepth, op.K);
+        const int64_t kend = min(k0 + depth, op.K);
 #pragma unroll 4
         for (int64_t k = k0 + tk; k < kend; k += 16) {
             const double x = p[k * op.sk];
@@ -519,9 +520,14 @@ hipError_t launch_exp_init(int32_t* hi, int32_t* lo, int64_t R, int32_t* stats, 
 hipError_t launch_exp_partial(const Operand& op, int32_t* hi, int32_t* lo, hipStream_t st)
 {
     const int rows_fast = (op.sr == 1 && op.sk != 1) ? 1 : 0;
-    dim3 grid((unsigned)((op.R + kExpRows - 1) / kExpRows),
-              (unsigned)((op.K + kExpDepth - 1) / kExpDepth));
-    hipLaunchKernelGGL(k_exp_partial, grid, dim3(256), 0, st, op, hi, lo, rows_fast);
+    int64_t depth = kExpDepth;
+    while ((op.K + depth - 1) / depth > 65535)
+        depth *= 2;
+    const int64_t gx = (op.R + kExpRows - 1) / kExpRows;
+    if (gx > 0x7fffffff)
+        return hipErrorInvalidValue;
+    dim3 grid((unsigned)gx, (unsigned)((op.K + depth - 1) / depth));
+    hipLaunchKernelGGL(k_exp_partial, grid, dim3(256), 0, st, op, hi, lo, rows_fast, depth);
     return hipGetLastError();
 }
 

@@ -396,3 +396,19 @@ def test_random_depth_split(case):
     Xo, so = ox.fixed_product(A, B, beta, S, balanced=form == "int8bal")
     np.testing.assert_array_equal(Xw.cpu().numpy(), limbs_of(Xo, nlimb))
     np.testing.assert_array_equal(scw.cpu().numpy(), so.astype(np.int32))
+
+
+def test_exponents_of_a_very_deep_product():
+    """Depth 20,000,000 (beyond 65535 blocks of 256 in the exponent pass's
+    second grid dimension, so its blocks deepen): the shared exponents of
+    both operands equal the oracle's."""
+    r = np.random.Generator(np.random.PCG64(77))
+    K = 20_000_000
+    A = np.ldexp(r.uniform(-1, 1, (1, 2, K)), r.integers(-30, 30, (1, 2, K)))
+    B = np.ldexp(r.uniform(-1, 1, (1, K, 3)), r.integers(-30, 30, (1, K, 3)))
+    A[0, 1, K - 1] = 2.0 ** 40           # the maximum sits in the last block
+    B[0, 0, 2] = 2.0 ** 41
+    E, F = md.exponents(dev(A), dev(B))
+    torch.cuda.synchronize()
+    assert list(E.cpu().numpy()) == ox.row_exponents(A[0])[0]
+    assert list(F.cpu().numpy()) == ox.row_exponents(B[0].T)[0]
