@@ -17,11 +17,11 @@ constexpr int kMagDepth = 4;
 __global__ __launch_bounds__(256) void k_mag_min_short(const v4i* __restrict__ qA,
                                                        const v4i* __restrict__ qB, int64_t M,
                                                        int64_t N, int64_t nkc,
-                                                       unsigned long long* minP)
+                                                       unsigned long long* minP, int64_t y0)
 {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t rb0 = ((int64_t)blockIdx.y * 2 + (wave >> 1)) * 4;
+    const int64_t rb0 = ((y0 + blockIdx.y) * 2 + (wave >> 1)) * 4;
     const int64_t cb0 = ((int64_t)blockIdx.x * 2 + (wave & 1)) * 4;
     const int64_t nrb = 2 * ((M + kTile - 1) / kTile), ncb = 2 * ((N + kTile - 1) / kTile);
     const uint64_t bytes = (uint64_t)nkc * 1024;
@@ -87,10 +87,10 @@ __global__ __launch_bounds__(256) void k_mag_min_short(const v4i* __restrict__ q
 // int64 every 2^11 depth fragments.
 __global__ __launch_bounds__(256) void k_mag_min(const v4i* __restrict__ qA,
                                                  const v4i* __restrict__ qB, int64_t M, int64_t N,
-                                                 int64_t nkc, unsigned long long* minP)
+                                                 int64_t nkc, unsigned long long* minP, int64_t y0)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t rb0 = ((int64_t)blockIdx.y * 2 + (wave >> 1)) * 4;
+    const int64_t rb0 = ((y0 + blockIdx.y) * 2 + (wave >> 1)) * 4;
     const int64_t cb0 = ((int64_t)blockIdx.x * 2 + (wave & 1)) * 4;
     const int64_t nrb = (M + 15) / 16, ncb = (N + 15) / 16;
     v4i acc[4][4];
@@ -157,17 +157,17 @@ __global__ __launch_bounds__(256) void k_mag_min(const v4i* __restrict__ qA,
 // at its diagonal entry (i, i); the other 15/16 of the entries are
 // discarded, which costs matrix-core time the inner products do not miss.
 
-// Diagonal sums t0 .. t0+G-1 of the 16 pairs of row block blockIdx.y over the
+// Diagonal sums t0 .. t0+G-1 of the 16 pairs of row block y0 + blockIdx.y over the
 // depth fragments [c0, c0 + range), range within one exactness chunk.  The
 // partial sums are added into D with 64-bit integer atomics: integer
 // addition is associative, so D does not depend on their order.
 template <class Form, int G>
-__global__ __launch_bounds__(64) void k_dot_band(DotArgs a)
+__global__ __launch_bounds__(64) void k_dot_band(DotArgs a, int64_t y0)
 {
     typedef typename Form::frag Frag;
     typedef typename Form::acc Acc;
     const int lane = threadIdx.x;
-    const int64_t rb = blockIdx.y;
+    const int64_t rb = y0 + blockIdx.y;
     const int64_t c0 = (int64_t)blockIdx.x * a.range, c1 = min(c0 + a.range, a.nkc);
     const int t0 = (int)blockIdx.z * G;
     const int64_t fstride = (int64_t)a.S * 64;
@@ -276,10 +276,18 @@ struct DispatchDot {
     static hipError_t run(const DotArgs& a, hipStream_t st)
     {
         if (a.band == G) {
-            dim3 grid((unsigned)((a.nkc + a.range - 1) / a.range), (unsigned)((a.batch + 15) / 16),
-                      (unsigned)a.nbands);
-            hipLaunchKernelGGL((k_dot_band<Form, G>), grid, dim3(64), 0, st, a);
-            return hipGetLastError();
+            // pair blocks on the grid's second dimension, at most 65535 per launch
+            const int64_t nyb = (a.batch + 15) / 16, gx = (a.nkc + a.range - 1) / a.range;
+            if (gx > 0x7fffffff)
+                return hipErrorInvalidValue;
+            for (int64_t y0 = 0; y0 < nyb; y0 += 65535) {
+                dim3 grid((unsigned)gx, (unsigned)std::min<int64_t>(nyb - y0, 65535), (unsigned)a.nbands);
+                hipLaunchKernelGGL((k_dot_band<Form, G>), grid, dim3(64), 0, st, a, y0);
+                const hipError_t e = hipGetLastError();
+                if (e != hipSuccess)
+                    return e;
+            }
+            return hipSuccess;
         }
         return DispatchDot<Form, G - 1>::run(a, st);
     }
@@ -294,14 +302,22 @@ struct DispatchDot<Form, 0> {
 hipError_t launch_mag_min(const void* qA, const void* qB, int64_t M, int64_t N, int64_t nkc,
                           unsigned long long* minP, hipStream_t st)
 {
-    dim3 grid((unsigned)((N + 127) / 128), (unsigned)((M + 127) / 128));
-    if (nkc <= 2048)
-        hipLaunchKernelGGL(k_mag_min_short, grid, dim3(256), 0, st, (const v4i*)qA, (const v4i*)qB,
-                           M, N, nkc, minP);
-    else
-        hipLaunchKernelGGL(k_mag_min, grid, dim3(256), 0, st, (const v4i*)qA, (const v4i*)qB, M, N,
-                           nkc, minP);
-    return hipGetLastError();
+    const int64_t gx = (N + 127) / 128, ny = (M + 127) / 128;
+    if (gx > 0x7fffffff)
+        return hipErrorInvalidValue;
+    for (int64_t y0 = 0; y0 < ny; y0 += 65535) {
+        dim3 grid((unsigned)gx, (unsigned)std::min<int64_t>(ny - y0, 65535));
+        if (nkc <= 2048)
+            hipLaunchKernelGGL(k_mag_min_short, grid, dim3(256), 0, st, (const v4i*)qA, (const v4i*)qB,
+                               M, N, nkc, minP, y0);
+        else
+            hipLaunchKernelGGL(k_mag_min, grid, dim3(256), 0, st, (const v4i*)qA, (const v4i*)qB, M, N,
+                               nkc, minP, y0);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_dot_diag(const DotArgs& a, int form_int8, hipStream_t st)

@@ -97,6 +97,7 @@ __global__ void k_exp_init(int32_t* hi, int32_t* lo, int64_t R, int32_t* stats)
 // 16 apart in each of the four waves (xor 16, 32), and every wave adds its
 // partial row result by atomics.
 constexpr int kExpRows = 16, kExpDepth = 256;
+constexpr int64_t kMaxGridY = 65535;   // blocks on a launch's second grid dimension
 
 __global__ __launch_bounds__(256) void k_exp_partial(Operand op, int32_t* hi, int32_t* lo,
                                                      int rows_fast, int64_t depth)
@@ -242,11 +243,11 @@ template <> struct Bytes<1> { typedef uint8_t type; };
 // in registers.
 template <int MW, int EPT, bool DBG>
 __global__ __launch_bounds__(256) void k_split_i8(Operand op, const int32_t* E, int S,
-                                                  int64_t nkc, int8_t* out, int32_t* dbg)
+                                                  int64_t nkc, int8_t* out, int32_t* dbg, int64_t rb0)
 {
     constexpr int beta = 7, D = 9, W = 63, parts = 4 / EPT;
     typedef typename Bytes<EPT>::type Store;
-    const int64_t rb = blockIdx.y, kc = blockIdx.x / parts;
+    const int64_t rb = rb0 + blockIdx.y, kc = blockIdx.x / parts;
     const int byte0 = EPT * ((int)threadIdx.x + 256 * (int)(blockIdx.x % parts));
     const int L = byte0 >> 4;                 // fragment lane
     const int64_t r = rb * kRowBlock + (L & 15);
@@ -311,12 +312,12 @@ __global__ __launch_bounds__(256) void k_split_i8(Operand op, const int32_t* E, 
 // {-1, 0, 1}) is carried up.
 template <int MW, int EPT, bool DBG>
 __global__ __launch_bounds__(256) void k_split_i8bal(Operand op, const int32_t* E, int S,
-                                                     int64_t nkc, int8_t* out, int32_t* dbg)
+                                                     int64_t nkc, int8_t* out, int32_t* dbg, int64_t rb0)
 {
     constexpr int D = 7, W = 56, parts = 4 / EPT;
     constexpr int64_t kBias = 0x80808080808080LL;
     typedef typename Bytes<EPT>::type Store;
-    const int64_t rb = blockIdx.y, kc = blockIdx.x / parts;
+    const int64_t rb = rb0 + blockIdx.y, kc = blockIdx.x / parts;
     const int byte0 = EPT * ((int)threadIdx.x + 256 * (int)(blockIdx.x % parts));
     const int L = byte0 >> 4;                 // fragment lane
     const int64_t r = rb * kRowBlock + (L & 15);
@@ -383,10 +384,10 @@ __global__ __launch_bounds__(256) void k_split_i8bal(Operand op, const int32_t* 
 // Nonoverlapping words give |a| >= |a^(0)| (1 - 2^-52) >= q 2^(E_r - 7) (1 - 2^-52).
 // E holds E_r + eoff.
 __global__ __launch_bounds__(256) void k_split_mag(Operand op, const int32_t* E, int eoff,
-                                                   int64_t nkc, int8_t* out)
+                                                   int64_t nkc, int8_t* out, int64_t rb0)
 {
     const int T = threadIdx.x;
-    const int64_t rb = blockIdx.y, kc = blockIdx.x;
+    const int64_t rb = rb0 + blockIdx.y, kc = blockIdx.x;
     const int L = T >> 2;
     const int64_t r = rb * kRowBlock + (L & 15);
     const int64_t kbase = kc * kKcI8 + 16 * (L >> 4) + 4 * (T & 3);
@@ -521,7 +522,7 @@ hipError_t launch_exp_partial(const Operand& op, int32_t* hi, int32_t* lo, hipSt
 {
     const int rows_fast = (op.sr == 1 && op.sk != 1) ? 1 : 0;
     int64_t depth = kExpDepth;
-    while ((op.K + depth - 1) / depth > 65535)
+    while ((op.K + depth - 1) / depth > kMaxGridY)
         depth *= 2;
     const int64_t gx = (op.R + kExpRows - 1) / kExpRows;
     if (gx > 0x7fffffff)
@@ -574,18 +575,26 @@ hipError_t split_i8_m(const Operand& op, const int32_t* E, int S, int64_t nrb, i
                       int8_t* out, int32_t* dbg, bool balanced, hipStream_t st)
 {
     constexpr int EPT = split_ept(MW);
-    const dim3 grid((unsigned)(nkc * (4 / EPT)), (unsigned)nrb);
-    if (balanced) {
-        if (dbg)
-            hipLaunchKernelGGL((k_split_i8bal<MW, EPT, true>), grid, dim3(256), 0, st, op, E, S, nkc, out, dbg);
-        else
-            hipLaunchKernelGGL((k_split_i8bal<MW, EPT, false>), grid, dim3(256), 0, st, op, E, S, nkc, out, dbg);
-    } else if (dbg) {
-        hipLaunchKernelGGL((k_split_i8<MW, EPT, true>), grid, dim3(256), 0, st, op, E, S, nkc, out, dbg);
-    } else {
-        hipLaunchKernelGGL((k_split_i8<MW, EPT, false>), grid, dim3(256), 0, st, op, E, S, nkc, out, dbg);
+    if (nkc * (4 / EPT) > 0x7fffffff)
+        return hipErrorInvalidValue;
+    // row blocks on the grid's second dimension, at most kMaxGridY per launch
+    for (int64_t y0 = 0; y0 < nrb; y0 += kMaxGridY) {
+        const dim3 grid((unsigned)(nkc * (4 / EPT)), (unsigned)std::min<int64_t>(nrb - y0, kMaxGridY));
+        if (balanced) {
+            if (dbg)
+                hipLaunchKernelGGL((k_split_i8bal<MW, EPT, true>), grid, dim3(256), 0, st, op, E, S, nkc, out, dbg, y0);
+            else
+                hipLaunchKernelGGL((k_split_i8bal<MW, EPT, false>), grid, dim3(256), 0, st, op, E, S, nkc, out, dbg, y0);
+        } else if (dbg) {
+            hipLaunchKernelGGL((k_split_i8<MW, EPT, true>), grid, dim3(256), 0, st, op, E, S, nkc, out, dbg, y0);
+        } else {
+            hipLaunchKernelGGL((k_split_i8<MW, EPT, false>), grid, dim3(256), 0, st, op, E, S, nkc, out, dbg, y0);
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
     }
-    return hipGetLastError();
+    return hipSuccess;
 }
 
 hipError_t launch_split_i8(const Operand& op, int m, const int32_t* E, int S, int64_t nrb,
@@ -626,9 +635,16 @@ hipError_t launch_validate(const Operand& op, int m, int32_t* flags, hipStream_t
 hipError_t launch_split_mag(const Operand& op, const int32_t* E, int eoff, int64_t nrb, int64_t nkc,
                             int8_t* out, hipStream_t st)
 {
-    dim3 grid((unsigned)nkc, (unsigned)nrb);
-    hipLaunchKernelGGL(k_split_mag, grid, dim3(256), 0, st, op, E, eoff, nkc, out);
-    return hipGetLastError();
+    if (nkc > 0x7fffffff)
+        return hipErrorInvalidValue;
+    for (int64_t y0 = 0; y0 < nrb; y0 += kMaxGridY) {
+        dim3 grid((unsigned)nkc, (unsigned)std::min<int64_t>(nrb - y0, kMaxGridY));
+        hipLaunchKernelGGL(k_split_mag, grid, dim3(256), 0, st, op, E, eoff, nkc, out, y0);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
 }
 
 template <int MW>
