@@ -307,6 +307,11 @@ int md_choose_params(int form, int64_t K, int T, int G, int *beta, int *S, int *
 /* Scratch bytes a call with these sizes and parameters needs. */
 size_t md_workspace_size(int form, int64_t M, int64_t N, int64_t K, int S);
 
+/* Scratch bytes an md_dot_ex call with batch pairs of length n and slice
+ * count S needs (with a forced S and this workspace the call, like
+ * md_gemm_ex, only launches kernels and can be captured into a HIP graph). */
+size_t md_dot_workspace_size(int form, int64_t batch, int64_t n, int S);
+
 /* Text of a return code (static storage). */
 const char *md_strerror(int code);
 

@@ -112,6 +112,8 @@ def lib():
     L.md_choose_params.restype = i32
     L.md_workspace_size.argtypes = [i32, i64, i64, i64, i32]
     L.md_workspace_size.restype = ctypes.c_size_t
+    L.md_dot_workspace_size.argtypes = [i32, i64, i64, i32]
+    L.md_dot_workspace_size.restype = ctypes.c_size_t
     L.md_fixed_limbs.argtypes = [i32, i32, i64]
     L.md_fixed_limbs.restype = i32
     L.md_exponents.argtypes = [i64, i64, i64, p, i64, p, i64, p, p, p]
@@ -256,13 +258,14 @@ def gemm(A: torch.Tensor, B: torch.Tensor, form: str = "fp64", stream=None) -> t
 
 def dot_ex(X: torch.Tensor, Y: torch.Tensor, out: torch.Tensor | None = None, *, form="fp64",
            rule="rho", target_bits=0, force_S=0, force_beta=0, events=None, stream=None,
-           validate=False):
+           validate=False, workspace: torch.Tensor | None = None):
     """Batched m-double inner products out_b = sum_k X[:, b, k] Y[:, b, k].
 
     X and Y are (m, batch, n) float64 planes on the HIP device (m = 1, 2, 4,
     8 or 16); out is (m, batch).  Returns (out, info dict); ``events`` and
     ``validate`` as in ``gemm_ex`` (events recorded around the contraction
-    and the fold).
+    and the fold).  ``workspace``: a device byte buffer of at least
+    ``md_dot_workspace_size`` bytes (the library then allocates nothing).
     """
     _check_planes(X, "X")
     _check_planes(Y, "Y")
@@ -284,6 +287,9 @@ def dot_ex(X: torch.Tensor, Y: torch.Tensor, out: torch.Tensor | None = None, *,
     opts.force_beta = force_beta
     opts.validate = 1 if validate else 0
     opts.info = ctypes.pointer(info)
+    if workspace is not None:
+        opts.workspace = ctypes.c_void_p(workspace.data_ptr())
+        opts.workspace_bytes = workspace.numel() * workspace.element_size()
     if events is not None:
         opts.ev_gemm_begin = ctypes.c_void_p(events[0])
         opts.ev_gemm_end = ctypes.c_void_p(events[1])

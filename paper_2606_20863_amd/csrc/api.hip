@@ -367,6 +367,14 @@ int md_choose_params(int form, int64_t K, int T, int G, int* beta, int* S, int* 
     return rc;
 }
 
+size_t md_dot_workspace_size(int form, int64_t batch, int64_t n, int S)
+{
+    // exponents and statistics, the two magnitude slices (slice rule), the
+    // two digit planes and the S x batch diagonal sums
+    return small_bytes(batch, batch) + 2 * digits_bytes(MD_FORM_INT8, batch, n, 1) +
+           2 * digits_bytes(form, batch, n, S) + (size_t)S * batch * sizeof(int64_t) + 4096;
+}
+
 size_t md_workspace_size(int form, int64_t M, int64_t N, int64_t K, int S)
 {
     size_t bytes = small_bytes(M, N) + digits_bytes(MD_FORM_INT8, M, K, 1) +

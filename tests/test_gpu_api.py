@@ -84,3 +84,25 @@ def test_streams_and_concurrency():
     for c1, c2 in outs:
         np.testing.assert_array_equal(c1.cpu().numpy(), r1)
         np.testing.assert_array_equal(c2.cpu().numpy(), r2)
+
+
+@pytest.mark.parametrize("form", ["int8bal", "fp64"])
+def test_dot_caller_workspace(form):
+    """md_dot_ex with a workspace of md_dot_workspace_size bytes (the slice
+    rule's magnitude slices included) gives the same words; a workspace too
+    small is MD_ENOMEM and leaves the output as it was."""
+    r = np.random.Generator(np.random.PCG64(12))
+    X = dev(mdinputs.mdouble(r, 4, (70, 900)))
+    Y = dev(mdinputs.mdouble(r, 4, (70, 900)))
+    ref, info = md.dot_ex(X, Y, form=form)
+    nbytes = md.lib().md_dot_workspace_size(md._FORMS[form], 70, 900, info["S"])
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    out, info2 = md.dot_ex(X, Y, form=form, workspace=ws)
+    np.testing.assert_array_equal(host(out), host(ref))
+    assert info2["S"] == info["S"]
+    keep = torch.full_like(ref, 3.0)
+    with pytest.raises(md.MDError) as e:
+        md.dot_ex(X, Y, keep, form=form, workspace=torch.empty(2048, dtype=torch.uint8, device="cuda"))
+    assert e.value.code == 5
+    torch.cuda.synchronize()
+    assert bool((keep == 3.0).all())

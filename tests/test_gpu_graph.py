@@ -8,7 +8,8 @@ same inputs word for word, and the first one the oracle's method.  Cases:
 the launch-bound double-double 64^3 product in the three forms, ragged
 quad-double sizes (whole-triangle INT8 kernels, FP64 LDS fold), octo-double
 balanced INT8 (banded kernels and their sum buffer), hexa-double FP64 (the
-buffer fold), and a forward + adjoint step (three products in one graph).
+buffer fold), a forward + adjoint step (three products in one graph), and
+batched inner products (md_dot_ex with md_dot_workspace_size bytes).
 """
 import numpy as np
 import pytest
@@ -113,3 +114,36 @@ def test_graph_of_forward_and_adjoint(form):
             ref, _ = md.gemm_ex(a, b, **kw)
             torch.cuda.synchronize()
             np.testing.assert_array_equal(C.cpu().numpy(), ref.cpu().numpy())
+
+
+@pytest.mark.parametrize("form", ["int8bal", "int8", "fp64"])
+def test_graph_of_inner_products(form):
+    """Batched inner products with a forced S and a workspace of
+    md_dot_workspace_size bytes, captured and replayed with new inputs: every
+    replay equals an eager call (and the first the oracle's method)."""
+    m, batch, n = 4, 90, 700
+    r = np.random.Generator(np.random.PCG64(404))
+    X = dev(mdinputs.mdouble(r, m, (batch, n)))
+    Y = dev(mdinputs.mdouble(r, m, (batch, n)))
+    _, info = md.dot_ex(X, Y, form=form)
+    kw = dict(form=form, force_S=info["S"], force_beta=info["beta"])
+    ws = torch.empty(md.lib().md_dot_workspace_size(md._FORMS[form], batch, n, info["S"]), dtype=torch.uint8,
+                     device="cuda")
+    out = torch.empty((m, batch), dtype=torch.float64, device="cuda")
+    g = warm_and_capture(lambda: md.dot_ex(X, Y, out, workspace=ws, **kw))
+    for rep in range(3):
+        Xh = mdinputs.mdouble(r, m, (batch, n))
+        Yh = mdinputs.mdouble(r, m, (batch, n))
+        X.copy_(torch.from_numpy(Xh))
+        Y.copy_(torch.from_numpy(Yh))
+        out.fill_(np.nan)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        ref, _ = md.dot_ex(X, Y, **kw)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(got, ref.cpu().numpy())
+        if rep == 0:
+            _, want = ox.method_dot(Xh, Yh, info["beta"], info["S"], balanced=form == "int8bal")
+            np.testing.assert_array_equal(got, want)
