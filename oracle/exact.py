@@ -526,70 +526,65 @@ def rho_G(A: np.ndarray, B: np.ndarray):
     return minP, g
 
 
-INT8_KGRAN = 64     # depth granule of the INT8 slice contraction
-FP64_KGRAN = 16     # depth granule of the FP64 slice contraction
-INT8_GMAX = 16      # widest band of diagonals the INT8 contraction handles
-FP64_GMAX = 16      # same, FP64
-INT8_SINGLE = 32    # INT8: up to this many diagonals form one band
+# Exactness ranges of the accumulators (Section 2: the partial sums of the
+# slice products must stay below a threshold for the summation to be exact).
+INT32_LIMIT = 1 << 31   # INT8 slices, INT32 accumulation
+FP64_LIMIT = 1 << 53    # FP64 slices: every integer below 2^53 is a double
+FP64_BETAS = range(8, 25)   # FP64 digit widths considered
 
 
-def band_round(S: int, gmax: int, single: int = 0):
-    """Round S up so that it splits into nb equal bands of at most gmax
-    diagonals: nb = ceil(S / gmax), band = ceil(S / nb); S <= single stays
-    one band.  Returns (S, band)."""
-    if S <= single:
-        return S, S
-    nb = -(-S // gmax)
-    band = -(-S // nb)
-    return nb * band, band
+def digit_max(form: str, beta: int) -> int:
+    """Largest digit magnitude: 2^beta - 1 for sign-magnitude digits, 128 for
+    the balanced 8-bit digits."""
+    return BAL_DMAX if form == "int8bal" else (1 << beta) - 1
 
 
-def chunk_depth(S: int, beta: int, K: int, limit: int, gran: int, dmax: int = 0) -> int:
-    """Largest multiple of ``gran`` with S * Kc * dmax^2 < limit, dmax the
-    largest digit magnitude (2^beta - 1 unless given), capped at K rounded
-    up to ``gran`` (0 if even one granule overflows)."""
-    dmax = dmax or (1 << beta) - 1
-    per = S * dmax * dmax
-    kc = ((limit - 1) // per) // gran * gran
-    kfull = -(-max(K, 1) // gran) * gran
-    return min(kc, kfull)
-
-
-def choose_params(form: str, K: int, T: int, G: int):
-    """(beta, S, Kc, band) for a slice form.
-
-    S is the budget's slice count rounded up to equal bands (``band_round``).
-    int8: beta = 7 (digits in [-127, 127]); every diagonal sum of a depth
-    chunk Kc stays below 2^31 (INT32 accumulation exact).
-    int8bal: balanced 8-bit digits (``slice_count_balanced``), same chunks
-    with digits up to 128 in magnitude.
-    fp64: beta in [8, 24]; every diagonal sum of a chunk stays below 2^53
-    (FP64 accumulation exact).  The smallest S wins, ties go to the larger
-    chunk Kc.
-    """
+def min_slices(form: str, T: int, G: int, beta: int = 0) -> int:
+    """The budget's smallest slice count for target 2^-T and ratio exponent
+    G: ``slice_count`` with beta = 7 (int8) or the given beta (fp64), or
+    ``slice_count_balanced`` (int8bal)."""
     if form == "int8":
-        S, band = band_round(slice_count(7, T, G), INT8_GMAX, INT8_SINGLE)
-        kc = chunk_depth(S, 7, K, 1 << 31, INT8_KGRAN)
-        if kc <= 0:
-            raise ValueError("no exact INT8 chunking")
-        return 7, S, kc, band
+        return slice_count(7, T, G)
     if form == "int8bal":
-        S, band = band_round(slice_count_balanced(T, G), INT8_GMAX, INT8_SINGLE)
-        kc = chunk_depth(S, BAL_BETA, K, 1 << 31, INT8_KGRAN, BAL_DMAX)
-        if kc <= 0:
-            raise ValueError("no exact INT8 chunking")
-        return BAL_BETA, S, kc, band
+        return slice_count_balanced(T, G)
+    if form == "fp64":
+        if not 1 <= beta <= 53:
+            raise ValueError("fp64 needs a digit width")
+        return slice_count(beta, T, G)
+    raise ValueError(form)
+
+
+def exact_depth(form: str, beta: int, S: int) -> int:
+    """Largest depth Kc over which every diagonal sum stays exact: a
+    diagonal of S slices holds at most S digit pairs per depth step, each
+    product at most dmax^2 in magnitude, so |partial sum| <= S Kc dmax^2,
+    which must stay below 2^31 (INT32) or 2^53 (FP64)."""
+    limit = FP64_LIMIT if form == "fp64" else INT32_LIMIT
+    d = digit_max(form, beta)
+    return (limit - 1) // (S * d * d)
+
+
+def budget_params(form: str, K: int, T: int, G: int):
+    """(beta, S, Kc) from the error budget and the exactness range alone:
+    S the smallest slice count meeting 2^-T, Kc the largest exact depth
+    capped at K.  int8: beta = 7; int8bal: beta = 8; fp64: the beta in
+    [8, 24] with the fewest slices, ties to the larger exact depth."""
+    if form in ("int8", "int8bal"):
+        beta = 7 if form == "int8" else BAL_BETA
+        S = min_slices(form, T, G)
+        return beta, S, min(exact_depth(form, beta, S), max(K, 1))
     if form == "fp64":
         best = None
-        for beta in range(8, 25):
-            S, band = band_round(slice_count(beta, T, G), FP64_GMAX)
-            kc = chunk_depth(S, beta, K, 1 << 53, FP64_KGRAN)
-            if kc <= 0:
+        for beta in FP64_BETAS:
+            S = min_slices(form, T, G, beta)
+            kc = min(exact_depth(form, beta, S), max(K, 1))
+            if kc < 1:
                 continue
-            key = (S, -kc)
-            if best is None or key < best[0]:
-                best = (key, (beta, S, kc, band))
-        return best[1]
+            if best is None or (S, -kc) < (best[1], -best[2]):
+                best = (beta, S, kc)
+        if best is None:
+            raise ValueError("no exact FP64 parameters")
+        return best
     raise ValueError(form)
 
 
@@ -724,12 +719,10 @@ def rho_G_dot(X: np.ndarray, Y: np.ndarray):
     return minP, g
 
 
-def choose_dot_params(X: np.ndarray, Y: np.ndarray, form: str, rule: str = "rho", T: int = 0):
-    """(beta, S, Kc, band) for a batch of inner products: the matrix
-    product's rule with G from the spans of all vectors (and, for the rho
-    rule, the smallest pair's magnitude certificate), depth n."""
-    m, _, n = X.shape
-    T = T or TARGET_BITS[m]
+def dot_G(X: np.ndarray, Y: np.ndarray, rule: str = "rho") -> int:
+    """The ratio exponent G of a batch of inner products: the span bound
+    over all vectors and, for the rho rule, the smallest pair's magnitude
+    certificate when it is smaller."""
     _, sx = row_exponents(X[0])
     _, sy = row_exponents(Y[0])
     G = span_G(max(sx), max(sy))
@@ -737,7 +730,7 @@ def choose_dot_params(X: np.ndarray, Y: np.ndarray, form: str, rule: str = "rho"
         _, g = rho_G_dot(X, Y)
         if g is not None:
             G = min(G, g)
-    return choose_params(form, n, T, G)
+    return G
 
 
 def method_dot(X: np.ndarray, Y: np.ndarray, beta: int, S: int, balanced: bool = False):

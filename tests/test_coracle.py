@@ -52,3 +52,30 @@ def test_exponents_match_python():
     F, spanF = coracle.exponents(B[0], by_columns=True)
     Fr, sfr = ox.row_exponents(B[0].T)
     assert list(F) == Fr and list(spanF) == sfr
+
+
+@pytest.mark.parametrize("name,S", [("dd64", 5), ("dd64", 14), ("qd1024", 27), ("qd1024", 33),
+                                    ("od1024", 52), ("od1024", 70)])
+def test_method_entries_balanced_match_python(name, S):
+    """The C oracle's balanced 8-bit digits (recoding of the truncated
+    integer, grids at 2^(E+2)) against the Python oracle's, on ragged
+    shapes, with leading words just below 2^E (the largest digit the
+    headroom admits) and an all-zero row and column."""
+    A, B = mdinputs.workload(name, M=7, N=6, K=45)
+    A[:, 2, :] = 0.0
+    B[:, :, 4] = 0.0
+    E, _ = ox.row_exponents(A[0])
+    F, _ = ox.row_exponents(B[0].T)
+    for i, k in ((0, 3), (5, 44), (6, 0)):
+        A[:, i, k] = 0.0
+        A[0, i, k] = np.nextafter(2.0 ** E[i], 0.0) * (-1) ** k
+    for k, j in ((7, 1), (44, 5)):
+        B[:, k, j] = 0.0
+        B[0, k, j] = -np.nextafter(2.0 ** F[j], 0.0)
+    rows, cols = [0, 2, 5, 6], [1, 3, 4, 5]
+    E, F, D, C = coracle.method_entries(A, B, 8, S, rows, cols, balanced=True)
+    ref = ox.method_product(A, B, 8, S, rows=rows, cols=cols, balanced=True)
+    assert list(E) == ref["E"] and list(F) == ref["F"]
+    assert np.abs(ref["dA"]).max() == 128 or S == 5       # the digit range is reached
+    np.testing.assert_array_equal(np.transpose(D, (2, 0, 1)), ref["D"])
+    np.testing.assert_array_equal(C, ref["C"])

@@ -25,6 +25,8 @@ import paper_2606_20863_amd as md
 from oracle import coracle
 from oracle import exact as ox
 
+import rulecheck
+
 pytestmark = pytest.mark.gpu
 
 
@@ -37,16 +39,16 @@ def host(t):
     return t.detach().cpu().numpy()
 
 
-def rule_params(X, Y, form, T):
-    """(beta, S) the library's rule picks for X Y (oracle's own rule)."""
+def rule_G(X, Y):
+    """The ratio exponent G the rule certifies for X Y (the oracle's span
+    and magnitude certificates)."""
     _, sx = ox.row_exponents(X[0])
     _, sy = ox.row_exponents(Y[0].T)
     G = ox.span_G(max(sx), max(sy))
     _, g_rho = ox.rho_G(X, Y)
     if g_rho is not None:
         G = min(G, g_rho)
-    beta, S, _, _ = ox.choose_params(form, X.shape[2], T, G)
-    return beta, S
+    return G
 
 
 def tr(X):
@@ -66,10 +68,13 @@ def test_adjoint_small_bitexact(form, name):
     C.backward(dev(W))
     dA, dB = host(tA.grad), host(tB.grad)
     bal = form == "int8bal"
-    beta, S = rule_params(W, tr(B), form, T)
-    np.testing.assert_array_equal(dA, ox.method_product(W, tr(B), beta, S, balanced=bal)["C"])
-    beta, S = rule_params(tr(A), W, form, T)
-    np.testing.assert_array_equal(dB, ox.method_product(tr(A), W, beta, S, balanced=bal)["C"])
+    # the library's parameters for each backward product (its host rule on
+    # the oracle's certified G), checked against the budget
+    for X, Y, got in ((W, tr(B), dA), (tr(A), W, dB)):
+        G = rule_G(X, Y)
+        beta, S, kc, band = md.choose_params(form, X.shape[2], T, G)
+        rulecheck.check_params(form, X.shape[2], T, G, beta, S, kc, band)
+        np.testing.assert_array_equal(got, ox.method_product(X, Y, beta, S, balanced=bal)["C"])
     # and within 2^-T of the exact gradients
     (ga, La), (gb, Lb) = ox.exact_gradients(A, B, W)
     ab, _ = ox.abs_product(W, tr(B))

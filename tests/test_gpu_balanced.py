@@ -24,6 +24,8 @@ import paper_2606_20863_amd as md
 from oracle import coracle
 from oracle import exact as ox
 
+import rulecheck
+
 pytestmark = pytest.mark.gpu
 
 
@@ -143,7 +145,7 @@ def test_triangle_every_S_several_chunks(S):
     """The one-row-block triangle kernels: the depth exceeds one exactness
     chunk (S K 128^2 >= 2^31), so the 32-bit fold columns carry between
     chunks."""
-    kc = ox.chunk_depth(S, 8, 1 << 30, 1 << 31, ox.INT8_KGRAN, ox.BAL_DMAX)
+    kc = rulecheck.library_chunk("int8bal", 8, S)
     K = kc + 81
     A, B = mdinputs.workload("dd64", M=17, N=19, K=K)
     C, info = md.gemm_ex(dev(A), dev(B), form="int8bal", force_S=S, force_beta=8)
@@ -168,9 +170,9 @@ def test_rule_and_bound_small(name, rule):
         if G_rho is not None:
             G = min(G, G_rho)
     assert info["G"] == G
-    beta, S, kc, band = ox.choose_params("int8bal", 72, T, G)
-    assert (info["beta"], info["S"], info["kc"], info["band"]) == (beta, S, kc, band)
-    assert S < ox.choose_params("int8", 72, T, G)[1]
+    rulecheck.check_info(info, "int8bal", 72, T, G)
+    beta, S = info["beta"], info["S"]
+    assert S < ox.min_slices("int8", T, G)
     np.testing.assert_array_equal(C, ox.method_product(A, B, beta, S, balanced=True)["C"])
     num, L = ox.exact_product(A, B)
     anum, _ = ox.abs_product(A, B)
@@ -224,8 +226,8 @@ def test_dot_rule_bitexact(m):
     X[:, 5, :] = 0.0
     out, info = md.dot_ex(dev(X), dev(Y), form="int8bal")
     out = host(out)
-    beta, S, kc, band = ox.choose_dot_params(X, Y, "int8bal")
-    assert (info["beta"], info["S"], info["kc"], info["band"]) == (beta, S, kc, band)
+    rulecheck.check_info(info, "int8bal", 130, ox.TARGET_BITS[m], ox.dot_G(X, Y))
+    beta, S = info["beta"], info["S"]
     _, ref = ox.method_dot(X, Y, beta, S, balanced=True)
     np.testing.assert_array_equal(out, ref)
     assert np.all(out[:, 5] == 0.0)

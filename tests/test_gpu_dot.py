@@ -25,6 +25,8 @@ import paper_2606_20863_amd as md
 from oracle import coracle
 from oracle import exact as ox
 
+import rulecheck
+
 pytestmark = pytest.mark.gpu
 
 
@@ -61,8 +63,8 @@ def test_dot_small_rule_bitexact(m, form):
     X[:, 5, :] = 0.0                      # an all-zero vector: its product is 0
     out, info = md.dot_ex(dev(X), dev(Y), form=form)
     out = host(out)
-    beta, S, kc, band = ox.choose_dot_params(X, Y, form)
-    assert (info["beta"], info["S"], info["kc"], info["band"]) == (beta, S, kc, band)
+    rulecheck.check_info(info, form, 130, ox.TARGET_BITS[m], ox.dot_G(X, Y))
+    beta, S = info["beta"], info["S"]
     _, ref = ox.method_dot(X, Y, beta, S)
     np.testing.assert_array_equal(out, ref)
     assert np.all(out[:, 5] == 0.0)

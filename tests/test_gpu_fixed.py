@@ -27,6 +27,8 @@ import mdinputs
 import paper_2606_20863_amd as md
 from oracle import exact as ox
 
+import rulecheck
+
 pytestmark = pytest.mark.gpu
 
 # (form, beta, S): FP64 slices folded in LDS (sums captured, folded after)
@@ -86,12 +88,12 @@ def test_fixed_product_matches_oracle_and_rounds_to_the_product(form, beta, S, m
 @pytest.mark.parametrize("form,beta,S,K,kc", [("int8bal", 8, 27, 5000, 4800), ("int8", 7, 30, 4500, 4416),
                                                ("int8bal", 8, 36, 3700, 3584), ("fp64", 20, 10, 900, 816)])
 def test_fixed_product_over_several_exactness_chunks(form, beta, S, K, kc):
-    """Depths beyond one exactness chunk (kc: the oracle's chunk depth for
-    this S and beta): the captured diagonal sums accumulate over the chunks
-    (whole-triangle, banded and FP64 kernels), the integer equals the
-    oracle's and rounds to md_gemm_ex's output."""
-    assert ox.chunk_depth(S, beta, K, 1 << (53 if form == "fp64" else 31), 16 if form == "fp64" else 64,
-                          128 if form == "int8bal" else 0) == kc < K
+    """Depths beyond one exactness chunk (kc: the oracle's exact depth for
+    this S and beta, rounded down to whole fragments): the captured diagonal
+    sums accumulate over the chunks (whole-triangle, banded and FP64
+    kernels), the integer equals the oracle's and rounds to md_gemm_ex's
+    output."""
+    assert rulecheck.library_chunk(form, beta, S) == kc < K
     m, M, N = 2, 20, 24
     A, B = operands(K + S, m, M, N, K)
     X, scale, info = md.gemm_fixed(dev(A), dev(B), S=S, beta=beta, form=form)

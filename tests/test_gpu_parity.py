@@ -14,6 +14,8 @@ import paper_2606_20863_amd as md
 from oracle import coracle
 from oracle import exact as ox
 
+import rulecheck
+
 pytestmark = pytest.mark.gpu
 
 
@@ -95,9 +97,11 @@ def test_bitexact_transposed_operands(transA, transB, form, S, beta):
 @pytest.mark.parametrize("form", ["int8", "fp64"])
 @pytest.mark.parametrize("name", ["dd64", "qd1024", "od1024"])
 def test_rule_and_bound_small(form, name, rule):
-    """Default parameters: the library's rule equals the oracle's, the
-    output equals the oracle's method layer bit for bit, and every entry is
-    within 2^-T of (|A||B|)_ij of the exact product."""
+    """Default parameters: the library's certificates equal the oracle's,
+    its slice count sits within the budget (at least the minimal S, less
+    than one band more), the output equals the oracle's method layer at the
+    library's S bit for bit, and every entry is within 2^-T of
+    (|A||B|)_ij of the exact product."""
     _, m, _, _, _, _, _ = mdinputs.WORKLOADS[name]
     A, B = mdinputs.workload(name, M=48, N=40, K=72)
     C, info = md.gemm_ex(dev(A), dev(B), form=form, rule=rule)
@@ -114,8 +118,8 @@ def test_rule_and_bound_small(form, name, rule):
         if G_rho is not None:
             G = min(G_span, G_rho)
     assert info["G"] == G
-    beta, S, kc, band = ox.choose_params(form, 72, T, G)
-    assert (info["beta"], info["S"], info["kc"], info["band"]) == (beta, S, kc, band)
+    rulecheck.check_info(info, form, 72, T, G)
+    beta, S = info["beta"], info["S"]
     ref = ox.method_product(A, B, beta, S)
     np.testing.assert_array_equal(C, ref["C"])
     num, L = ox.exact_product(A, B)
@@ -144,7 +148,7 @@ def test_triangle_kernel_every_S_several_chunks(S):
     """Every one-row-block triangle instantiation without the debug dump:
     the depth exceeds one exactness chunk (S K 127^2 >= 2^31), so the
     register fold carries between chunks."""
-    kc = ox.chunk_depth(S, 7, 1 << 30, 1 << 31, ox.INT8_KGRAN)
+    kc = rulecheck.library_chunk("int8", 7, S)
     K = kc + 81
     A, B = mdinputs.workload("dd64", M=17, N=19, K=K)
     C, info = md.gemm_ex(dev(A), dev(B), form="int8", force_S=S, force_beta=7)
@@ -155,8 +159,9 @@ def test_triangle_kernel_every_S_several_chunks(S):
 @pytest.mark.parametrize("m", [1, 16])
 @pytest.mark.parametrize("form", ["int8", "fp64"])
 def test_word_counts_one_and_sixteen(m, form):
-    """Doubles and hexa-doubles: the rule's parameters equal the oracle's,
-    the output equals the oracle's method bit for bit and is within 2^-T.
+    """Doubles and hexa-doubles: the rule's parameters sit within the
+    oracle's budget, the output equals the oracle's method at the library's
+    S bit for bit and is within 2^-T.
     At m = 16 the banded kernels' LDS fold does not fit (S = 120 INT8,
     about 40 FP64), so their diagonal sums go through the [S][M][N] buffer
     and the separate fold-and-round kernel."""
@@ -172,8 +177,8 @@ def test_word_counts_one_and_sixteen(m, form):
     _, G_rho = ox.rho_G(A, B)
     if G_rho is not None:
         G = min(G, G_rho)
-    beta, S, kc, band = ox.choose_params(form, 50, T, G)
-    assert (info["beta"], info["S"], info["kc"], info["band"]) == (beta, S, kc, band)
+    rulecheck.check_info(info, form, 50, T, G)
+    beta, S = info["beta"], info["S"]
     np.testing.assert_array_equal(C, ox.method_product(A, B, beta, S)["C"])
     num, L = ox.exact_product(A, B)
     anum, _ = ox.abs_product(A, B)

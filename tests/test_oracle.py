@@ -275,7 +275,7 @@ def test_budget_rule_meets_target(name, form):
     _, sA = ox.row_exponents(A[0])
     _, sB = ox.row_exponents(B[0].T)
     G = ox.span_G(max(sA), max(sB))
-    beta, S, kc, band = ox.choose_params(form, 24, T, G)
+    beta, S, kc = ox.budget_params(form, 24, T, G)
     worst, res = _max_err(A, B, beta, S)
     assert worst <= -T
     for i in range(6):
@@ -490,3 +490,30 @@ def test_fixed_product_one_slice_closed_form(form, beta, shift):
             want = sum(t(A[0, i, k], Ei) * t(B[0, k, j], Fj) for k in range(9))
             assert X[i, j] == want, (i, j)
             assert sc[i, j] == Ei + Fj - 2 * shift
+
+
+def test_log2_fraction_pinned():
+    """log2_fraction against exact Fraction arithmetic, not against itself:
+    powers of two give their exponent exactly; for any x, writing the
+    result as n + f (n an integer) the exact quotient x / 2^n, rounded once
+    to a double, has log2 within 1e-12 of f; and 2^(n-1) <= x < 2^(n+2)
+    holds exactly, for magnitudes from 2^-3000 to 2^3000."""
+    import math
+    r = np.random.Generator(np.random.PCG64(4161))
+    for k in (-3000, -1075, -1, 0, 1, 52, 53, 1024, 3000):
+        assert ox.log2_fraction(Fraction(2) ** k) == k
+    for _ in range(400):
+        bits_p = int(r.integers(1, 3000))
+        bits_q = int(r.integers(1, 3000))
+        p = int(r.integers(1, 1 << 62)) << max(bits_p - 62, 0) | int(r.integers(0, 1 << 30))
+        q = int(r.integers(1, 1 << 62)) << max(bits_q - 62, 0) | 1
+        x = Fraction(p, q)
+        v = ox.log2_fraction(x)
+        n = math.floor(v)
+        f = v - n
+        y = x / Fraction(2) ** n                    # exact
+        assert abs(math.log2(float(y)) - f) < 1e-12, (v, float(y))
+        assert Fraction(2) ** (n - 1) <= x < Fraction(2) ** (n + 2)
+    # a planted mistake of one bit in the scaling would be seen
+    x = Fraction(3, 1 << 2000)
+    assert abs(ox.log2_fraction(x) - (math.log2(3) - 2000)) < 1e-12

@@ -171,14 +171,18 @@ def test_rule_and_headline_slice_count():
         S = ox.slice_count_balanced(T, G)
         assert 8 * S >= T + G + ox.ceil_log2(S + 3) + 3
         assert 8 * (S - 1) < T + G + ox.ceil_log2(S + 2) + 3
-    assert ox.choose_params("int8bal", 4096, 200, 3) == (8, 27, 4096, 27)
+    assert ox.budget_params("int8bal", 4096, 200, 3) == (8, 27, 4096)
 
 
-def test_chunk_depth_balanced():
-    kc = ox.chunk_depth(27, 8, 1 << 20, 1 << 31, 64, 128)
-    assert 27 * kc * 128 * 128 < 2 ** 31 <= 27 * (kc + 64) * 128 * 128
-    # the sign-magnitude bound is the default
-    assert ox.chunk_depth(30, 7, 1 << 20, 1 << 31, 64) == ox.chunk_depth(30, 7, 1 << 20, 1 << 31, 64, 127)
+def test_exact_depth_balanced():
+    """The largest exact depth: S kc dmax^2 < 2^31 <= S (kc + 1) dmax^2,
+    dmax = 128 for the balanced digits and 2^beta - 1 otherwise."""
+    kc = ox.exact_depth("int8bal", 8, 27)
+    assert 27 * kc * 128 * 128 < 2 ** 31 <= 27 * (kc + 1) * 128 * 128
+    kc = ox.exact_depth("int8", 7, 30)
+    assert 30 * kc * 127 * 127 < 2 ** 31 <= 30 * (kc + 1) * 127 * 127
+    kc = ox.exact_depth("fp64", 21, 10)
+    assert 10 * kc * (2 ** 21 - 1) ** 2 < 2 ** 53 <= 10 * (kc + 1) * (2 ** 21 - 1) ** 2
 
 
 @pytest.mark.parametrize("m,lead", [(2, ("uniform",)), (4, ("log2uniform", 8.0)), (8, ("log2uniform", 16.0))])
@@ -193,7 +197,7 @@ def test_method_within_target(m, lead):
     _, sb = ox.row_exponents(B[0].T)
     G = min(ox.span_G(max(sa), max(sb)), G if G is not None else 10 ** 6)
     T = ox.TARGET_BITS[m]
-    beta, S, _, _ = ox.choose_params("int8bal", K, T, G)
+    beta, S, _ = ox.budget_params("int8bal", K, T, G)
     res = ox.method_product(A, B, beta, S, balanced=True)
     num, L = ox.exact_product(A, B)
     anum, _ = ox.abs_product(A, B)

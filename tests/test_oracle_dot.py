@@ -113,7 +113,7 @@ def test_rule_meets_target_and_small_S_fails(m, form):
     T = ox.TARGET_BITS[m]
     X, Y = batch(m, 3, 40, 50 + m, lead=("log2uniform", 8.0))
     vals, absvals = ox.exact_dots(X, Y)
-    beta, S, _, _ = ox.choose_dot_params(X, Y, form)
+    beta, S, _ = ox.budget_params(form, X.shape[2], ox.TARGET_BITS[X.shape[0]], ox.dot_G(X, Y))
     _, out = ox.method_dot(X, Y, beta, S)
     for b in range(3):
         err = abs(ox.entry_value(out[:, b]) - vals[b])
