@@ -395,7 +395,7 @@ def small_case(md, torch, reps=200):
     for form in ("fp64", "int8bal", "int8"):
         C, info = md.gemm_ex(A, B, form=form)
         kw = dict(form=form, force_S=info["S"], force_beta=info["beta"])
-        ws = torch.empty(md.lib().md_workspace_size(md._FORMS[form], M, N, K, info["S"]),
+        ws = torch.empty(md.lib().md_gemm_workspace_size(md._FORMS[form], M, N, K, info["S"]),
                          dtype=torch.uint8, device="cuda")
         Cg = torch.empty_like(C)
         us_rule = per_call_us(lambda: md.gemm_ex(A, B, C, form=form))
@@ -419,6 +419,35 @@ def small_case(md, torch, reps=200):
     return row
 
 
+def host_cpu():
+    """The host's CPU model, physical cores and logical CPUs (from
+    /proc/cpuinfo), and the CPUs this process may run on."""
+    model, cores, logical = None, set(), 0
+    try:
+        phys = core = None
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                key, _, val = line.partition(":")
+                key, val = key.strip(), val.strip()
+                if key == "processor":
+                    logical += 1
+                elif key == "model name" and model is None:
+                    model = val
+                elif key == "physical id":
+                    phys = val
+                elif key == "core id":
+                    core = val
+                    cores.add((phys, core))
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        allowed = os.cpu_count()
+    return {"cpu_model": model, "physical_cores": len(cores) or None, "logical_cpus": logical or os.cpu_count(),
+            "cpus_allowed": allowed}
+
+
 def cpu_baseline(A, B, K):
     """The exact C oracle on whole output rows of the same product."""
     import numpy as np
@@ -432,7 +461,7 @@ def cpu_baseline(A, B, K):
     dt = time.perf_counter() - t0
     gflops = 2.0 * K * ii.shape[0] / dt / 1e9
     return {"value": round(gflops, 6), "unit": "GFLOP/s", "cores": coracle.threads(),
-            "kind": "oracle",
+            "kind": "oracle", **host_cpu(),
             "sample": f"{rows} full rows x {N} columns of the {WORKLOAD} product "
                       f"(exact superaccumulator oracle, {dt:.1f} s); rate scaled per output entry"}
 
@@ -592,7 +621,8 @@ def main():
     if not args.no_split:
         out["depth_split"] = depth_split(md, torch, A, B, C8, info8)
         progress("depth split done")
-    defer_error(head_form, "max_log2_err_sampled", Ah, Bh, C8)
+    defer_error(head_form, "max_log2_err_sampled", Ah, Bh, C8, n=64)
+    head_form["error_sample"] = "64 x 64 grid of entries (4,096), exact C oracle"
     defer_error(out["fp64_form"], "max_log2_err_sampled", Ah, Bh, C64)
     if sm is not None:
         defer_error(out["int8_sign_magnitude_form"], "max_log2_err_sampled", Ah, Bh, sm[0])

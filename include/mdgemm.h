@@ -43,8 +43,18 @@
  * Every call is ordered on `stream` (a hipStream_t; NULL = the null stream).
  * Choosing S from the data needs the exponent spans on the host, so the
  * call synchronises `stream` once after the exponent step unless
- * opts->force_S is set.  Errors of argument checking are returned before
- * any work is queued; device faults surface at the next synchronisation.
+ * opts->force_S is set, or opts->s_hint with opts->cert: then the call runs
+ * on the hinted S and the device checks the data's certificate into
+ * *opts->cert without waiting.  Errors of argument checking are returned
+ * before any work is queued; device faults surface at the next
+ * synchronisation.
+ *
+ * Range: the 2^-T bound needs every product inside the double range, which
+ * the rule checks from the shared exponents (E_i + F_j + ceil(log2 K) <=
+ * 1023 and E_i + F_j >= G + T - 1073 over the rows and columns with a
+ * nonzero leading word); where it fails the call still returns the rounded
+ * words, and md_info.input_flags bit 16 (MD_CERT_RANGE in a certificate)
+ * reports that no bound is certified.
  *
  * All entry points are thread-safe; calls on different streams may run
  * concurrently.  The library allocates its scratch memory with
@@ -100,11 +110,28 @@ typedef struct md_info {
     int G_span;         /* span bound: span_A + span_B + 2 */
     int G_rho;          /* magnitude bound (-1: not computed or not certifiable) */
     int target_bits;    /* T */
-    double log2_bound;  /* certified log2 of the max relative error vs (|A||B|)_ij */
+    double log2_bound;  /* certified log2 of the max relative error vs (|A||B|)_ij
+                           (+inf: none; 0 with a forced S; NaN with a hint: see md_cert) */
     int input_flags;    /* validation mode: OR over the entries of 1 (a word not finite),
                            2 (not weakly nonoverlapping), 4 (leading word out of range);
-                           md_gemm_fixed: 8 (a given shared exponent not taken) */
+                           md_gemm_fixed: 8 (a given shared exponent not taken);
+                           the rule: 16 (a product may leave the double range, no bound) */
 } md_info;
+
+/* Certificate of a call run on a slice-count hint (md_opts.s_hint), written
+ * on the device in stream order into caller-owned device memory: the rule's
+ * certificates for this call's data, checked against the hinted S. */
+typedef struct md_cert {
+    int32_t flags;      /* MD_CERT_SMALL | MD_CERT_RANGE, 0 when the hint meets 2^-T */
+    int32_t S_min;      /* S the rule would take for this data (same form and beta) */
+    int32_t S;          /* S used (the hint) */
+    int32_t G;          /* certified ratio exponent (the smaller of G_span and G_rho) */
+    int32_t G_span;
+    int32_t G_rho;      /* -1: not computed (MD_S_SPAN) or not certifiable */
+    double log2_bound;  /* certified log2 relative error of the S used (+inf: none) */
+} md_cert;
+#define MD_CERT_SMALL 1 /* the hint is below S_min: 2^-T is not certified, log2_bound is */
+#define MD_CERT_RANGE 2 /* a product may leave the double range: no bound */
 
 /* Debug dump (small shapes): every non-NULL pointer is a device buffer the
  * caller owns, of at least the size shown; the library writes it during the
@@ -137,10 +164,18 @@ typedef struct md_opts {
     int32_t *exp_flags;    /* md_gemm_fixed with given E or F: optional device int32 into
                               which bit 8 is ORed (never cleared) when a given exponent is
                               not taken, instead of a synchronisation and MD_EINPUT */
+    int s_hint;            /* > 0 (force_S = 0): run on this S (FP64: with force_beta)
+                              without waiting for the rule, e.g. the previous call's S;
+                              needs cert */
+    md_cert *cert;         /* with s_hint: device record of the data's certificate */
 } md_opts;
 
 /*
- * C = A B for m-double matrices, the plain FP64-slice form.
+ * C = A B for m-double matrices, the plain FP64-slice form: the paper's
+ * error-free summation of m-double inner products (Section 2: split every
+ * double into bit fields, add the parts exactly, fuse once; Figure 1) for
+ * every entry, its convolution sums run as slice matrix products
+ * (Conclusions).
  *   m: words per entry, 1, 2, 4, 8 or 16.
  *   A: m planes of M x K, row-major, dense (lda = K, plane stride M K).
  *   B: m planes of K x N, row-major, dense.
@@ -153,7 +188,8 @@ int md_gemm(int m, int64_t M, int64_t N, int64_t K, const double *A, const doubl
             void *stream);
 
 /*
- * C = op(A) op(B) with strides and options.
+ * C = op(A) op(B) with strides and options: md_gemm's computation (Section
+ * 2, Figure 1, Conclusions) in any of the three slice forms.
  *   op(A) is M x K: element (i, k) at A[i*lda + k] (transA = 0) or
  *   A[k*lda + i] (transA = 1), word w at + w*plane_stride_A.
  *   op(B) is K x N: element (k, j) at B[k*ldb + j] (transB = 0) or
@@ -161,7 +197,7 @@ int md_gemm(int m, int64_t M, int64_t N, int64_t K, const double *A, const doubl
  *   C: element (i, j) word w at C[w*plane_stride_C + i*ldc + j].
  *   opts may be NULL (FP64 form, MD_S_RHO rule, T = 50 m).
  * Graph capture: with opts->force_S set, opts->validate and opts->dbg
- * clear and a workspace of at least md_workspace_size bytes, the call only
+ * clear and a workspace of at least md_gemm_workspace_size bytes, the call only
  * launches kernels on `stream` (no allocation, copy, memset or
  * synchronisation), so it can be captured into a HIP graph and replayed.
  * Replays reuse the workspace: replays (or calls) that share one must not
@@ -263,7 +299,9 @@ int md_exponents(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda, 
  *          rounded words they produce on the way (m M N doubles).
  *   E, F:  shared exponents of the rows of A and columns of B (device, M and
  *          N int32) or NULL for the data's own.  Each given one must be at
- *          least the data's own and at most 1100; otherwise the call
+ *          least the data's own (any value from -1100 for a row or column
+ *          whose leading words are all zero in this block: its digits are
+ *          zero on every grid) and at most 1100; otherwise the call
  *          returns MD_EINPUT with md_info.input_flags bit 8 (if opts->info),
  *          X and scale unspecified.  Given E or F make the call synchronise
  *          `stream` once to check them, unless opts->exp_flags is set: then
@@ -304,7 +342,11 @@ int md_fixed_round(int m, int64_t count, int nlimb, const int32_t *X, const int3
  */
 int md_choose_params(int form, int64_t K, int T, int G, int *beta, int *S, int *kc, int *band);
 
-/* Scratch bytes a call with these sizes and parameters needs. */
+/* Scratch bytes an md_gemm_ex call with these sizes, form and S needs (the
+ * workspace that lets a call allocate nothing). */
+size_t md_gemm_workspace_size(int form, int64_t M, int64_t N, int64_t K, int S);
+
+/* The same (the name of earlier versions). */
 size_t md_workspace_size(int form, int64_t M, int64_t N, int64_t K, int S);
 
 /* Scratch bytes an md_dot_ex call with batch pairs of length n and slice

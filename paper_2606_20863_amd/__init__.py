@@ -68,13 +68,27 @@ class MDDebug(ctypes.Structure):
                 ("digits_B", ctypes.c_void_p), ("D", ctypes.c_void_p)]
 
 
+class MDCert(ctypes.Structure):
+    _fields_ = [("flags", ctypes.c_int32), ("S_min", ctypes.c_int32), ("S", ctypes.c_int32),
+                ("G", ctypes.c_int32), ("G_span", ctypes.c_int32), ("G_rho", ctypes.c_int32),
+                ("log2_bound", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+CERT_SMALL = 1   # the hinted S is below the rule's: 2^-T not certified
+CERT_RANGE = 2   # a product may leave the double range: no bound
+
+
 class MDOpts(ctypes.Structure):
     _fields_ = [("form", ctypes.c_int), ("s_rule", ctypes.c_int), ("target_bits", ctypes.c_int),
                 ("force_S", ctypes.c_int), ("force_beta", ctypes.c_int),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
                 ("dbg", ctypes.POINTER(MDDebug)), ("info", ctypes.POINTER(MDInfo)),
                 ("ev_gemm_begin", ctypes.c_void_p), ("ev_gemm_end", ctypes.c_void_p),
-                ("validate", ctypes.c_int), ("exp_flags", ctypes.c_void_p)]
+                ("validate", ctypes.c_int), ("exp_flags", ctypes.c_void_p),
+                ("s_hint", ctypes.c_int), ("cert", ctypes.c_void_p)]
 
 
 class MDError(RuntimeError):
@@ -110,6 +124,8 @@ def lib():
     L.md_choose_params.argtypes = [i32, i64, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                    ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.md_choose_params.restype = i32
+    L.md_gemm_workspace_size.argtypes = [i32, i64, i64, i64, i32]
+    L.md_gemm_workspace_size.restype = ctypes.c_size_t
     L.md_workspace_size.argtypes = [i32, i64, i64, i64, i32]
     L.md_workspace_size.restype = ctypes.c_size_t
     L.md_dot_workspace_size.argtypes = [i32, i64, i64, i32]
@@ -169,10 +185,45 @@ def _check_planes(X: torch.Tensor, name: str):
         raise ValueError(f"{name} must be a float64 (m, rows, cols) tensor on the HIP device")
 
 
+def _device_buffer(t: torch.Tensor, name: str, device, nbytes: int = 1):
+    """Pointer and size of a caller's device buffer: contiguous, on the
+    operands' device, at least nbytes long (checked before any call, so no
+    host pointer reaches a kernel)."""
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.device != device or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous tensor on {device}")
+    size = t.numel() * t.element_size()
+    if size < nbytes:
+        raise ValueError(f"{name} holds {size} bytes, {nbytes} needed")
+    return ctypes.c_void_p(t.data_ptr()), size
+
+
+def new_cert(device=None) -> torch.Tensor:
+    """A device buffer for one md_cert record (see ``read_cert``)."""
+    return torch.zeros(ctypes.sizeof(MDCert), dtype=torch.uint8, device=device or "cuda")
+
+
+def read_cert(cert: torch.Tensor) -> dict:
+    """The md_cert record a hinted call wrote (synchronises with the copy)."""
+    raw = bytes(cert[:ctypes.sizeof(MDCert)].cpu().numpy().tobytes())
+    return MDCert.from_buffer_copy(raw).as_dict()
+
+
+def _slice_opts(opts: "MDOpts", device, force_S, force_beta, s_hint, cert, workspace):
+    opts.force_S = force_S
+    opts.force_beta = force_beta
+    opts.s_hint = s_hint
+    if s_hint:
+        if cert is None:
+            raise ValueError("s_hint needs a cert buffer (new_cert())")
+        opts.cert, _ = _device_buffer(cert, "cert", device, ctypes.sizeof(MDCert))
+    if workspace is not None:
+        opts.workspace, opts.workspace_bytes = _device_buffer(workspace, "workspace", device)
+
+
 def gemm_ex(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None, *, transA=False,
             transB=False, form="fp64", rule="rho", target_bits=0, force_S=0, force_beta=0,
             debug=None, workspace: torch.Tensor | None = None, events=None, stream=None,
-            validate=False):
+            validate=False, s_hint=0, cert: torch.Tensor | None = None):
     """C = op(A) op(B) in m-double arithmetic.
 
     A is (m, M, K) (or (m, K, M) with transA), B is (m, K, N) (or (m, N, K)
@@ -181,7 +232,11 @@ def gemm_ex(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None, *, 
     digits_A, digits_B, D (see ``md_debug``).  ``events`` may be a pair of
     raw hipEvent_t handles recorded around the slice contraction.
     ``validate``: check the input preconditions first (MDError MD_EINPUT,
-    C untouched, when an entry breaks them).
+    C untouched, when an entry breaks them).  ``s_hint`` (with ``cert``, a
+    ``new_cert()`` buffer): run on that S without waiting for the rule; the
+    device writes the data's certificate into ``cert`` (``read_cert``).
+    ``workspace``: a contiguous device buffer of at least
+    ``md_gemm_workspace_size`` bytes (the call then allocates nothing).
     """
     _check_planes(A, "A")
     _check_planes(B, "B")
@@ -203,13 +258,9 @@ def gemm_ex(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None, *, 
     opts.form = _FORMS[form]
     opts.s_rule = _RULES[rule]
     opts.target_bits = target_bits
-    opts.force_S = force_S
-    opts.force_beta = force_beta
     opts.validate = 1 if validate else 0
     opts.info = ctypes.pointer(info)
-    if workspace is not None:
-        opts.workspace = ctypes.c_void_p(workspace.data_ptr())
-        opts.workspace_bytes = workspace.numel() * workspace.element_size()
+    _slice_opts(opts, A.device, force_S, force_beta, s_hint, cert, workspace)
     if events is not None:
         opts.ev_gemm_begin = ctypes.c_void_p(events[0])
         opts.ev_gemm_end = ctypes.c_void_p(events[1])
@@ -258,14 +309,16 @@ def gemm(A: torch.Tensor, B: torch.Tensor, form: str = "fp64", stream=None) -> t
 
 def dot_ex(X: torch.Tensor, Y: torch.Tensor, out: torch.Tensor | None = None, *, form="fp64",
            rule="rho", target_bits=0, force_S=0, force_beta=0, events=None, stream=None,
-           validate=False, workspace: torch.Tensor | None = None):
+           validate=False, workspace: torch.Tensor | None = None, s_hint=0,
+           cert: torch.Tensor | None = None):
     """Batched m-double inner products out_b = sum_k X[:, b, k] Y[:, b, k].
 
     X and Y are (m, batch, n) float64 planes on the HIP device (m = 1, 2, 4,
     8 or 16); out is (m, batch).  Returns (out, info dict); ``events`` and
     ``validate`` as in ``gemm_ex`` (events recorded around the contraction
     and the fold).  ``workspace``: a device byte buffer of at least
-    ``md_dot_workspace_size`` bytes (the library then allocates nothing).
+    ``md_dot_workspace_size`` bytes (the library then allocates nothing);
+    ``s_hint`` and ``cert`` as in ``gemm_ex``.
     """
     _check_planes(X, "X")
     _check_planes(Y, "Y")
@@ -283,13 +336,9 @@ def dot_ex(X: torch.Tensor, Y: torch.Tensor, out: torch.Tensor | None = None, *,
     opts.form = _FORMS[form]
     opts.s_rule = _RULES[rule]
     opts.target_bits = target_bits
-    opts.force_S = force_S
-    opts.force_beta = force_beta
     opts.validate = 1 if validate else 0
     opts.info = ctypes.pointer(info)
-    if workspace is not None:
-        opts.workspace = ctypes.c_void_p(workspace.data_ptr())
-        opts.workspace_bytes = workspace.numel() * workspace.element_size()
+    _slice_opts(opts, X.device, force_S, force_beta, s_hint, cert, workspace)
     if events is not None:
         opts.ev_gemm_begin = ctypes.c_void_p(events[0])
         opts.ev_gemm_end = ctypes.c_void_p(events[1])
@@ -470,4 +519,4 @@ class MDGemm(torch.autograd.Function):
 
 
 __all__ = ["gemm", "gemm_ex", "gemm_ordinary", "dot", "dot_ex", "MDGemm", "choose_params", "lib",
-           "MDError", "MDInfo"]
+           "MDError", "MDInfo", "MDCert", "new_cert", "read_cert"]

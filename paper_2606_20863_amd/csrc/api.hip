@@ -2,6 +2,7 @@
 // scratch memory and the launch sequence on the caller's stream.
 #include "../../include/mdgemm.h"
 #include "mdgemm_internal.h"
+#include "rule.h"
 
 #include <algorithm>
 #include <climits>
@@ -58,41 +59,7 @@ int hip_fail(hipError_t e)
     return MD_EHIP;
 }
 
-int ceil_log2(int64_t n)
-{
-    int b = 0;
-    while (((int64_t)1 << b) < n)
-        ++b;
-    return b;
-}
-
-// Smallest S with beta S >= T + G + ceil(log2(S + 2)) + 1.  Per product term,
-// truncating both entries to S digits and dropping the digit pairs with
-// s + u >= S errs by less than (S + 1 + 2^-(beta S)) 2^(E_i + F_j - beta S);
-// with 2^G bounding N_ij 2^(E_i + F_j) / (|A||B|)_ij this keeps the
-// method's error below 2^-(T+1) of (|A||B|)_ij, and the final rounding into
-// m words adds less than 2^-(53 m) <= 2^-(T+5) of it.
-int slice_count(int beta, int T, int G)
-{
-    int S = 1;
-    while ((int64_t)beta * S < (int64_t)T + G + ceil_log2(S + 2) + 1)
-        ++S;
-    return S;
-}
-
-// Balanced INT8 digits: smallest S with 8 S >= T + G + ceil(log2(S + 3)) + 3.
-// The grids start at 2^(E_i + 2) and 2^(F_j + 2); per product term the
-// truncation errs by less than 2^(E_i + F_j + 3 - 8 S) and the dropped pairs
-// (digits up to 128 in magnitude) by less than
-// (S - 1) (256/255) 2^(E_i + F_j + 2 - 8 S), together less than
-// (S + 3) 2^(E_i + F_j + 2 - 8 S) for S <= 511.
-int slice_count_balanced(int T, int G)
-{
-    int S = 1;
-    while ((int64_t)8 * S < (int64_t)T + G + ceil_log2(S + 3) + 3)
-        ++S;
-    return S;
-}
+int ceil_log2(int64_t n) { return rule_ceil_log2(n); }
 
 bool is_i8(int form) { return form == MD_FORM_INT8 || form == MD_FORM_INT8_BAL; }
 
@@ -105,18 +72,9 @@ int64_t digit_max(int form, int beta)
     return form == MD_FORM_INT8_BAL ? 128 : ((int64_t)1 << beta) - 1;
 }
 
-// Bands of at most gmax diagonals, all of one width: S rounds up to
-// nb * ceil(S / nb) with nb = ceil(S / gmax); S <= single stays one band
-// (INT8 contracts up to kTriMaxI8 diagonals at once).
 void band_round(int Smin, int gmax, int single, int& S, int& band)
 {
-    if (Smin <= single) {
-        S = band = Smin;
-        return;
-    }
-    const int nb = (Smin + gmax - 1) / gmax;
-    band = (Smin + nb - 1) / nb;
-    S = nb * band;
+    rule_band_round(Smin, gmax, single, S, band);
 }
 
 // Largest multiple of gran with S * kc * dmax^2 < limit (dmax the largest
@@ -135,13 +93,13 @@ int choose(int form, int64_t K, int T, int G, int& beta, int& S, int64_t& kc, in
         return MD_EINVAL_OPT;
     if (form == MD_FORM_INT8) {
         beta = 7;
-        band_round(slice_count(7, T, G), kGmaxI8, kTriMaxI8, S, band);
+        band_round(rule_slice_count(7, T, G), kGmaxI8, kTriMaxI8, S, band);
         kc = chunk_depth(S, 127, K, (int64_t)1 << 31, kKcI8);
         return kc > 0 ? MD_OK : MD_ERANGE;
     }
     if (form == MD_FORM_INT8_BAL) {
         beta = 8;
-        band_round(slice_count_balanced(T, G), kGmaxI8, kTriMaxI8, S, band);
+        band_round(rule_slice_count_balanced(T, G), kGmaxI8, kTriMaxI8, S, band);
         kc = chunk_depth(S, 128, K, (int64_t)1 << 31, kKcI8);
         return kc > 0 ? MD_OK : MD_ERANGE;
     }
@@ -149,7 +107,7 @@ int choose(int form, int64_t K, int T, int G, int& beta, int& S, int64_t& kc, in
         bool found = false;
         for (int b = 8; b <= 24; ++b) {
             int s, bd;
-            band_round(slice_count(b, T, G), kGmaxF64, 0, s, bd);
+            band_round(rule_slice_count(b, T, G), kGmaxF64, 0, s, bd);
             const int64_t k = chunk_depth(s, ((int64_t)1 << b) - 1, K, (int64_t)1 << 53, kKcF64);
             if (k <= 0)
                 continue;
@@ -183,22 +141,6 @@ bool needs_global_fold(int form, int band, int S, int ncol)
     if (is_i8(form))
         return !(band == S && S <= kTriMaxI8);
     return (size_t)4 * ncol * 256 * sizeof(int64_t) > 160 * 1024;
-}
-
-// Magnitude certificate.  With q = floor(|a^(0)| 2^(7-E_i)) and strongly
-// nonoverlapping words, |a_ik||b_kj| >= (1 - 2^-51) 2^(E_i+F_j-14) qA_ik qB_kj,
-// so N_ij 2^(E_i+F_j) / (|A||B|)_ij <= K 2^14 / ((1 - 2^-51) minP).  Returns the
-// smallest G >= 0 with minP 2^G >= K 2^14 + 1 (which covers the 1 - 2^-51
-// factor for K < 2^36), or -1 when minP is 0 (no certificate).
-int rho_exponent(uint64_t minP, int64_t K)
-{
-    if (minP == 0 || minP == ~0ull)
-        return -1;
-    const unsigned __int128 target = ((unsigned __int128)K << 14) + 1;
-    int g = 0;
-    while (((unsigned __int128)minP << g) < target)
-        ++g;
-    return g;
 }
 
 struct Span {
@@ -328,6 +270,109 @@ size_t small_bytes(int64_t M, int64_t N)
     return (size_t)(3 * round_up(M + 64, 64) + 3 * round_up(N + 64, 64) + 64) * sizeof(int32_t) + 7 * 256;
 }
 
+
+// Slice parameters of a call and what the rule certified.
+struct Choice {
+    int beta = 0, S = 0, band = 0;
+    int64_t kc = 0;
+    int G = -1, G_span = -1, G_rho = -1, span_A = -1, span_B = -1;
+    int flags = 0;              // md_info.input_flags bits of the rule (16: range)
+    double log2_bound = 0.0;
+};
+
+// Option checks of the slice parameters (before any device work).
+int check_slice_opts(const md_opts& o)
+{
+    if (o.force_S < 0 || o.force_S > 512 || o.s_hint < 0 || o.s_hint > 512)
+        return MD_EINVAL_OPT;
+    const int S = o.force_S > 0 ? o.force_S : o.s_hint;
+    if (S == 0)
+        return MD_OK;
+    if (o.force_S == 0 && !o.cert)
+        return MD_EINVAL_OPT;   // a hint needs the device record of its certificate
+    // a given S must split into equal bands
+    int s2, band;
+    band_round(S, is_i8(o.form) ? kGmaxI8 : kGmaxF64, is_i8(o.form) ? kTriMaxI8 : 0, s2, band);
+    if (s2 != S)
+        return MD_EINVAL_OPT;
+    const int need = o.form == MD_FORM_INT8 ? 7 : o.form == MD_FORM_INT8_BAL ? 8 : 0;
+    if (need)
+        return o.force_beta == need || (o.force_S == 0 && o.force_beta == 0) ? MD_OK : MD_EINVAL_OPT;
+    return o.force_beta >= 1 && o.force_beta <= 24 ? MD_OK : MD_EINVAL_OPT;
+}
+
+// Forced S (opts->force_S): no device reads.  Hint (opts->s_hint): the same
+// parameters, and the certificate of the data is checked on the device into
+// *opts->cert after the statistics (no wait).  Otherwise the rule: one copy
+// of the statistics to the host and one synchronisation.  stats: the
+// call's statistics (kStatWords), complete in stream order.
+int choose_slices(const md_opts& o, int m, int64_t K, int T, const int32_t* stats, hipStream_t st, Choice& c)
+{
+    const int Sgiven = o.force_S > 0 ? o.force_S : o.s_hint;
+    hipError_t e;
+    if (Sgiven > 0) {
+        c.beta = o.form == MD_FORM_INT8 ? 7 : o.form == MD_FORM_INT8_BAL ? 8 : o.force_beta;
+        const int gmax = is_i8(o.form) ? kGmaxI8 : kGmaxF64;
+        const int single = is_i8(o.form) ? kTriMaxI8 : 0;
+        int s2;
+        band_round(Sgiven, gmax, single, s2, c.band);
+        if (s2 != Sgiven)
+            return MD_EINVAL_OPT;   // a given S must split into equal bands
+        c.S = Sgiven;
+        c.kc = chunk_depth(c.S, digit_max(o.form, c.beta), K,
+                           is_i8(o.form) ? ((int64_t)1 << 31) : ((int64_t)1 << 53), is_i8(o.form) ? kKcI8 : kKcF64);
+        if (c.kc <= 0)
+            return MD_ERANGE;
+        if (o.force_S > 0)
+            return MD_OK;
+        if ((e = launch_cert(stats, o.form, K, T, m, c.beta, c.S, o.cert, st)) != hipSuccess)
+            return hip_fail(e);
+        c.log2_bound = __builtin_nan("");
+        return MD_OK;
+    }
+    int32_t h[kStatWords];
+    if ((e = hipMemcpyAsync(h, stats, sizeof(h), hipMemcpyDeviceToHost, st)) != hipSuccess)
+        return hip_fail(e);
+    if ((e = hipStreamSynchronize(st)) != hipSuccess)
+        return hip_fail(e);
+    c.span_A = h[0];
+    c.span_B = h[1];
+    c.G_span = h[0] + h[1] + 2;
+    c.G = c.G_span;
+    if (o.s_rule == MD_S_RHO) {
+        uint64_t minP;
+        memcpy(&minP, h + 2, sizeof(minP));
+        c.G_rho = rule_rho_exponent(minP, K);
+        if (c.G_rho >= 0 && c.G_rho < c.G)
+            c.G = c.G_rho;
+    }
+    const int rc = choose(o.form, K, T, c.G, c.beta, c.S, c.kc, c.band);
+    if (rc)
+        return rc;
+    c.log2_bound = rule_log2_bound(o.form == MD_FORM_INT8_BAL, c.G, c.beta, c.S, m);
+    if (!rule_in_range(h[4], h[5], h[6], h[7], K, c.G, T)) {
+        c.flags |= 16;
+        c.log2_bound = __builtin_inf();
+    }
+    return MD_OK;
+}
+
+void fill_info(md_info* in, const Choice& c, int T, bool validated)
+{
+    in->S = c.S;
+    in->beta = c.beta;
+    in->kc = (int)std::min<int64_t>(c.kc, INT_MAX);
+    in->band = c.band;
+    in->span_A = c.span_A;
+    in->span_B = c.span_B;
+    in->G = c.G;
+    in->G_span = c.G_span;
+    in->G_rho = c.G_rho;
+    in->target_bits = T;
+    in->log2_bound = c.log2_bound;
+    in->input_flags = validated ? in->input_flags | c.flags : c.flags;
+}
+
 }  // namespace
 
 extern "C" {
@@ -351,7 +396,7 @@ const char* md_strerror(int code)
 
 int md_last_hip_error(void) { return g_last_hip; }
 
-int md_version(void) { return 200; }
+int md_version(void) { return 30000; }
 
 int md_choose_params(int form, int64_t K, int T, int G, int* beta, int* S, int* kc, int* band)
 {
@@ -375,7 +420,7 @@ size_t md_dot_workspace_size(int form, int64_t batch, int64_t n, int S)
            2 * digits_bytes(form, batch, n, S) + (size_t)S * batch * sizeof(int64_t) + 4096;
 }
 
-size_t md_workspace_size(int form, int64_t M, int64_t N, int64_t K, int S)
+size_t md_gemm_workspace_size(int form, int64_t M, int64_t N, int64_t K, int S)
 {
     size_t bytes = small_bytes(M, N) + digits_bytes(MD_FORM_INT8, M, K, 1) +
                    digits_bytes(MD_FORM_INT8, N, K, 1) + digits_bytes(form, M, K, S) +
@@ -389,6 +434,11 @@ size_t md_workspace_size(int form, int64_t M, int64_t N, int64_t K, int S)
     if (global)
         bytes += (size_t)gd_elements(M, N, S, is_i8(form) ? 2 : 1) * sizeof(int64_t) + 256;
     return bytes;
+}
+
+size_t md_workspace_size(int form, int64_t M, int64_t N, int64_t K, int S)
+{
+    return md_gemm_workspace_size(form, M, N, K, S);
 }
 
 }  // extern "C"
@@ -455,9 +505,7 @@ int gemm_impl(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, co
             return MD_EALIAS;
     }
     const int T = o.target_bits > 0 ? o.target_bits : 50 * m;
-    if (o.force_S < 0 || o.force_S > 512 || (o.force_S > 0 && (o.force_beta < 1 || o.force_beta > 24)) ||
-        (o.force_S > 0 && o.form == MD_FORM_INT8 && o.force_beta != 7) ||
-        (o.force_S > 0 && o.form == MD_FORM_INT8_BAL && o.force_beta != 8))
+    if (check_slice_opts(o) != MD_OK)
         return MD_EINVAL_OPT;
     if ((E_in || F_in) && (o.force_S == 0 || !exp_flags))
         return MD_EINVAL_OPT;
@@ -515,15 +563,11 @@ int gemm_impl(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, co
     if ((e = launch_exp_partial(opA, hiA, loA, st)) != hipSuccess) return hip_fail(e);
     if ((e = launch_exp_partial(opB, hiB, loB, st)) != hipSuccess) return hip_fail(e);
     const int eoff = grid_offset(o.form);
-    if ((e = launch_exp_final(hiA, loA, M, E, stats, dbg ? dbg->E : nullptr, eoff, st)) != hipSuccess) return hip_fail(e);
-    if ((e = launch_exp_final(hiB, loB, N, F, stats + 1, dbg ? dbg->F : nullptr, eoff, st)) != hipSuccess) return hip_fail(e);
-    if (E_in && (e = launch_exp_set(E_in, M, eoff, E, exp_flags, st)) != hipSuccess) return hip_fail(e);
-    if (F_in && (e = launch_exp_set(F_in, N, eoff, F, exp_flags, st)) != hipSuccess) return hip_fail(e);
+    if ((e = launch_exp_final(hiA, loA, M, E, stats, stats + 4, dbg ? dbg->E : nullptr, eoff, st)) != hipSuccess) return hip_fail(e);
+    if ((e = launch_exp_final(hiB, loB, N, F, stats + 1, stats + 6, dbg ? dbg->F : nullptr, eoff, st)) != hipSuccess) return hip_fail(e);
+    if (E_in && (e = launch_exp_set(E_in, hiA, M, eoff, E, exp_flags, st)) != hipSuccess) return hip_fail(e);
+    if (F_in && (e = launch_exp_set(F_in, hiB, N, eoff, F, exp_flags, st)) != hipSuccess) return hip_fail(e);
 
-    int32_t spans[4] = {0, 0, 0, 0};   // span_A, span_B, minimum magnitude product (uint64)
-    int beta, S, band;
-    int64_t kc;
-    int G = 0, G_span = 0, G_rho = -1;
     const bool use_rho = o.force_S == 0 && o.s_rule == MD_S_RHO;
     if (use_rho) {
         // magnitude certificate: min_ij sum_k qA_ik qB_kj, q the 7-bit
@@ -543,37 +587,14 @@ int gemm_impl(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, co
         if ((e = launch_mag_min(qA, qB, M, N, nkm, (unsigned long long*)(stats + 2), st)) != hipSuccess)
             return hip_fail(e);
     }
-    if (o.force_S > 0) {
-        beta = o.force_beta;
-        const int gmax = is_i8(o.form) ? kGmaxI8 : kGmaxF64;
-        const int single = is_i8(o.form) ? kTriMaxI8 : 0;
-        int s2;
-        band_round(o.force_S, gmax, single, s2, band);
-        if (s2 != o.force_S)
-            return MD_EINVAL_OPT;   // forced S must split into equal bands
-        S = o.force_S;
-        kc = chunk_depth(S, digit_max(o.form, beta), K, is_i8(o.form) ? ((int64_t)1 << 31) : ((int64_t)1 << 53),
-                         is_i8(o.form) ? kKcI8 : kKcF64);
-        if (kc <= 0)
-            return MD_ERANGE;
-    } else {
-        if ((e = hipMemcpyAsync(spans, stats, sizeof(spans), hipMemcpyDeviceToHost, st)) != hipSuccess)
-            return hip_fail(e);
-        if ((e = hipStreamSynchronize(st)) != hipSuccess)
-            return hip_fail(e);
-        G_span = spans[0] + spans[1] + 2;
-        G = G_span;
-        if (use_rho) {
-            uint64_t minP;
-            memcpy(&minP, spans + 2, sizeof(minP));
-            G_rho = rho_exponent(minP, K);
-            if (G_rho >= 0 && G_rho < G)
-                G = G_rho;
-        }
-        const int rc = choose(o.form, K, T, G, beta, S, kc, band);
+    Choice ch;
+    {
+        const int rc = choose_slices(o, m, K, T, stats, st, ch);
         if (rc)
             return rc;
     }
+    const int beta = ch.beta, S = ch.S, band = ch.band;
+    const int64_t kc = ch.kc;
     const int kcg = is_i8(o.form) ? kKcI8 : kKcF64;
     const int64_t nkc = (K + kcg - 1) / kcg;
     const int64_t Mp = round_up(M, kTile), Np = round_up(N, kTile);
@@ -683,26 +704,8 @@ int gemm_impl(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, co
     if (o.ev_gemm_end && (e = hipEventRecord((hipEvent_t)o.ev_gemm_end, st)) != hipSuccess)
         return hip_fail(e);
 
-    if (o.info) {
-        md_info* in = o.info;
-        in->S = S;
-        in->beta = beta;
-        in->kc = (int)std::min<int64_t>(kc, INT_MAX);
-        in->band = band;
-        in->span_A = spans[0];
-        in->span_B = spans[1];
-        in->G = G;
-        in->G_span = G_span;
-        in->G_rho = G_rho;
-        in->target_bits = T;
-        if (!o.validate)
-            in->input_flags = 0;
-        // certified bound of the method plus the final rounding
-        const double lb = o.form == MD_FORM_INT8_BAL
-                              ? (double)(G + 2 - 8 * S) + __builtin_log2((double)S + 3.0)
-                              : (double)(G - beta * S) + __builtin_log2((double)S + 2.0);
-        in->log2_bound = o.force_S > 0 ? 0.0 : __builtin_log2(__builtin_exp2(lb) + __builtin_exp2(-53.0 * m + 0.1));
-    }
+    if (o.info)
+        fill_info(o.info, ch, T, o.validate != 0);
     return MD_OK;
 }
 
@@ -758,9 +761,7 @@ int md_dot_ex(int m, int64_t batch, int64_t n, const double* X, int64_t ldx, int
             return MD_EALIAS;
     }
     const int T = o.target_bits > 0 ? o.target_bits : 50 * m;
-    if (o.force_S < 0 || o.force_S > 512 || (o.force_S > 0 && (o.force_beta < 1 || o.force_beta > 24)) ||
-        (o.force_S > 0 && o.form == MD_FORM_INT8 && o.force_beta != 7) ||
-        (o.force_S > 0 && o.form == MD_FORM_INT8_BAL && o.force_beta != 8))
+    if (check_slice_opts(o) != MD_OK)
         return MD_EINVAL_OPT;
 
     hipStream_t st = (hipStream_t)stream;
@@ -813,14 +814,10 @@ int md_dot_ex(int m, int64_t batch, int64_t n, const double* X, int64_t ldx, int
     if ((e = launch_exp_partial(opX, hiX, loX, st)) != hipSuccess) return hip_fail(e);
     if ((e = launch_exp_partial(opY, hiY, loY, st)) != hipSuccess) return hip_fail(e);
     const int eoff = grid_offset(o.form);
-    if ((e = launch_exp_final(hiX, loX, batch, E, stats, nullptr, eoff, st)) != hipSuccess) return hip_fail(e);
-    if ((e = launch_exp_final(hiY, loY, batch, F, stats + 1, nullptr, eoff, st)) != hipSuccess) return hip_fail(e);
+    if ((e = launch_exp_final(hiX, loX, batch, E, stats, stats + 4, nullptr, eoff, st)) != hipSuccess) return hip_fail(e);
+    if ((e = launch_exp_final(hiY, loY, batch, F, stats + 1, stats + 6, nullptr, eoff, st)) != hipSuccess) return hip_fail(e);
 
     const int64_t nrb = round_up(batch, kTile) / kRowBlock;
-    int32_t spans[4] = {0, 0, 0, 0};   // span_X, span_Y, minimum magnitude product (uint64)
-    int beta, S, band;
-    int64_t kc;
-    int G = 0, G_span = 0, G_rho = -1;
     const bool use_rho = o.force_S == 0 && o.s_rule == MD_S_RHO;
     if (use_rho) {
         // magnitude certificate over the pairs: min_b sum_k qX_bk qY_bk
@@ -839,37 +836,14 @@ int md_dot_ex(int m, int64_t batch, int64_t n, const double* X, int64_t ldx, int
         if ((e = launch_mag_min_diag(qX, qY, batch, nkm, (unsigned long long*)(stats + 2), st)) != hipSuccess)
             return hip_fail(e);
     }
-    if (o.force_S > 0) {
-        beta = o.force_beta;
-        const int gmax = is_i8(o.form) ? kGmaxI8 : kGmaxF64;
-        const int single = is_i8(o.form) ? kTriMaxI8 : 0;
-        int s2;
-        band_round(o.force_S, gmax, single, s2, band);
-        if (s2 != o.force_S)
-            return MD_EINVAL_OPT;
-        S = o.force_S;
-        kc = chunk_depth(S, digit_max(o.form, beta), n, is_i8(o.form) ? ((int64_t)1 << 31) : ((int64_t)1 << 53),
-                         is_i8(o.form) ? kKcI8 : kKcF64);
-        if (kc <= 0)
-            return MD_ERANGE;
-    } else {
-        if ((e = hipMemcpyAsync(spans, stats, sizeof(spans), hipMemcpyDeviceToHost, st)) != hipSuccess)
-            return hip_fail(e);
-        if ((e = hipStreamSynchronize(st)) != hipSuccess)
-            return hip_fail(e);
-        G_span = spans[0] + spans[1] + 2;
-        G = G_span;
-        if (use_rho) {
-            uint64_t minP;
-            memcpy(&minP, spans + 2, sizeof(minP));
-            G_rho = rho_exponent(minP, n);
-            if (G_rho >= 0 && G_rho < G)
-                G = G_rho;
-        }
-        const int rc = choose(o.form, n, T, G, beta, S, kc, band);
+    Choice ch;
+    {
+        const int rc = choose_slices(o, m, n, T, stats, st, ch);
         if (rc)
             return rc;
     }
+    const int beta = ch.beta, S = ch.S, band = ch.band;
+    const int64_t kc = ch.kc;
     const int kcg = is_i8(o.form) ? kKcI8 : kKcF64;
     const int64_t nkc = (n + kcg - 1) / kcg;
     const int ncol = fold_columns(beta, S, nkc * kcg);
@@ -928,25 +902,8 @@ int md_dot_ex(int m, int64_t batch, int64_t n, const double* X, int64_t ldx, int
     if (o.ev_gemm_end && (e = hipEventRecord((hipEvent_t)o.ev_gemm_end, st)) != hipSuccess)
         return hip_fail(e);
 
-    if (o.info) {
-        md_info* in = o.info;
-        in->S = S;
-        in->beta = beta;
-        in->kc = (int)std::min<int64_t>(kc, INT_MAX);
-        in->band = band;
-        in->span_A = spans[0];
-        in->span_B = spans[1];
-        in->G = G;
-        in->G_span = G_span;
-        in->G_rho = G_rho;
-        in->target_bits = T;
-        if (!o.validate)
-            in->input_flags = 0;
-        const double lb = o.form == MD_FORM_INT8_BAL
-                              ? (double)(G + 2 - 8 * S) + __builtin_log2((double)S + 3.0)
-                              : (double)(G - beta * S) + __builtin_log2((double)S + 2.0);
-        in->log2_bound = o.force_S > 0 ? 0.0 : __builtin_log2(__builtin_exp2(lb) + __builtin_exp2(-53.0 * m + 0.1));
-    }
+    if (o.info)
+        fill_info(o.info, ch, T, o.validate != 0);
     return MD_OK;
 }
 
@@ -1023,7 +980,7 @@ int md_exponents(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, 
         const Operand op{A, 1, lda, 1, M, K};
         if ((e = launch_exp_init(hi, lo, M, stats, st)) != hipSuccess) return hip_fail(e);
         if (K > 0 && (e = launch_exp_partial(op, hi, lo, st)) != hipSuccess) return hip_fail(e);
-        if ((e = launch_exp_final(hi, lo, M, E, stats, nullptr, 0, st)) != hipSuccess) return hip_fail(e);
+        if ((e = launch_exp_final(hi, lo, M, E, stats, nullptr, nullptr, 0, st)) != hipSuccess) return hip_fail(e);
         q = lo + round_up(M + 64, 64);
     }
     if (doF) {
@@ -1031,7 +988,7 @@ int md_exponents(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, 
         const Operand op{B, 1, 1, ldb, N, K};
         if ((e = launch_exp_init(hi, lo, N, stats, st)) != hipSuccess) return hip_fail(e);
         if (K > 0 && (e = launch_exp_partial(op, hi, lo, st)) != hipSuccess) return hip_fail(e);
-        if ((e = launch_exp_final(hi, lo, N, F, stats + 1, nullptr, 0, st)) != hipSuccess) return hip_fail(e);
+        if ((e = launch_exp_final(hi, lo, N, F, stats + 1, nullptr, nullptr, 0, st)) != hipSuccess) return hip_fail(e);
     }
     return MD_OK;
 }

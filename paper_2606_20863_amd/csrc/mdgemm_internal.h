@@ -86,18 +86,31 @@ hipError_t ensure_dynamic_lds(const void* kernel, size_t bytes);
 hipError_t launch_fill_zero(double* C, int m, int64_t M, int64_t N, int64_t ldc, int64_t psc,
                             hipStream_t st);
 
-// stats[0..1]: span maxima of A and B (reset by launch_exp_init)
+// Statistics of a call (int32 words, reset by launch_exp_init with stats):
+// [0], [1] the span maxima of A and B; [2..3] the smallest magnitude
+// product (uint64, starts at UINT64_MAX); [4], [5] the largest and
+// smallest shared exponent of A's rows with a nonzero leading word, [6],
+// [7] those of B's columns.
+constexpr int kStatWords = 8;
 hipError_t launch_exp_init(int32_t* hi, int32_t* lo, int64_t R, int32_t* stats, hipStream_t st);
 hipError_t launch_exp_partial(const Operand& op, int32_t* hi, int32_t* lo, hipStream_t st);
 // E[r] = shared exponent + eoff (2 for the balanced INT8 digits, else 0);
-// dbgE gets the shared exponent itself
+// dbgE gets the shared exponent itself; ext (optional) the largest and
+// smallest shared exponent of the rows with a nonzero leading word
 hipError_t launch_exp_final(const int32_t* hi, const int32_t* lo, int64_t R, int32_t* E,
-                            int32_t* span_max, int32_t* dbgE, int eoff, hipStream_t st);
+                            int32_t* span_max, int32_t* ext, int32_t* dbgE, int eoff, hipStream_t st);
+// Certificate of a call run on a slice-count hint: from stats (complete on
+// the stream), writes an md_cert record to cert (device).  beta, S, band:
+// the parameters used; T the target, m the words, K the depth.
+hipError_t launch_cert(const int32_t* stats, int form, int64_t K, int T, int m, int beta, int S,
+                       void* cert, hipStream_t st);
 
 // E[r] = Ein[r] + eoff where Ein[r] is at least the shared exponent (E[r] -
-// eoff) and at most 1100; else E[r] is kept and *flags |= 8
-hipError_t launch_exp_set(const int32_t* Ein, int64_t R, int eoff, int32_t* E, int32_t* flags,
-                          hipStream_t st);
+// eoff; -1100 for a row whose leading words are all zero, hi[r] = INT_MIN
+// from the exponent pass) and at most 1100; else E[r] is kept and
+// *flags |= 8
+hipError_t launch_exp_set(const int32_t* Ein, const int32_t* hi, int64_t R, int eoff, int32_t* E,
+                          int32_t* flags, hipStream_t st);
 
 // INT8 digits: 7-bit sign-magnitude, or balanced 8-bit (E then holds the
 // shared exponent + 2)

@@ -86,6 +86,8 @@ __global__ void k_exp_init(int32_t* hi, int32_t* lo, int64_t R, int32_t* stats)
         stats[r] = 0;
     if (r == 0 && stats)
         *reinterpret_cast<unsigned long long*>(stats + 2) = ~0ull;
+    if (r < 4 && stats)   // largest and smallest shared exponents of A, then B
+        stats[4 + r] = (r & 1) ? INT_MAX : INT_MIN;
 }
 
 // Block: 16 rows x `depth` (256, more only where the grid's second
@@ -142,20 +144,35 @@ __global__ __launch_bounds__(256) void k_exp_partial(Operand op, int32_t* hi, in
 }
 
 // E[r] = the shared exponent plus eoff (the digit grid's start); the debug
-// dump and the spans take the shared exponent itself.
+// dump and the spans take the shared exponent itself.  ext (optional):
+// ext[0] and ext[1] take the largest and smallest shared exponent of the
+// rows with a nonzero leading word (wavefront-reduced, one atomic pair per
+// wave).
 __global__ void k_exp_final(const int32_t* hi, const int32_t* lo, int64_t R, int32_t* E,
-                            int32_t* span_max, int32_t* dbgE, int eoff)
+                            int32_t* span_max, int32_t* ext, int32_t* dbgE, int eoff)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= R)
-        return;
-    const int h = hi[r];
+    const int h = r < R ? hi[r] : INT_MIN;
     const int e = h == INT_MIN ? 0 : h;
-    const int span = h == INT_MIN ? 0 : h - lo[r];
-    E[r] = e + eoff;
-    if (dbgE)
-        dbgE[r] = e;
-    atomicMax(span_max, span);
+    int span = h == INT_MIN ? 0 : h - lo[r];
+    int emax = h, emin = h == INT_MIN ? INT_MAX : h;
+    if (r < R) {
+        E[r] = e + eoff;
+        if (dbgE)
+            dbgE[r] = e;
+    }
+    for (int o = 1; o < 64; o <<= 1) {
+        span = max(span, __shfl_xor(span, o));
+        emax = max(emax, __shfl_xor(emax, o));
+        emin = min(emin, __shfl_xor(emin, o));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(span_max, span);
+        if (ext && emax != INT_MIN) {
+            atomicMax(ext, emax);
+            atomicMin(ext + 1, emin);
+        }
+    }
 }
 
 // Input preconditions of one entry (flags: 1 a word not finite, 2 not
@@ -533,37 +550,42 @@ hipError_t launch_exp_partial(const Operand& op, int32_t* hi, int32_t* lo, hipSt
 }
 
 hipError_t launch_exp_final(const int32_t* hi, const int32_t* lo, int64_t R, int32_t* E,
-                            int32_t* span_max, int32_t* dbgE, int eoff, hipStream_t st)
+                            int32_t* span_max, int32_t* ext, int32_t* dbgE, int eoff, hipStream_t st)
 {
     const int64_t blocks = std::max<int64_t>((R + 255) / 256, 1);
     hipLaunchKernelGGL(k_exp_final, dim3((unsigned)blocks), dim3(256), 0, st, hi, lo, R, E,
-                       span_max, dbgE, eoff);
+                       span_max, ext, dbgE, eoff);
     return hipGetLastError();
 }
 
 // Caller-given shared exponents: E[r] (the data's own + eoff) becomes
 // Ein[r] + eoff when Ein[r] lies in [own, kExpMax]; otherwise E[r] stays and
 // bit 8 is set in *flags (a coarser grid keeps every word below 2^E; a
-// finer one would not).
+// finer one would not).  A row with no nonzero leading word (hi[r] at its
+// initial INT_MIN) splits into zero digits on every grid, so any Ein[r] in
+// [-kExpMax, kExpMax] is taken for it: E = 0 is only the all-zero
+// convention, not a bound on the grid.
 constexpr int kExpMax = 1100;
 
-__global__ void k_exp_set(const int32_t* Ein, int64_t R, int eoff, int32_t* E, int32_t* flags)
+__global__ void k_exp_set(const int32_t* Ein, const int32_t* hi, int64_t R, int eoff, int32_t* E,
+                          int32_t* flags)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= R)
         return;
     const int own = E[r] - eoff, want = Ein[r];
-    if (want >= own && want <= kExpMax)
+    const int lowest = hi[r] == INT_MIN ? -kExpMax : own;
+    if (want >= lowest && want <= kExpMax)
         E[r] = want + eoff;
     else
         atomicOr(flags, 8);
 }
 
-hipError_t launch_exp_set(const int32_t* Ein, int64_t R, int eoff, int32_t* E, int32_t* flags,
-                          hipStream_t st)
+hipError_t launch_exp_set(const int32_t* Ein, const int32_t* hi, int64_t R, int eoff, int32_t* E,
+                          int32_t* flags, hipStream_t st)
 {
     const int64_t blocks = std::max<int64_t>((R + 255) / 256, 1);
-    hipLaunchKernelGGL(k_exp_set, dim3((unsigned)blocks), dim3(256), 0, st, Ein, R, eoff, E, flags);
+    hipLaunchKernelGGL(k_exp_set, dim3((unsigned)blocks), dim3(256), 0, st, Ein, hi, R, eoff, E, flags);
     return hipGetLastError();
 }
 

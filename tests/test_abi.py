@@ -269,7 +269,7 @@ def test_struct_layouts_match_the_header(tmp_path):
     """The binding's ctypes structures against the header compiled by gcc:
     size and every field's offset."""
     import subprocess
-    structs = {"md_info": md.MDInfo, "md_debug": md.MDDebug, "md_opts": md.MDOpts}
+    structs = {"md_info": md.MDInfo, "md_debug": md.MDDebug, "md_opts": md.MDOpts, "md_cert": md.MDCert}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -286,3 +286,50 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_workspace_size_names():
+    """The scope's name md_gemm_workspace_size and the earlier
+    md_workspace_size give the same sizes."""
+    L = md.lib()
+    for form in (0, 1, 2):
+        for (M, N, K, S) in ((1, 1, 1, 1), (70, 36, 90, 27), (4096, 4096, 4096, 27), (1024, 1024, 1024, 56)):
+            a = L.md_gemm_workspace_size(form, M, N, K, S)
+            assert a == L.md_workspace_size(form, M, N, K, S) and a > 0
+
+
+def test_hint_needs_a_certificate_and_a_valid_S():
+    """A slice-count hint without a certificate record, a hint that does
+    not split into equal bands, and a sign-magnitude hint with another
+    digit width are refused before any device work."""
+    L = md.lib()
+    a, b, c = (ctypes.c_void_p(0x100000 * k) for k in (1, 2, 3))
+    cert = ctypes.c_void_p(0x900000)
+    for form, hint, beta, with_cert, rc in ((2, 27, 0, False, 7), (2, 37, 0, True, 7), (1, 20, 8, True, 7),
+                                            (0, 10, 0, True, 7), (0, 10, 25, True, 7)):
+        opts = md.MDOpts()
+        opts.form = form
+        opts.s_hint = hint
+        opts.force_beta = beta
+        if with_cert:
+            opts.cert = cert
+        assert L.md_gemm_ex(2, 0, 0, 4, 4, 4, a, 4, 16, b, 4, 16, c, 4, 16, ctypes.byref(opts), None) == rc
+        assert L.md_dot_ex(2, 4, 4, a, 4, 16, b, 4, 16, c, 4, ctypes.byref(opts), None) == rc
+
+
+def test_binding_refuses_host_buffers():
+    """The binding checks a caller's workspace and certificate buffers
+    (contiguous, on the operands' device) before calling the library, so a
+    host pointer never reaches a kernel.  Without a GPU the operands
+    themselves are host tensors: the check on them comes first."""
+    import torch
+    A = torch.zeros((2, 4, 4), dtype=torch.float64)
+    with pytest.raises(ValueError):
+        md.gemm_ex(A, A, workspace=torch.zeros(1 << 20, dtype=torch.uint8))
+    with pytest.raises(ValueError):
+        md._device_buffer(torch.zeros(64, dtype=torch.uint8), "workspace", torch.device("cuda", 0))
+    with pytest.raises(ValueError):
+        md._device_buffer(torch.zeros((8, 8), dtype=torch.uint8).t(), "cert", torch.device("cpu"))
+    opts = md.MDOpts()
+    with pytest.raises(ValueError):
+        md._slice_opts(opts, torch.device("cuda", 0), 0, 0, 27, None, None)

@@ -4,7 +4,8 @@ The loss is sum(W * C) with C = A B, so the exact gradients are
 dA* = W B^T and dB* = A^T W (bilinear).  Checks:
 
 * small shapes: both gradients bit-exact against the oracle's method layer
-  on (W, B^T) and (A^T, W) with the parameters its own rule picks;
+  on (W, B^T) and (A^T, W) at the library's parameters (checked against
+  the budget);
 * double-double 2048^3 (FP64 form): 64 sampled entries of dA and of dB
   within 2^-100 of (|W||B^T|) and (|A^T||W|) of the exact gradient, and
   against quad-double central differences with step 2^-40 (the perturbed
@@ -119,31 +120,41 @@ def test_dd2048_forward_adjoint_fp64():
     ea = grad_errors(W, tr(B), dA, ia, ka)
     eb = grad_errors(tr(A), W, dB, kb, jb)
     assert np.max(ea) <= -100 and np.max(eb) <= -100
-    # quad-double central differences, step 2^-40
+    # quad-double central differences, step 2^-40, on all 64 sampled
+    # entries of dA and of dB.  A perturbed row of A changes one row of C
+    # (its own exponent, its own products), so the 128 perturbed rows go
+    # through one quad-double product; likewise the perturbed columns of B.
     h = Fraction(1, 1 << 40)
-    Bq, Aq = dev(as_qd(B)), dev(as_qd(A))
-    Wv = lambda i, j: ox.entry_value(W[:, i, j])
-    _, abs_a, _ = coracle.exact_entries(W, tr(B), ia[:16], ka[:16])
-    for e, (i, k) in enumerate(zip(ia[:16], ka[:16])):
-        rows = []
-        for sgn in (1, -1):
-            row = as_qd(A[:, i:i + 1, :])
-            row[:, 0, k] = ox.renorm_rn(ox.entry_value(A[:, i, k]) + sgn * h, 4)
-            rows.append(host(md.gemm_ex(dev(row), Bq, form="fp64")[0]))
-        Lp = sum(Wv(i, j) * ox.entry_value(rows[0][:, 0, j]) for j in range(N))
-        Lm = sum(Wv(i, j) * ox.entry_value(rows[1][:, 0, j]) for j in range(N))
+    Wv = [[None] * N for _ in range(M)]
+
+    def w(i, j):
+        if Wv[i][j] is None:
+            Wv[i][j] = ox.entry_value(W[:, i, j])
+        return Wv[i][j]
+
+    rows = np.zeros((4, 128, K))
+    for e, (i, k) in enumerate(zip(ia, ka)):
+        for q, sgn in enumerate((1, -1)):
+            rows[:2, 2 * e + q] = A[:, i]
+            rows[:, 2 * e + q, k] = ox.renorm_rn(ox.entry_value(A[:, i, k]) + sgn * h, 4)
+    Cr = host(md.gemm_ex(dev(rows), dev(as_qd(B)), form="fp64")[0])
+    _, abs_a, _ = coracle.exact_entries(W, tr(B), ia, ka)
+    for e, (i, k) in enumerate(zip(ia, ka)):
+        Lp = sum(w(i, j) * ox.entry_value(Cr[:, 2 * e, j]) for j in range(N))
+        Lm = sum(w(i, j) * ox.entry_value(Cr[:, 2 * e + 1, j]) for j in range(N))
         fd = (Lp - Lm) / (2 * h)
         diff = abs(fd - ox.entry_value(dA[:, i, k]))
         assert diff <= Fraction(abs_a[e]) * Fraction(1, 1 << 99), (i, k)
-    _, abs_b, _ = coracle.exact_entries(tr(A), W, kb[:16], jb[:16])
-    for e, (k, j) in enumerate(zip(kb[:16], jb[:16])):
-        cols = []
-        for sgn in (1, -1):
-            col = as_qd(B[:, :, j:j + 1])
-            col[:, k, 0] = ox.renorm_rn(ox.entry_value(B[:, k, j]) + sgn * h, 4)
-            cols.append(host(md.gemm_ex(Aq, dev(col), form="fp64")[0]))
-        Lp = sum(Wv(i, j) * ox.entry_value(cols[0][:, i, 0]) for i in range(M))
-        Lm = sum(Wv(i, j) * ox.entry_value(cols[1][:, i, 0]) for i in range(M))
+    cols = np.zeros((4, K, 128))
+    for e, (k, j) in enumerate(zip(kb, jb)):
+        for q, sgn in enumerate((1, -1)):
+            cols[:2, :, 2 * e + q] = B[:, :, j]
+            cols[:, k, 2 * e + q] = ox.renorm_rn(ox.entry_value(B[:, k, j]) + sgn * h, 4)
+    Cc = host(md.gemm_ex(dev(as_qd(A)), dev(cols), form="fp64")[0])
+    _, abs_b, _ = coracle.exact_entries(tr(A), W, kb, jb)
+    for e, (k, j) in enumerate(zip(kb, jb)):
+        Lp = sum(w(i, j) * ox.entry_value(Cc[:, i, 2 * e]) for i in range(M))
+        Lm = sum(w(i, j) * ox.entry_value(Cc[:, i, 2 * e + 1]) for i in range(M))
         fd = (Lp - Lm) / (2 * h)
         diff = abs(fd - ox.entry_value(dB[:, k, j]))
         assert diff <= Fraction(abs_b[e]) * Fraction(1, 1 << 99), (k, j)

@@ -21,12 +21,12 @@ def host(t):
 
 @pytest.mark.parametrize("form", ["int8", "int8bal", "fp64"])
 def test_caller_workspace(form):
-    """With a workspace of md_workspace_size bytes the library allocates
+    """With a workspace of md_gemm_workspace_size bytes the library allocates
     nothing and gives the same words; a workspace too small is MD_ENOMEM."""
     A, B = mdinputs.workload("qd1024", M=40, N=56, K=130)
     ref, info = md.gemm_ex(dev(A), dev(B), form=form)
     ref = host(ref)
-    nbytes = md.lib().md_workspace_size(md._FORMS[form], 40, 56, 130, info["S"])
+    nbytes = md.lib().md_gemm_workspace_size(md._FORMS[form], 40, 56, 130, info["S"])
     ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     C, info2 = md.gemm_ex(dev(A), dev(B), form=form, workspace=ws)
     np.testing.assert_array_equal(host(C), ref)
@@ -39,12 +39,12 @@ def test_caller_workspace(form):
 
 def test_workspace_covers_the_global_fold():
     """Hexa-double FP64: the [S][M][N] diagonal-sum buffer is part of
-    md_workspace_size."""
+    md_gemm_workspace_size."""
     r = np.random.Generator(np.random.PCG64(9))
     A = mdinputs.mdouble(r, 16, (24, 40))
     B = mdinputs.mdouble(r, 16, (40, 20))
     ref, info = md.gemm_ex(dev(A), dev(B), form="fp64")
-    nbytes = md.lib().md_workspace_size(0, 24, 20, 40, info["S"])
+    nbytes = md.lib().md_gemm_workspace_size(0, 24, 20, 40, info["S"])
     assert nbytes >= info["S"] * 24 * 20 * 8
     ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     C, _ = md.gemm_ex(dev(A), dev(B), form="fp64", workspace=ws)
@@ -53,11 +53,11 @@ def test_workspace_covers_the_global_fold():
 
 def test_workspace_covers_the_int8_sum_buffer():
     """Octo-double balanced INT8 (S > 32, bands): the diagonal-sum buffer of
-    the banded kernels is part of md_workspace_size."""
+    the banded kernels is part of md_gemm_workspace_size."""
     A, B = mdinputs.workload("od1024", M=70, N=36, K=90)
     ref, info = md.gemm_ex(dev(A), dev(B), form="int8bal")
     assert info["S"] > 32
-    nbytes = md.lib().md_workspace_size(md._FORMS["int8bal"], 70, 36, 90, info["S"])
+    nbytes = md.lib().md_gemm_workspace_size(md._FORMS["int8bal"], 70, 36, 90, info["S"])
     ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     C, _ = md.gemm_ex(dev(A), dev(B), form="int8bal", workspace=ws)
     np.testing.assert_array_equal(host(C), host(ref))

@@ -198,26 +198,6 @@ def test_word_counts_one_and_sixteen_rule(m):
     assert max(ox.error_report(C, num, anum, L).values()) <= -ox.TARGET_BITS[m]
 
 
-def test_qd4096_benchmark_workload_sampled():
-    """The quad-double 4096^3 benchmark product in the launch configuration
-    the benchmark times: a 24 x 24 grid of entries bit-exact against the C
-    oracle's method layer, within 2^-200 of the exact product."""
-    A, B = mdinputs.workload("qd4096")
-    C, info = md.gemm_ex(dev(A), dev(B), form="int8bal")
-    C = host(C)
-    assert info["S"] == 27 and info["kc"] >= 4096
-    rows = np.linspace(0, 4095, 24).astype(np.int64)
-    cols = np.linspace(0, 4095, 24).astype(np.int64)
-    _, _, _, Cref = coracle.method_entries(A, B, 8, info["S"], rows, cols, balanced=True)
-    np.testing.assert_array_equal(C[:, rows][:, :, cols], Cref)
-    ii, jj = np.meshgrid(rows, cols, indexing="ij")
-    ii, jj = ii.ravel(), jj.ravel()
-    Cq = np.ascontiguousarray(np.transpose(C[:, ii, jj], (1, 0)))
-    _, absab, err = coracle.exact_entries(A, B, ii, jj, Cq)
-    rel = np.abs(err) / absab
-    assert np.all(rel <= 2.0 ** -200), np.log2(rel.max())
-
-
 @pytest.mark.parametrize("m", [1, 2, 4, 8, 16])
 def test_dot_rule_bitexact(m):
     r = rng(900 + m)

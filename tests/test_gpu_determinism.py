@@ -36,7 +36,7 @@ def test_repeated_products_are_bit_identical(form, m):
     with torch.cuda.stream(side):
         runs.append(md.gemm_ex(A, B, form=form, stream=side)[0])
     torch.cuda.current_stream().wait_stream(side)
-    ws = torch.empty(md.lib().md_workspace_size(md._FORMS[form], M, N, K, info["S"]), dtype=torch.uint8,
+    ws = torch.empty(md.lib().md_gemm_workspace_size(md._FORMS[form], M, N, K, info["S"]), dtype=torch.uint8,
                      device="cuda")
     runs.append(md.gemm_ex(A, B, form=form, workspace=ws)[0])
     torch.cuda.synchronize()

@@ -414,3 +414,43 @@ def test_exponents_of_a_very_deep_product():
     torch.cuda.synchronize()
     assert list(E.cpu().numpy()) == ox.row_exponents(A[0])[0]
     assert list(F.cpu().numpy()) == ox.row_exponents(B[0].T)[0]
+
+
+@pytest.mark.parametrize("form,beta,S", [("int8bal", 8, 14), ("int8", 7, 16), ("fp64", 20, 6)])
+def test_depth_split_with_rows_zero_in_one_block(form, beta, S):
+    """A row of A and a column of B that are zero in one depth block only,
+    with negative whole-depth exponents (leading words below 1/2): the
+    block's integers on the whole-depth grid are zero there, the call takes
+    the given exponents (no flag), and the blocks sum and round to the
+    whole product's output."""
+    m, M, N, K, k0 = 4, 12, 10, 90, 40
+    r = np.random.Generator(np.random.PCG64(515))
+    A = mdinputs.mdouble(r, m, (M, K), ("log2uniform", 8.0))
+    B = mdinputs.mdouble(r, m, (K, N), ("log2uniform", 8.0))
+    A[:, 2, :] *= 2.0 ** -20            # whole-depth exponents well below 0
+    B[:, :, 7] *= 2.0 ** -20
+    A[:, 2, :k0] = 0.0                  # zero in the first block only
+    B[:, k0:, 7] = 0.0                  # zero in the second block only
+    Eo, _ = ox.row_exponents(A[0])
+    Fo, _ = ox.row_exponents(B[0].T)
+    assert Eo[2] < 0 and Fo[7] < 0
+    Ad, Bd = dev(A), dev(B)
+    E, F = md.exponents(Ad, Bd)
+    nlimb = md.fixed_limbs(beta, S, K)
+    flags = torch.zeros(1, dtype=torch.int32, device="cuda")
+    X1, sc, _ = md.gemm_fixed(Ad[:, :, :k0], Bd[:, :k0, :], E, F, S=S, beta=beta, form=form, nlimb=nlimb,
+                              flags=flags)
+    X2, sc2, _ = md.gemm_fixed(Ad[:, :, k0:], Bd[:, k0:, :], E, F, S=S, beta=beta, form=form, nlimb=nlimb,
+                               flags=flags)
+    Xs = md.fixed_add(X1, X2)
+    C = md.fixed_round(Xs, sc, m)
+    Cg, _ = md.gemm_ex(Ad, Bd, form=form, force_S=S, force_beta=beta)
+    torch.cuda.synchronize()
+    assert int(flags.item()) == 0
+    np.testing.assert_array_equal(sc.cpu().numpy(), sc2.cpu().numpy())
+    bal = form == "int8bal"
+    for Xb, sl in ((X1, slice(0, k0)), (X2, slice(k0, K))):
+        Xo, so = ox.fixed_product(A[:, :, sl], B[:, sl, :], beta, S, E=Eo, F=Fo, balanced=bal)
+        np.testing.assert_array_equal(Xb.cpu().numpy(), limbs_of(Xo, nlimb))
+        np.testing.assert_array_equal(sc.cpu().numpy(), so.astype(np.int32))
+    np.testing.assert_array_equal(C.cpu().numpy(), Cg.cpu().numpy())

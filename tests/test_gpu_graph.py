@@ -31,7 +31,7 @@ def dev(x):
 
 
 def workspace(form, M, N, K, S):
-    n = md.lib().md_workspace_size(md._FORMS[form], M, N, K, S)
+    n = md.lib().md_gemm_workspace_size(md._FORMS[form], M, N, K, S)
     return torch.empty(n, dtype=torch.uint8, device="cuda")
 
 

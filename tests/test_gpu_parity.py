@@ -5,6 +5,8 @@ being unique) the output words, against the oracle's method layer on the
 same seeded inputs.  Within bound: the output against the exact product,
 2^-T of (|A||B|)_ij for every checked entry, T = 50 m.
 """
+import functools
+
 import numpy as np
 import pytest
 import torch
@@ -278,19 +280,29 @@ def test_qd1024_workload_sampled(form):
     assert np.all(rel <= 2.0 ** -200), np.log2(rel.max())
 
 
-@pytest.mark.parametrize("form", ["int8", "fp64"])
-def test_qd4096_benchmark_workload_sampled(form):
+@functools.lru_cache(maxsize=1)
+def qd4096():
+    return mdinputs.workload("qd4096")
+
+
+GRID64 = np.linspace(0, 4095, 64).astype(np.int64)
+
+
+@pytest.mark.parametrize("form", ["int8bal", "int8", "fp64"])
+def test_qd4096_benchmark_workload_grid64(form):
     """The quad-double 4096^3 benchmark product in the launch configuration
-    the benchmark times for these two forms: a 16 x 16 grid of entries
-    bit-exact against the C oracle's method layer and within 2^-200 of the
-    exact product."""
-    A, B = mdinputs.workload("qd4096")
+    the benchmark times, in its three forms: a 64 x 64 grid of entries
+    (4,096, every 65th row and column from 0 to 4095) bit-exact against the
+    C oracle's method layer at the library's S, within 2^-200 of the exact
+    product, and within the certified bound; S within the budget."""
+    A, B = qd4096()
     C, info = md.gemm_ex(dev(A), dev(B), form=form)
     C = host(C)
-    assert info["S"] == (30 if form == "int8" else 10)
-    rows = np.linspace(0, 4095, 16).astype(np.int64)
-    cols = np.linspace(0, 4095, 16).astype(np.int64)
-    _, _, _, Cref = coracle.method_entries(A, B, info["beta"], info["S"], rows, cols)
+    assert info["S"] == {"int8bal": 27, "int8": 30, "fp64": 10}[form]
+    rulecheck.check_info(info, form, 4096, 200, info["G"])
+    rows = cols = GRID64
+    _, _, _, Cref = coracle.method_entries(A, B, info["beta"], info["S"], rows, cols,
+                                           balanced=form == "int8bal")
     np.testing.assert_array_equal(C[:, rows][:, :, cols], Cref)
     ii, jj = np.meshgrid(rows, cols, indexing="ij")
     ii, jj = ii.ravel(), jj.ravel()
@@ -298,3 +310,4 @@ def test_qd4096_benchmark_workload_sampled(form):
     _, absab, err = coracle.exact_entries(A, B, ii, jj, Cq)
     rel = np.abs(err) / absab
     assert np.all(rel <= 2.0 ** -200), np.log2(rel.max())
+    assert np.log2(rel.max()) <= info["log2_bound"]

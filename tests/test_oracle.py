@@ -517,3 +517,37 @@ def test_log2_fraction_pinned():
     # a planted mistake of one bit in the scaling would be seen
     x = Fraction(3, 1 << 2000)
     assert abs(ox.log2_fraction(x) - (math.log2(3) - 2000)) < 1e-12
+
+
+@pytest.mark.parametrize("balanced", [False, True])
+def test_depth_split_with_rows_zero_in_one_block(balanced):
+    """A row of A zero in the first depth block and a column of B zero in
+    the second, both with negative whole-depth exponents: on the whole
+    depth's grid the blocks' integers are zero there and still add up to
+    the whole product's, which rounds to the method's output."""
+    m, M, N, K, k0 = 4, 5, 4, 30, 12
+    r = np.random.Generator(np.random.PCG64(516))
+    A = mdinputs.mdouble(r, m, (M, K), ("log2uniform", 8.0))
+    B = mdinputs.mdouble(r, m, (K, N), ("log2uniform", 8.0))
+    A[:, 1, :] *= 2.0 ** -20
+    B[:, :, 3] *= 2.0 ** -20
+    A[:, 1, :k0] = 0.0
+    B[:, k0:, 3] = 0.0
+    beta, S = (8, 14) if balanced else (7, 16)
+    E, _ = ox.row_exponents(A[0])
+    F, _ = ox.row_exponents(B[0].T)
+    assert E[1] < 0 and F[3] < 0
+    # the block's own exponents differ: all-zero (0 by convention)
+    Eb, _ = ox.row_exponents(A[0, :, :k0])
+    assert Eb[1] == 0 != E[1]
+    X, sc = ox.fixed_product(A, B, beta, S, balanced=balanced)
+    X1, s1 = ox.fixed_product(A[:, :, :k0], B[:, :k0, :], beta, S, E, F, balanced)
+    X2, s2 = ox.fixed_product(A[:, :, k0:], B[:, k0:, :], beta, S, E, F, balanced)
+    assert all(X1[1, j] == 0 for j in range(N)) and all(X2[i, 3] == 0 for i in range(M))
+    assert np.array_equal(s1, sc) and np.array_equal(s2, sc)
+    assert all(X1[i, j] + X2[i, j] == X[i, j] for i in range(M) for j in range(N))
+    ref = ox.method_product(A, B, beta, S, balanced=balanced)
+    for i in range(M):
+        for j in range(N):
+            x = Fraction(X[i, j]) * Fraction(2) ** int(sc[i, j])
+            assert tuple(ox.renorm_rn(x, m)) == tuple(ref["C"][:, i, j])
