@@ -196,10 +196,11 @@ int md_gemm(int m, int64_t M, int64_t N, int64_t K, const double *A, const doubl
  *   B[j*ldb + k] (transB = 1), word w at + w*plane_stride_B.
  *   C: element (i, j) word w at C[w*plane_stride_C + i*ldc + j].
  *   opts may be NULL (FP64 form, MD_S_RHO rule, T = 50 m).
- * Graph capture: with opts->force_S set, opts->validate and opts->dbg
- * clear and a workspace of at least md_gemm_workspace_size bytes, the call only
- * launches kernels on `stream` (no allocation, copy, memset or
- * synchronisation), so it can be captured into a HIP graph and replayed.
+ * Graph capture: with opts->force_S (or opts->s_hint and opts->cert) set,
+ * opts->validate and opts->dbg clear and a workspace of at least
+ * md_gemm_workspace_size bytes, the call only launches kernels on `stream`
+ * (no allocation, copy, memset or synchronisation), so it can be captured
+ * into a HIP graph and replayed.
  * Replays reuse the workspace: replays (or calls) that share one must not
  * run concurrently.
  */
@@ -207,6 +208,30 @@ int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, c
                int64_t lda, int64_t plane_stride_A, const double *B, int64_t ldb,
                int64_t plane_stride_B, double *C, int64_t ldc, int64_t plane_stride_C,
                const md_opts *opts, void *stream);
+
+/*
+ * md_gemm_ex for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * same arguments and results as md_gemm_ex, but its scratch is a
+ * library-owned array of MD_NOALLOC_SCRATCH_BYTES bytes in each device's
+ * global memory (held until the process ends), so the call makes no
+ * allocation or free of any kind.
+ *   opts->workspace must be NULL (MD_EINVAL_OPT otherwise).
+ *   A call whose scratch (md_gemm_workspace_size for its form and S) would
+ *   exceed the array returns MD_ENOMEM with C untouched; with the slice
+ *   rule this is known only after the exponent step has run on the stream.
+ * The array keeps the last call's contents; no step reads scratch it has
+ * not written in the same call.  All calls on one device share the array:
+ * calls that overlap in time on one device (different streams or host
+ * threads without ordering) race and give undefined results; calls on one
+ * stream are ordered.  Graph capture as md_gemm_ex (forced S or a hint),
+ * with no workspace needed.
+ */
+#define MD_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int md_gemm_ex_noalloc(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, const double *A,
+                       int64_t lda, int64_t plane_stride_A, const double *B, int64_t ldb,
+                       int64_t plane_stride_B, double *C, int64_t ldc, int64_t plane_stride_C,
+                       const md_opts *opts, void *stream);
 
 /*
  * Batched inner products of m-double vectors, the paper's experiment

@@ -115,6 +115,8 @@ def lib():
     L.md_gemm_ex.argtypes = [i32, i32, i32, i64, i64, i64, p, i64, i64, p, i64, i64, p, i64, i64,
                              ctypes.POINTER(MDOpts), p]
     L.md_gemm_ex.restype = i32
+    L.md_gemm_ex_noalloc.argtypes = L.md_gemm_ex.argtypes
+    L.md_gemm_ex_noalloc.restype = i32
     L.md_dot_ex.argtypes = [i32, i64, i64, p, i64, i64, p, i64, i64, p, i64, ctypes.POINTER(MDOpts), p]
     L.md_dot_ex.restype = i32
     L.md_dot.argtypes = [i32, i64, i64, p, p, p, p]
@@ -223,7 +225,7 @@ def _slice_opts(opts: "MDOpts", device, force_S, force_beta, s_hint, cert, works
 def gemm_ex(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None, *, transA=False,
             transB=False, form="fp64", rule="rho", target_bits=0, force_S=0, force_beta=0,
             debug=None, workspace: torch.Tensor | None = None, events=None, stream=None,
-            validate=False, s_hint=0, cert: torch.Tensor | None = None):
+            validate=False, s_hint=0, cert: torch.Tensor | None = None, noalloc=False):
     """C = op(A) op(B) in m-double arithmetic.
 
     A is (m, M, K) (or (m, K, M) with transA), B is (m, K, N) (or (m, N, K)
@@ -237,6 +239,8 @@ def gemm_ex(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None, *, 
     device writes the data's certificate into ``cert`` (``read_cert``).
     ``workspace``: a contiguous device buffer of at least
     ``md_gemm_workspace_size`` bytes (the call then allocates nothing).
+    ``noalloc``: call md_gemm_ex_noalloc (the library's own fixed scratch
+    array, no workspace; C must then be given to allocate nothing at all).
     """
     _check_planes(A, "A")
     _check_planes(B, "B")
@@ -283,9 +287,12 @@ def gemm_ex(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None, *, 
         opts.dbg = ctypes.pointer(dbg)
     lda = A.shape[2]
     ldb = B.shape[2]
-    rc = lib().md_gemm_ex(m, int(transA), int(transB), M, N, K, _ptr(A), lda, A.shape[1] * A.shape[2],
-                          _ptr(B), ldb, B.shape[1] * B.shape[2], _ptr(C), N, M * N,
-                          ctypes.byref(opts), _stream_handle(stream))
+    if noalloc and workspace is not None:
+        raise ValueError("md_gemm_ex_noalloc takes no workspace")
+    fn = lib().md_gemm_ex_noalloc if noalloc else lib().md_gemm_ex
+    rc = fn(m, int(transA), int(transB), M, N, K, _ptr(A), lda, A.shape[1] * A.shape[2],
+            _ptr(B), ldb, B.shape[1] * B.shape[2], _ptr(C), N, M * N,
+            ctypes.byref(opts), _stream_handle(stream))
     _check(rc, info)
     return C, info.as_dict()
 

@@ -164,6 +164,35 @@ std::mutex g_pool_mu;
 hipMemPool_t g_pool[64];
 bool g_pool_init[64];
 
+// Scratch of md_gemm_ex_noalloc: one array in every device's global memory,
+// held until the process ends.  Host code takes its device address from
+// hipGetSymbolAddress (once per device, with that device current) and
+// passes that address on; the array's name itself is only a host-side
+// stand-in.
+static __device__ __align__(256) char noalloc_scratch[MD_NOALLOC_SCRATCH_BYTES];
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[64];
+
+int noalloc_scratch_address(void** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_fail(e);
+    if (dev < 0 || dev >= 64)
+        return MD_EINVAL_OPT;
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch));
+        if (e != hipSuccess)
+            return hip_fail(e);
+        g_noalloc_ptr[dev] = p;
+    }
+    *out = g_noalloc_ptr[dev];
+    return MD_OK;
+}
+
 int get_pool(hipMemPool_t& pool)
 {
     int dev = 0;
@@ -465,7 +494,7 @@ int gemm_impl(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, co
               int64_t lda, int64_t plane_stride_A, const double* B, int64_t ldb,
               int64_t plane_stride_B, double* C, int64_t ldc, int64_t plane_stride_C,
               const md_opts* opts, void* stream, const int32_t* E_in, const int32_t* F_in,
-              int32_t* exp_flags, const FixedOut* fx)
+              int32_t* exp_flags, const FixedOut* fx, bool noalloc = false)
 {
     g_last_hip = 0;
     if (m != 1 && m != 2 && m != 4 && m != 8 && m != 16)
@@ -531,7 +560,15 @@ int gemm_impl(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, co
 
     Scratch scr;
     scr.st = st;
-    if (o.workspace) {
+    if (noalloc) {
+        // md_gemm_ex_noalloc: the library's fixed array, never the pool
+        void* p = nullptr;
+        const int rc = noalloc_scratch_address(&p);
+        if (rc)
+            return rc;
+        scr.user = (char*)p;
+        scr.user_bytes = MD_NOALLOC_SCRATCH_BYTES;
+    } else if (o.workspace) {
         scr.user = (char*)o.workspace;
         scr.user_bytes = o.workspace_bytes;
     }
@@ -720,6 +757,18 @@ int md_gemm_ex(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, c
 {
     return gemm_impl(m, transA, transB, M, N, K, A, lda, plane_stride_A, B, ldb, plane_stride_B, C, ldc,
                      plane_stride_C, opts, stream, nullptr, nullptr, nullptr, nullptr);
+}
+
+int md_gemm_ex_noalloc(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, const double* A,
+                       int64_t lda, int64_t plane_stride_A, const double* B, int64_t ldb,
+                       int64_t plane_stride_B, double* C, int64_t ldc, int64_t plane_stride_C,
+                       const md_opts* opts, void* stream)
+{
+    g_last_hip = 0;
+    if (opts && (opts->workspace || opts->workspace_bytes))
+        return MD_EINVAL_OPT;   // the scratch is the library's own array
+    return gemm_impl(m, transA, transB, M, N, K, A, lda, plane_stride_A, B, ldb, plane_stride_B, C, ldc,
+                     plane_stride_C, opts, stream, nullptr, nullptr, nullptr, nullptr, true);
 }
 
 int md_dot_ex(int m, int64_t batch, int64_t n, const double* X, int64_t ldx, int64_t plane_stride_X,

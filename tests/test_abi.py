@@ -333,3 +333,15 @@ def test_binding_refuses_host_buffers():
     opts = md.MDOpts()
     with pytest.raises(ValueError):
         md._slice_opts(opts, torch.device("cuda", 0), 0, 0, 27, None, None)
+
+
+def test_noalloc_takes_no_workspace():
+    """md_gemm_ex_noalloc refuses a caller workspace before any device
+    work (its scratch is the library's own array)."""
+    L = md.lib()
+    a, b, c = (ctypes.c_void_p(0x100000 * k) for k in (1, 2, 3))
+    opts = md.MDOpts()
+    opts.workspace = ctypes.c_void_p(0x800000)
+    opts.workspace_bytes = 1 << 20
+    assert L.md_gemm_ex_noalloc(2, 0, 0, 4, 4, 4, a, 4, 16, b, 4, 16, c, 4, 16, ctypes.byref(opts), None) == 7
+    assert L.md_gemm_ex_noalloc(3, 0, 0, 4, 4, 4, a, 4, 16, b, 4, 16, c, 4, 16, None, None) == 1
