@@ -87,21 +87,44 @@ int64_t chunk_depth(int S, int64_t dmax, int64_t K, int64_t limit, int gran)
     return std::min(kc, kfull);
 }
 
-int choose(int form, int64_t K, int T, int G, int& beta, int& S, int64_t& kc, int& band)
+// The two-band INT8 contraction takes S (a multiple of 4 in [36, 64]) when
+// its whole depth is one exactness chunk.
+bool duo_fits(int S, int64_t dmax, int64_t K)
+{
+    if (S % 4 || S < kDuoMin || S > kDuoMax)
+        return false;
+    const int64_t kfull = (std::max<int64_t>(K, 1) + kKcI8 - 1) / kKcI8 * kKcI8;
+    return chunk_depth(S, dmax, K, (int64_t)1 << 31, kKcI8) >= kfull;
+}
+
+// INT8 slices: S = the budget's Smin up to 32 (one triangle); above that
+// Smin rounded up to a multiple of 4 (at least 36) in two bands of S/2 when
+// one exactness chunk holds the depth (and duo: the caller's kernels take
+// two bands), else equal bands of at most 16.
+int choose_i8(int Smin, int64_t dmax, int64_t K, bool duo, int& S, int64_t& kc, int& band)
+{
+    const int S4 = std::max(kDuoMin, (Smin + 3) / 4 * 4);
+    if (duo && Smin > kTriMaxI8 && duo_fits(S4, dmax, K)) {
+        S = S4;
+        band = S4 / 2;
+    } else {
+        band_round(Smin, kGmaxI8, kTriMaxI8, S, band);
+    }
+    kc = chunk_depth(S, dmax, K, (int64_t)1 << 31, kKcI8);
+    return kc > 0 ? MD_OK : MD_ERANGE;
+}
+
+int choose(int form, int64_t K, int T, int G, int& beta, int& S, int64_t& kc, int& band, bool duo = true)
 {
     if (T < 1 || G < 0 || K < 0)
         return MD_EINVAL_OPT;
     if (form == MD_FORM_INT8) {
         beta = 7;
-        band_round(rule_slice_count(7, T, G), kGmaxI8, kTriMaxI8, S, band);
-        kc = chunk_depth(S, 127, K, (int64_t)1 << 31, kKcI8);
-        return kc > 0 ? MD_OK : MD_ERANGE;
+        return choose_i8(rule_slice_count(7, T, G), 127, K, duo, S, kc, band);
     }
     if (form == MD_FORM_INT8_BAL) {
         beta = 8;
-        band_round(rule_slice_count_balanced(T, G), kGmaxI8, kTriMaxI8, S, band);
-        kc = chunk_depth(S, 128, K, (int64_t)1 << 31, kKcI8);
-        return kc > 0 ? MD_OK : MD_ERANGE;
+        return choose_i8(rule_slice_count_balanced(T, G), 128, K, duo, S, kc, band);
     }
     if (form == MD_FORM_FP64) {
         bool found = false;
@@ -139,7 +162,7 @@ int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 bool needs_global_fold(int form, int band, int S, int ncol)
 {
     if (is_i8(form))
-        return !(band == S && S <= kTriMaxI8);
+        return !(band == S && S <= kTriMaxI8) && !duo_shape(S, band);
     return (size_t)4 * ncol * 256 * sizeof(int64_t) > 160 * 1024;
 }
 
@@ -309,8 +332,11 @@ struct Choice {
     double log2_bound = 0.0;
 };
 
-// Option checks of the slice parameters (before any device work).
-int check_slice_opts(const md_opts& o)
+// Option checks of the slice parameters (before any device work).  A given
+// S splits into equal bands of at most 16 diagonals, or (duo: the call may
+// use the two-band INT8 kernel) into two bands of S/2 over one exactness
+// chunk of depth K.
+int check_slice_opts(const md_opts& o, int64_t K, bool duo)
 {
     if (o.force_S < 0 || o.force_S > 512 || o.s_hint < 0 || o.s_hint > 512)
         return MD_EINVAL_OPT;
@@ -322,7 +348,7 @@ int check_slice_opts(const md_opts& o)
     // a given S must split into equal bands
     int s2, band;
     band_round(S, is_i8(o.form) ? kGmaxI8 : kGmaxF64, is_i8(o.form) ? kTriMaxI8 : 0, s2, band);
-    if (s2 != S)
+    if (s2 != S && !(duo && is_i8(o.form) && duo_fits(S, digit_max(o.form, o.form == MD_FORM_INT8 ? 7 : 8), K)))
         return MD_EINVAL_OPT;
     const int need = o.form == MD_FORM_INT8 ? 7 : o.form == MD_FORM_INT8_BAL ? 8 : 0;
     if (need)
@@ -335,7 +361,8 @@ int check_slice_opts(const md_opts& o)
 // *opts->cert after the statistics (no wait).  Otherwise the rule: one copy
 // of the statistics to the host and one synchronisation.  stats: the
 // call's statistics (kStatWords), complete in stream order.
-int choose_slices(const md_opts& o, int m, int64_t K, int T, const int32_t* stats, hipStream_t st, Choice& c)
+int choose_slices(const md_opts& o, int m, int64_t K, int T, const int32_t* stats, hipStream_t st, Choice& c,
+                  bool duo)
 {
     const int Sgiven = o.force_S > 0 ? o.force_S : o.s_hint;
     hipError_t e;
@@ -345,7 +372,9 @@ int choose_slices(const md_opts& o, int m, int64_t K, int T, const int32_t* stat
         const int single = is_i8(o.form) ? kTriMaxI8 : 0;
         int s2;
         band_round(Sgiven, gmax, single, s2, c.band);
-        if (s2 != Sgiven)
+        if (duo && is_i8(o.form) && Sgiven > kTriMaxI8 && duo_fits(Sgiven, digit_max(o.form, c.beta), K))
+            c.band = Sgiven / 2;   // two bands over the whole depth
+        else if (s2 != Sgiven)
             return MD_EINVAL_OPT;   // a given S must split into equal bands
         c.S = Sgiven;
         c.kc = chunk_depth(c.S, digit_max(o.form, c.beta), K,
@@ -375,7 +404,7 @@ int choose_slices(const md_opts& o, int m, int64_t K, int T, const int32_t* stat
         if (c.G_rho >= 0 && c.G_rho < c.G)
             c.G = c.G_rho;
     }
-    const int rc = choose(o.form, K, T, c.G, c.beta, c.S, c.kc, c.band);
+    const int rc = choose(o.form, K, T, c.G, c.beta, c.S, c.kc, c.band, duo);
     if (rc)
         return rc;
     c.log2_bound = rule_log2_bound(o.form == MD_FORM_INT8_BAL, c.G, c.beta, c.S, m);
@@ -534,7 +563,9 @@ int gemm_impl(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, co
             return MD_EALIAS;
     }
     const int T = o.target_bits > 0 ? o.target_bits : 50 * m;
-    if (check_slice_opts(o) != MD_OK)
+    // the two-band kernel writes neither the diagonal-sum dump nor integers
+    const bool duo = !fx && !(o.dbg && o.dbg->D);
+    if (check_slice_opts(o, K, duo) != MD_OK)
         return MD_EINVAL_OPT;
     if ((E_in || F_in) && (o.force_S == 0 || !exp_flags))
         return MD_EINVAL_OPT;
@@ -626,7 +657,7 @@ int gemm_impl(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, co
     }
     Choice ch;
     {
-        const int rc = choose_slices(o, m, K, T, stats, st, ch);
+        const int rc = choose_slices(o, m, K, T, stats, st, ch, duo);
         if (rc)
             return rc;
     }
@@ -810,7 +841,7 @@ int md_dot_ex(int m, int64_t batch, int64_t n, const double* X, int64_t ldx, int
             return MD_EALIAS;
     }
     const int T = o.target_bits > 0 ? o.target_bits : 50 * m;
-    if (check_slice_opts(o) != MD_OK)
+    if (check_slice_opts(o, n, false) != MD_OK)
         return MD_EINVAL_OPT;
 
     hipStream_t st = (hipStream_t)stream;
@@ -887,7 +918,7 @@ int md_dot_ex(int m, int64_t batch, int64_t n, const double* X, int64_t ldx, int
     }
     Choice ch;
     {
-        const int rc = choose_slices(o, m, n, T, stats, st, ch);
+        const int rc = choose_slices(o, m, n, T, stats, st, ch, false);
         if (rc)
             return rc;
     }

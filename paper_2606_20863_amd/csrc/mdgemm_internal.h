@@ -30,6 +30,14 @@ constexpr int kTile = 32;       // rows and columns per workgroup (2 x 2 waves)
 constexpr int kTriMaxI8 = 32;   // INT8: up to this many diagonals in one band (whole triangle)
 constexpr int kGmaxI8 = 16;     // INT8: widest band when S needs several bands
 constexpr int kGmaxF64 = 16;    // widest band of diagonals, FP64 form
+constexpr int kDuoMin = 36;     // INT8: S in [kDuoMin, kDuoMax], a multiple of 4, may run as two
+constexpr int kDuoMax = 64;     //   bands of S/2 diagonals over the whole depth (one exactness chunk)
+
+// S and band of the two-band INT8 contraction
+inline bool duo_shape(int S, int band)
+{
+    return S % 4 == 0 && S >= kDuoMin && S <= kDuoMax && 2 * band == S;
+}
 
 // element (r, k), word w of an operand: p[w * ps + r * sr + k * sk]
 struct Operand {
@@ -142,6 +150,12 @@ hipError_t launch_tri_s29_32(const GemmArgs& a, hipStream_t st);
 hipError_t launch_tri8_s1_22(const GemmArgs& a, hipStream_t st);
 hipError_t launch_tri8_s23_28(const GemmArgs& a, hipStream_t st);
 hipError_t launch_tri8_s29_32(const GemmArgs& a, hipStream_t st);
+// two-band kernels (duo_shape, one exactness chunk, no debug dump or
+// fixed-point output), by digit width and range of S
+hipError_t launch_duo_s36_48(const GemmArgs& a, hipStream_t st);
+hipError_t launch_duo_s52_64(const GemmArgs& a, hipStream_t st);
+hipError_t launch_duo8_s36_48(const GemmArgs& a, hipStream_t st);
+hipError_t launch_duo8_s52_64(const GemmArgs& a, hipStream_t st);
 // their fixed-point variants (a.fixX set, one exactness chunk)
 hipError_t launch_trifix_s1_22(const GemmArgs& a, hipStream_t st);
 hipError_t launch_trifix_s23_32(const GemmArgs& a, hipStream_t st);

@@ -282,6 +282,16 @@ hipError_t launch_gemm_i8(const GemmArgs& a, hipStream_t st)
             return launch_tri_s23_28(a, st);
         return launch_tri_s29_32(a, st);
     }
+    // two bands over the whole depth, folded in registers
+    if (duo_shape(a.S, a.band)) {
+        if (a.kcc < a.nkc || a.dbgD || a.fixX || a.gD)
+            return hipErrorInvalidValue;
+        if (a.beta == 8)
+            return a.S <= 48 ? launch_duo8_s36_48(a, st) : launch_duo8_s52_64(a, st);
+        if (a.beta != 7)
+            return hipErrorInvalidValue;
+        return a.S <= 48 ? launch_duo_s36_48(a, st) : launch_duo_s52_64(a, st);
+    }
     // bands: the diagonal sums go through a.gD
     if (!a.gD)
         return hipErrorInvalidValue;

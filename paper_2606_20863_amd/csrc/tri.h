@@ -37,11 +37,13 @@ constexpr int tri_issue_a(int S, int R, int LA, int q)
     return q < S ? -1 : 0;   // the next chunk's A cannot precede this chunk
 }
 
-template <int S, int R, int LA>
+// SS: slices per depth chunk in memory (S when the triangle is the whole
+// contraction; more when it is the first band of a longer split).
+template <int S, int R, int LA, int SS = S>
 __device__ __forceinline__ void tri_run_i8(v4i (&acc)[R][S], const FragStream (&LDA)[R],
                                            const FragStream& LDB, int64_t c0, int64_t c1)
 {
-    constexpr uint32_t F = 1024, CS = (uint32_t)S * F;
+    constexpr uint32_t F = 1024, CS = (uint32_t)SS * F;
     uint32_t ck = (uint32_t)c0 * CS;
     v4i win[S], ar[R][S + 2];
 #pragma unroll

@@ -12,6 +12,11 @@ from oracle import exact as ox
 GRAN = {"int8": 64, "int8bal": 64, "fp64": 16}    # depth granule of a fragment
 ONE_BAND = {"int8": 32, "int8bal": 32, "fp64": 0}  # whole-triangle kernels: S up to this
 WIDEST_BAND = 16                                   # diagonals per band otherwise
+TWO_BANDS = (36, 64)   # INT8: S a multiple of 4 in this range may run as two bands of S/2
+
+
+def two_bands(form, S, band):
+    return form != "fp64" and S % 4 == 0 and TWO_BANDS[0] <= S <= TWO_BANDS[1] and 2 * band == S
 
 
 def check_params(form, K, T, G, beta, S, kc, band):
@@ -31,6 +36,9 @@ def check_params(form, K, T, G, beta, S, kc, band):
     assert S - smin < band, (S, smin, band)
     if smin <= ONE_BAND[form]:
         assert S == smin == band
+    elif two_bands(form, S, band):
+        # two bands over the whole depth: one exactness chunk
+        assert kc >= K and (S - smin < 4 or S == TWO_BANDS[0])
     else:
         assert band <= WIDEST_BAND
     if form == "fp64":

@@ -158,6 +158,41 @@ def test_triangle_kernel_every_S_several_chunks(S):
     np.testing.assert_array_equal(host(C), ox.method_product(A, B, 7, S)["C"])
 
 
+@pytest.mark.parametrize("beta", [7, 8])
+@pytest.mark.parametrize("S", range(36, 65, 4))
+def test_two_band_kernel_every_S(S, beta):
+    """Every two-band instantiation (S = 36 .. 64, both digit widths): two
+    bands of S/2 diagonals over the whole depth, folded in registers and
+    LDS, bit-exact against the oracle; M = 70 leaves a row block past the
+    padded digit array, N and K are ragged."""
+    form = "int8" if beta == 7 else "int8bal"
+    A, B = mdinputs.workload("od1024", M=70, N=33, K=100)
+    A[:, 5, :] = 0.0
+    C, info = md.gemm_ex(dev(A), dev(B), form=form, force_S=S, force_beta=beta)
+    assert info["band"] == S // 2 and info["kc"] >= 100
+    np.testing.assert_array_equal(host(C), ox.method_product(A, B, beta, S, balanced=beta == 8)["C"])
+
+
+def test_two_bands_need_one_exactness_chunk():
+    """A depth beyond one exactness chunk at S = 56 runs in bands of 14
+    (the sum buffer); S = 40, which splits into neither, is refused; the
+    debug dump of the diagonal sums also takes the bands."""
+    kc = rulecheck.library_chunk("int8bal", 8, 56)
+    A, B = mdinputs.workload("od1024", M=20, N=18, K=kc + 70)
+    C, info = md.gemm_ex(dev(A), dev(B), form="int8bal", force_S=56, force_beta=8)
+    assert info["band"] == 14 and info["kc"] == kc
+    np.testing.assert_array_equal(host(C), ox.method_product(A, B, 8, 56, balanced=True)["C"])
+    kc40 = rulecheck.library_chunk("int8bal", 8, 40)
+    A, B = mdinputs.workload("od1024", M=4, N=4, K=kc40 + 70)
+    with pytest.raises(md.MDError) as err:
+        md.gemm_ex(dev(A), dev(B), form="int8bal", force_S=40, force_beta=8)
+    assert err.value.code == 7
+    A, B = mdinputs.workload("od1024", M=21, N=19, K=70)
+    got, info = run_debug(A, B, "int8", 56, 7)
+    assert info["band"] == 14
+    check_against_oracle(A, B, got, 7, 56)
+
+
 @pytest.mark.parametrize("m", [1, 16])
 @pytest.mark.parametrize("form", ["int8", "fp64"])
 def test_word_counts_one_and_sixteen(m, form):
