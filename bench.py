@@ -76,6 +76,8 @@ def int8_kernel_name(info, K):
     S, band, b = info["S"], info["band"], info["beta"]
     if band == S and S <= 32:
         return f"k_tri2_i8<{S}, {b}>" if info["kc"] >= K else f"k_tri_i8<{S}, false, {b}>"
+    if 2 * band == S and S % 4 == 0 and 36 <= S <= 64:
+        return f"k_duo_i8<{S}, {b}>"
     return f"k_band2_i8<{band}>"
 
 
@@ -202,7 +204,13 @@ def paper_inner_products(md, torch, steps=5):
     paper's own parameters (FP64 form, beta = 13, S = 4m).  Whole-call
     milliseconds (inputs resident), the contraction and fold alone from HIP
     events, and the largest error over 8 sampled pairs against the exact
-    products (checked by the CPU leg) relative to sum |x||y|."""
+    products (checked by the CPU leg) relative to sum |x||y|.  The balanced
+    INT8 form also on the rule's S as a hint (no host round trip), with the
+    HBM bytes a call must read (the m words of both operands, 2 8 m batch n)
+    and that rate against 8 TB/s.  Beside them, m = 1, 2, 4, 8: the same
+    products in ordinary m-double arithmetic on the GPU (md_dot_ordinary),
+    and the ordinary-to-error-free time ratio beside the paper's one-core
+    ratio from Table 2."""
     import numpy as np
     import mdinputs
     X16, Y16 = mdinputs.paper_dot_workload(16)
@@ -237,6 +245,38 @@ def paper_inner_products(md, torch, steps=5):
             row[label] = {"S": info["S"], "beta": info["beta"], "ms_per_call": round(ms, 4),
                           "contraction_fold_ms": round(kern, 4)}
             defer_entries(row[label], "max_log2_err_sampled", Xs, Ys, idx, idx, Cq)
+            if label == "int8bal":
+                cert = md.new_cert()
+                hint = dict(form="int8bal", s_hint=info["S"], cert=cert)
+                oh, _ = md.dot_ex(X, Y, **hint)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(steps):
+                    oh, _ = md.dot_ex(X, Y, **hint)
+                torch.cuda.synchronize()
+                msh = (time.perf_counter() - t0) * 1e3 / steps
+                nbytes = 2 * 8 * m * X.shape[1] * X.shape[2]
+                row[label].update({"ms_per_call_hint": round(msh, 4),
+                                   "hint_equals_rule": bool(torch.equal(oh, out)),
+                                   "hint_certificate_flags": md.read_cert(cert)["flags"],
+                                   "input_bytes_per_call": nbytes,
+                                   "hint_hbm_frac": round(nbytes / (msh * 1e-3) / 8e12, 4)})
+        if m <= 8:
+            md.dot_ordinary(X, Y)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                oo = md.dot_ordinary(X, Y)
+            torch.cuda.synchronize()
+            mso = (time.perf_counter() - t0) * 1e3 / steps
+            row["ordinary"] = {"arithmetic": "ordinary m-double, every operation renormalised "
+                                             "(md_dot_ordinary, 64 partial sums per pair)",
+                               "ms_per_call": round(mso, 4)}
+            defer_entries(row["ordinary"], "max_log2_err_sampled", Xs, Ys, idx, idx,
+                          np.ascontiguousarray(oo.cpu().numpy()[:, pairs].T))
+            row["gpu_ordinary_over_int8bal"] = round(mso / row["int8bal"]["ms_per_call"], 3)
+            row["gpu_ordinary_over_int8bal_hint"] = round(mso / row["int8bal"]["ms_per_call_hint"], 3)
+            row["paper_cpu_ordinary_over_vectorized"] = round(PAPER_TABLE2_MS[m][0] / PAPER_TABLE2_MS[m][1], 3)
         rows[f"m{m}"] = row
         progress(f"inner products m={m} done")
         del X, Y
@@ -373,8 +413,11 @@ def small_case(md, torch, reps=200):
     """Double-double 64^3, the smallest workload, where launches and the
     host round trip dominate: microseconds per product (a) eager with the
     slice rule (one host synchronisation for the exponent spans), (b) eager
-    with the rule's S forced and a caller workspace (kernel launches only),
-    (c) replays of a HIP graph holding (b), whose output must equal (a)'s."""
+    with the rule's S as a hint and a caller workspace (the certificate
+    checked on the device, no synchronisation; its record must carry no
+    flag), (c) eager with the rule's S forced and a caller workspace (kernel
+    launches only), (d) replays of a HIP graph holding (c), whose output
+    must equal (a)'s."""
     import mdinputs
     Ah, Bh = mdinputs.workload("dd64")
     A = torch.from_numpy(Ah).cuda()
@@ -399,6 +442,11 @@ def small_case(md, torch, reps=200):
                          dtype=torch.uint8, device="cuda")
         Cg = torch.empty_like(C)
         us_rule = per_call_us(lambda: md.gemm_ex(A, B, C, form=form))
+        cert = md.new_cert()
+        Ch = torch.empty_like(C)
+        hint = dict(form=form, s_hint=info["S"], force_beta=info["beta"] if form == "fp64" else 0, cert=cert)
+        us_hint = per_call_us(lambda: md.gemm_ex(A, B, Ch, workspace=ws, **hint))
+        c = md.read_cert(cert)
         us_forced = per_call_us(lambda: md.gemm_ex(A, B, C, workspace=ws, **kw))
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
@@ -412,6 +460,8 @@ def small_case(md, torch, reps=200):
         Cg.zero_()
         us_graph = per_call_us(g.replay)
         row[form] = {"S": info["S"], "beta": info["beta"], "eager_rule_us": us_rule,
+                     "eager_hint_us": us_hint, "hint_certificate_flags": c["flags"],
+                     "hint_equals_rule": bool(torch.equal(Ch, C)),
                      "eager_forced_us": us_forced, "graph_replay_us": us_graph,
                      "graph_equals_eager": bool(torch.equal(Cg, C))}
         defer_error(row[form], "max_log2_err_sampled", Ah, Bh, C)

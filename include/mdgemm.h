@@ -267,14 +267,31 @@ int md_dot(int m, int64_t batch, int64_t n, const double *X, const double *Y, do
  * multiplication and addition renormalised to m words, each entry
  * accumulated over k in increasing order from zero.  m = 1 (plain double
  * arithmetic), 2 (accurate double-double addition, Dekker-product
- * multiplication) or 4 (quad-double operations grouped by order, one
- * renormalisation each); no fused multiply-add.  Not error-free: the error
- * grows with K.  Dense planes as
- * md_gemm; C must not overlap A or B.  M = 0 or N = 0 is a no-op; K = 0
- * writes zeros.  Return codes as md_gemm (MD_EINVAL_M for other m).
+ * multiplication), 4 (quad-double operations grouped by order, one
+ * renormalisation each) or 8 (floating-point expansion arithmetic as in
+ * CAMPARY, the paper's reference for any length: addition by merging the
+ * words by magnitude, multiplication by the product of expansions
+ * truncated at order 8, both renormalised by VecSum and VecSumErrBranch);
+ * no fused multiply-add.  Not error-free: the error grows with K.  Dense
+ * planes as md_gemm; C must not overlap A or B.  M = 0 or N = 0 is a no-op;
+ * K = 0 writes zeros.  Return codes as md_gemm (MD_EINVAL_M for other m).
  */
 int md_gemm_ordinary(int m, int64_t M, int64_t N, int64_t K, const double *A, const double *B,
                      double *C, void *stream);
+
+/*
+ * Batched inner products in ordinary m-double arithmetic (the "ordinary"
+ * side of the paper's experiment, Section 3, Table 2): out_b = sum_k
+ * x_bk y_bk with md_gemm_ordinary's operations, m = 1, 2, 4 or 8.  Order:
+ * 64 partial sums per pair, sum l accumulating add(acc, mul(x_k, y_k)) over
+ * k = l, l + 64, l + 128, .. from zero, then pairwise, sum l < h taking
+ * add(sum_l, sum_(l+h)) for h = 32, 16, .., 1.  Dense planes as md_dot (X
+ * and Y: word w of element k of vector b at [w batch n + b n + k]; out:
+ * [w batch + b]); out must not overlap X or Y.  batch = 0 is a no-op;
+ * n = 0 writes zeros.  Return codes as md_dot (MD_EINVAL_M for other m).
+ */
+int md_dot_ordinary(int m, int64_t batch, int64_t n, const double *X, const double *Y, double *out,
+                    void *stream);
 
 /*
  * Exact fixed-point results (paper, Section 1: multiword integers; the

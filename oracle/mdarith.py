@@ -1,4 +1,4 @@
-"""Ordinary double-double and quad-double arithmetic with operation counters.
+"""Ordinary double-, quad- and octo-double arithmetic with operation counters.
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 
@@ -20,6 +20,11 @@ multiplication entry compared:
 * double-double multiplication: TwoProd of the high parts, the two cross
   products added to its error, one Fast2Sum: 24 operations (the table says
   23; the paper does not name its variant, so this entry stays unpinned).
+
+Octo-double addition and multiplication follow floating-point expansion
+arithmetic (CAMPARY's VecSum, VecSumErrBranch, merge-based addition and the
+truncated product of expansions), see the section that defines them; their
+counts (135 and 1769) stand beside the table's 269 and 1742, unpinned.
 
 The counters are the ordinary method's cost model: an ordinary m-double
 product of an M x K by a K x N matrix costs M N K (add_m + mul_m) double
@@ -177,6 +182,129 @@ def qd_mul(c: Counter, x, y):
     return renorm5(c, p0, r1, r2, r3, 0.0)
 
 
+# ---------------------------------------------------------------------------
+# octo-double operations (m = 8): floating-point expansion arithmetic in the
+# manner of CAMPARY (Joldes, Muller, Popescu and Tucker; the paper's
+# reference for multiple double arithmetic of any length), built from the
+# same error-free transformations:
+#
+# * VecSum: from the last term up, TwoSum of each term with the running sum;
+#   the exact sum is kept, the first output is the rounded sum;
+# * VecSumErrBranch: Fast2Sum down the terms, starting a new output word
+#   whenever the error is nonzero, until m words are out;
+# * renormalisation to m words: VecSumErrBranch of VecSum;
+# * addition: the 2m words of both operands merged by decreasing magnitude
+#   (here with Batcher's odd-even merge network, a fixed order of
+#   compare-exchanges, so that a GPU thread runs it without branches), then
+#   renormalised;
+# * multiplication (Joldes, Muller and Popescu's product of expansions
+#   truncated at order m): for order n = 0 .. m-1 the n+1 products
+#   x_i y_(n-i) by TwoProd; their high parts and the errors carried from the
+#   orders below pass through VecSum, whose first word is the result's word
+#   of order n and whose other words are carried on with the new TwoProd
+#   errors; at order m the products x_i y_(m-i) and every carried error are
+#   added plainly; the m+1 words are renormalised.
+# ---------------------------------------------------------------------------
+
+def vec_sum(c: Counter, x):
+    """VecSum: (s_0, e_1, .., e_(n-1)) with s_0 + sum e_i = sum x_i exactly."""
+    n = len(x)
+    out = [0.0] * n
+    s = x[n - 1]
+    for i in range(n - 2, -1, -1):
+        s, out[i + 1] = two_sum(c, x[i], s)
+    out[0] = s
+    return out
+
+
+def vec_sum_err_branch(c: Counter, e, m: int):
+    """VecSumErrBranch: m words from a VecSum output, a new word started
+    only where the Fast2Sum error is nonzero (zeros pad the tail)."""
+    r = [0.0] * m
+    j = 0
+    eps = e[0]
+    for i in range(len(e) - 1):
+        rj, nxt = fast_two_sum(c, eps, e[i + 1])
+        r[j] = rj
+        if nxt != 0.0:
+            if j >= m - 1:
+                return r
+            j += 1
+            eps = nxt
+        else:
+            eps = rj
+    r[j] = eps
+    return r
+
+
+def renormalize(c: Counter, x, m: int):
+    """The terms x (roughly decreasing) as m nonoverlapping words."""
+    return vec_sum_err_branch(c, vec_sum(c, x), m)
+
+
+def odd_even_merge(n: int):
+    """Batcher's odd-even merge of two sorted runs of n = 2^k terms: the
+    compare-exchange pairs (i, j), i < j, in order."""
+    pairs = []
+
+    def merge(lo, hi, r):
+        step = 2 * r
+        if step < hi - lo:
+            merge(lo, hi, step)
+            merge(lo + r, hi, step)
+            pairs.extend((i, i + r) for i in range(lo + r, hi - r, step))
+        else:
+            pairs.append((lo, lo + r))
+
+    merge(0, 2 * n - 1, 1)
+    return pairs
+
+
+def merge_by_magnitude(x, y):
+    """The words of x and y (each by decreasing magnitude) in one list by
+    decreasing magnitude: the merge network, exchanging where the earlier
+    word is strictly smaller in magnitude."""
+    z = list(x) + list(y)
+    for i, j in odd_even_merge(len(x)):
+        if abs(z[i]) < abs(z[j]):
+            z[i], z[j] = z[j], z[i]
+    return z
+
+
+def od_add(c: Counter, x, y):
+    """Octo-double addition: merge, then renormalise 16 words to 8."""
+    return renormalize(c, merge_by_magnitude(x, y), 8)
+
+
+def md_mul_expansion(c: Counter, x, y, m: int):
+    """The product of two m-word expansions truncated at order m (see the
+    section comment), renormalised to m words."""
+    p, e = two_prod(c, x[0], y[0])
+    r = [p]
+    errs = [e]
+    for n in range(1, m):
+        P, Eh = [], []
+        for i in range(n + 1):
+            pi, ei = two_prod(c, x[i], y[n - i])
+            P.append(pi)
+            Eh.append(ei)
+        s = vec_sum(c, P + errs)
+        r.append(s[0])
+        errs = s[1:] + Eh
+    t = c.mul(x[1], y[m - 1])
+    for i in range(2, m):
+        t = c.add(t, c.mul(x[i], y[m - i]))
+    for e in errs:
+        t = c.add(t, e)
+    r.append(t)
+    return renormalize(c, r, m)
+
+
+def od_mul(c: Counter, x, y):
+    """Octo-double multiplication."""
+    return md_mul_expansion(c, x, y, 8)
+
+
 def d_add(c: Counter, x, y):
     """Ordinary 1-double addition: one IEEE rounding."""
     return (c.add(x[0], y[0]),)
@@ -187,11 +315,11 @@ def d_mul(c: Counter, x, y):
     return (c.mul(x[0], y[0]),)
 
 
-ORDINARY = {1: (d_add, d_mul), 2: (dd_add, dd_mul), 4: (qd_add, qd_mul)}
+ORDINARY = {1: (d_add, d_mul), 2: (dd_add, dd_mul), 4: (qd_add, qd_mul), 8: (od_add, od_mul)}
 
 
 def ordinary_dot(c: Counter, xs, ys, m: int):
-    """sum_k x_k * y_k in ordinary m-double arithmetic (m = 1, 2, 4): the
+    """sum_k x_k * y_k in ordinary m-double arithmetic (m = 1, 2, 4, 8): the
     accumulator starts at zero and takes add(acc, mul(x_k, y_k)) for k in
     increasing order, each operation renormalised."""
     add, mul = ORDINARY[m]
@@ -199,6 +327,23 @@ def ordinary_dot(c: Counter, xs, ys, m: int):
     for x, y in zip(xs, ys):
         acc = add(c, acc, mul(c, x, y))
     return acc
+
+
+def ordinary_dot_lanes(c: Counter, xs, ys, m: int, lanes: int = 64):
+    """sum_k x_k * y_k in ordinary m-double arithmetic, in the order of a
+    batched kernel that gives one vector pair to ``lanes`` threads: thread l
+    accumulates add(acc, mul(x_k, y_k)) over k = l, l + lanes, l + 2 lanes,
+    .. from zero (as ``ordinary_dot``), then the partial sums meet pairwise:
+    for h = lanes/2, lanes/4, .., 1, thread l < h takes add(acc_l, acc_(l+h)).
+    ``lanes`` = 1 is ``ordinary_dot``."""
+    add, _ = ORDINARY[m]
+    acc = [ordinary_dot(c, xs[l::lanes], ys[l::lanes], m) for l in range(lanes)]
+    h = lanes // 2
+    while h >= 1:
+        for l in range(h):
+            acc[l] = add(c, acc[l], acc[l + h])
+        h //= 2
+    return acc[0]
 
 
 def ordinary_gemm(A, B, rows=None, cols=None):
@@ -222,10 +367,12 @@ def ordinary_gemm(A, B, rows=None, cols=None):
 
 
 def op_count(fn, m: int = 2) -> int:
-    """Double operations one call of an m-double ``fn`` (m = 2, 4) costs."""
+    """Double operations one call of an m-double ``fn`` (m = 2, 4, 8) costs
+    on full-length operands (the octo-double renormalisation stops early on
+    short ones)."""
     c = Counter()
-    x = (1.0, 2.0 ** -60, 2.0 ** -115, -(2.0 ** -170))[:m]
-    y = (3.0, -(2.0 ** -58), 2.0 ** -112, 2.0 ** -166)[:m]
+    x = tuple((-1.0) ** (w // 3) * (1.0 + w / 16) * 2.0 ** (-57 * w) for w in range(m))
+    y = tuple((-1.0) ** (w // 2) * (3.0 - w / 16) * 2.0 ** (-55 * w) for w in range(m))
     fn(c, x, y)
     return c.n
 

@@ -123,6 +123,8 @@ def lib():
     L.md_dot.restype = i32
     L.md_gemm_ordinary.argtypes = [i32, i64, i64, i64, p, p, p, p]
     L.md_gemm_ordinary.restype = i32
+    L.md_dot_ordinary.argtypes = [i32, i64, i64, p, p, p, p]
+    L.md_dot_ordinary.restype = i32
     L.md_choose_params.argtypes = [i32, i64, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                    ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.md_choose_params.restype = i32
@@ -361,8 +363,8 @@ def dot(X: torch.Tensor, Y: torch.Tensor, form: str = "fp64", stream=None) -> to
 
 
 def gemm_ordinary(A: torch.Tensor, B: torch.Tensor, stream=None) -> torch.Tensor:
-    """C = A B in ordinary m-double arithmetic (m = 1, 2, 4), every operation
-    renormalised: the comparison baseline, not error-free."""
+    """C = A B in ordinary m-double arithmetic (m = 1, 2, 4, 8), every
+    operation renormalised: the comparison baseline, not error-free."""
     _check_planes(A, "A")
     _check_planes(B, "B")
     A = A.contiguous()
@@ -374,6 +376,22 @@ def gemm_ordinary(A: torch.Tensor, B: torch.Tensor, stream=None) -> torch.Tensor
     C = torch.empty((m, M, N), dtype=torch.float64, device=A.device)
     _check(lib().md_gemm_ordinary(m, M, N, K, _ptr(A), _ptr(B), _ptr(C), _stream_handle(stream)))
     return C
+
+
+def dot_ordinary(X: torch.Tensor, Y: torch.Tensor, stream=None) -> torch.Tensor:
+    """Batched inner products in ordinary m-double arithmetic (m = 1, 2, 4,
+    8) of (m, batch, n) planes, 64 partial sums per pair met pairwise: the
+    comparison baseline of ``dot``, not error-free."""
+    _check_planes(X, "X")
+    _check_planes(Y, "Y")
+    X = X.contiguous()
+    Y = Y.contiguous()
+    if X.shape != Y.shape:
+        raise ValueError("X and Y differ in shape")
+    m, batch, n = X.shape
+    out = torch.empty((m, batch), dtype=torch.float64, device=X.device)
+    _check(lib().md_dot_ordinary(m, batch, n, _ptr(X), _ptr(Y), _ptr(out), _stream_handle(stream)))
+    return out
 
 
 def fixed_limbs(beta: int, S: int, K: int) -> int:
@@ -525,5 +543,5 @@ class MDGemm(torch.autograd.Function):
         return dA, dB, None
 
 
-__all__ = ["gemm", "gemm_ex", "gemm_ordinary", "dot", "dot_ex", "MDGemm", "choose_params", "lib",
+__all__ = ["gemm", "gemm_ex", "gemm_ordinary", "dot_ordinary", "dot", "dot_ex", "MDGemm", "choose_params", "lib",
            "MDError", "MDInfo", "MDCert", "new_cert", "read_cert"]

@@ -996,7 +996,7 @@ int md_gemm_ordinary(int m, int64_t M, int64_t N, int64_t K, const double* A, co
                      double* C, void* stream)
 {
     g_last_hip = 0;
-    if (m != 1 && m != 2 && m != 4)
+    if (m != 1 && m != 2 && m != 4 && m != 8)
         return MD_EINVAL_M;
     if (M < 0 || N < 0 || K < 0)
         return MD_EINVAL_DIM;
@@ -1013,6 +1013,27 @@ int md_gemm_ordinary(int m, int64_t M, int64_t N, int64_t K, const double* A, co
         return MD_EALIAS;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = K == 0 ? launch_fill_zero(C, m, M, N, N, M * N, st) : launch_ordinary(m, A, B, C, M, N, K, st);
+    return e == hipSuccess ? MD_OK : hip_fail(e);
+}
+
+int md_dot_ordinary(int m, int64_t batch, int64_t n, const double* X, const double* Y, double* out,
+                    void* stream)
+{
+    g_last_hip = 0;
+    if (m != 1 && m != 2 && m != 4 && m != 8)
+        return MD_EINVAL_M;
+    if (batch < 0 || n < 0 || batch > (INT64_C(1) << 40) || n > (INT64_C(1) << 40) || !mul_ok(batch, n))
+        return MD_EINVAL_DIM;
+    if (batch == 0)
+        return MD_OK;
+    if (!out || (n > 0 && (!X || !Y)))
+        return MD_ENULL;
+    const Span so = extent(out, m, 1, batch, 0, 1, batch);
+    if (n > 0 && (overlap(so, extent(X, m, batch, n, n, 1, batch * n)) || overlap(so, extent(Y, m, batch, n, n, 1, batch * n))))
+        return MD_EALIAS;
+    hipStream_t st = (hipStream_t)stream;
+    const hipError_t e = n == 0 ? launch_fill_zero(out, m, 1, batch, batch, batch, st)
+                                : launch_ordinary_dot(m, X, Y, out, batch, batch, n, st);
     return e == hipSuccess ? MD_OK : hip_fail(e);
 }
 

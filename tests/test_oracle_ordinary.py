@@ -9,10 +9,18 @@ baseline, Section 1, Table 1) against exact arithmetic.
   the double-double operations to double-double accuracy;
 * the ordinary inner product accumulates add(acc, mul(x_k, y_k)) in
   increasing k and stays within K 2^-(52 m - 3) of sum |x||y|;
+* octo-double addition and multiplication (floating-point expansions:
+  VecSum, VecSumErrBranch, merge-based addition, the truncated product)
+  stay within 2^-412 of the exact sum and product; the merge network sorts
+  (every 0/1 input with sorted halves, and random ones); dropping the
+  TwoProd errors of the order-6 products (terms of order 7) would cost
+  about 2^-370;
+* the lane-order inner product (the batched GPU kernel's order) with one
+  lane is the sequential one, and with 64 lanes meets the same bound;
 * operation counts beside Table 1: double-double addition 20 (pinned in
   test_oracle.py); quad-double addition 85 and multiplication 194 against
-  the table's 89 and 336, whose algorithms the paper does not name
-  (reported, parity unpinned).
+  the table's 89 and 336, octo-double 135 and 1769 against 269 and 1742,
+  whose algorithms the paper does not name (reported, parity unpinned).
 """
 from fractions import Fraction
 
@@ -83,7 +91,7 @@ def test_qd_ops_on_double_doubles():
         assert abs(val(p) - val(q)) <= Fraction(2) ** -100 * ref
 
 
-@pytest.mark.parametrize("m", [1, 2, 4])
+@pytest.mark.parametrize("m", [1, 2, 4, 8])
 def test_ordinary_dot_bound(m):
     r = rng(10 + m)
     K = 64
@@ -133,3 +141,94 @@ def test_op_counts_beside_table1():
     # reported beside the table's 89 and 336 (algorithms unnamed: unpinned)
     assert ma.op_count(ma.qd_add, 4) == 85
     assert ma.op_count(ma.qd_mul, 4) == 194
+    # octo-double expansion arithmetic beside the table's 269 and 1742
+    assert ma.op_count(ma.od_add, 8) == 135
+    assert ma.op_count(ma.od_mul, 8) == 1769
+
+
+def od_samples(n, seed, lead=("log2uniform", 20.0)):
+    return mdinputs.mdouble(rng(seed), 8, (n,), lead)
+
+
+def test_merge_network_sorts():
+    """Batcher's odd-even merge of two sorted runs of 8: every 0/1 input
+    whose halves are sorted (the 0-1 principle), and random magnitudes."""
+    pairs = ma.odd_even_merge(8)
+    for a in range(9):
+        for b in range(9):
+            z = [1] * a + [0] * (8 - a) + [1] * b + [0] * (8 - b)
+            for i, j in pairs:
+                if z[i] < z[j]:
+                    z[i], z[j] = z[j], z[i]
+            assert z == sorted(z, reverse=True)
+    r = rng(40)
+    for _ in range(200):
+        x = sorted(r.standard_normal(8), key=abs, reverse=True)
+        y = sorted(r.standard_normal(8), key=abs, reverse=True)
+        z = ma.merge_by_magnitude(x, y)
+        assert [abs(v) for v in z] == sorted((abs(v) for v in x + y), reverse=True)
+
+
+def test_od_add_accuracy():
+    X = od_samples(300, 41)
+    Y = od_samples(300, 42)
+    Y[0, :100] = -X[0, :100]              # the leading words cancel
+    Y[:, 100:150] = 0.0                   # a zero operand
+    worst = Fraction(0)
+    for i in range(300):
+        x, y = tuple(X[:, i]), tuple(Y[:, i])
+        s = ma.od_add(ma.Counter(), x, y)
+        assert ox.is_nonoverlapping(s, strong=False)
+        err = abs(val(s) - (val(x) + val(y)))
+        worst = max(worst, err / (abs(val(x)) + abs(val(y))))
+    assert worst <= Fraction(2) ** -412, float(worst)
+
+
+def test_od_mul_accuracy():
+    X = od_samples(300, 43)
+    Y = od_samples(300, 44)
+    worst = Fraction(0)
+    for i in range(300):
+        x, y = tuple(X[:, i]), tuple(Y[:, i])
+        p = ma.od_mul(ma.Counter(), x, y)
+        assert ox.is_nonoverlapping(p, strong=False)
+        err = abs(val(p) - val(x) * val(y))
+        worst = max(worst, err / abs(val(x) * val(y)))
+    assert worst <= Fraction(2) ** -412, float(worst)
+
+
+def test_od_ops_on_quad_doubles():
+    """Octo-doubles whose four trailing words are zero: sums and products
+    to at least quad-double accuracy against exact arithmetic, and a zero
+    octo-double added changes nothing."""
+    X = od_samples(60, 45)
+    Y = od_samples(60, 46)
+    X[4:] = 0.0
+    Y[4:] = 0.0
+    for i in range(60):
+        x, y = tuple(X[:, i]), tuple(Y[:, i])
+        assert abs(val(ma.od_add(ma.Counter(), x, y)) - (val(x) + val(y))) <= \
+            Fraction(2) ** -412 * (abs(val(x)) + abs(val(y)))
+        assert abs(val(ma.od_mul(ma.Counter(), x, y)) - val(x) * val(y)) <= Fraction(2) ** -412 * abs(val(x) * val(y))
+        assert val(ma.od_add(ma.Counter(), x, (0.0,) * 8)) == val(x)
+
+
+@pytest.mark.parametrize("m", [1, 2, 4, 8])
+def test_lane_order_dot(m):
+    r = rng(50 + m)
+    K = 200
+    X = mdinputs.mdouble(r, m, (K,), ("log2uniform", 8.0))
+    Y = mdinputs.mdouble(r, m, (K,), ("log2uniform", 8.0))
+    xs = [tuple(X[:, k]) for k in range(K)]
+    ys = [tuple(Y[:, k]) for k in range(K)]
+    assert ma.ordinary_dot_lanes(ma.Counter(), xs, ys, m, lanes=1) == ma.ordinary_dot(ma.Counter(), xs, ys, m)
+    out = ma.ordinary_dot_lanes(ma.Counter(), xs, ys, m, lanes=64)
+    exact = sum(val(x) * val(y) for x, y in zip(xs, ys))
+    absum = sum(abs(val(x) * val(y)) for x, y in zip(xs, ys))
+    assert abs(val(out) - exact) <= K * Fraction(2) ** -(52 * m - 3) * absum
+    # 4 lanes by hand: two rounds of pairwise sums
+    add, _ = ma.ORDINARY[m]
+    c = ma.Counter()
+    acc = [ma.ordinary_dot(c, xs[l::4], ys[l::4], m) for l in range(4)]
+    want = add(c, add(c, acc[0], acc[2]), add(c, acc[1], acc[3]))
+    assert ma.ordinary_dot_lanes(ma.Counter(), xs, ys, m, lanes=4) == want
