@@ -362,7 +362,7 @@ int check_slice_opts(const md_opts& o, int64_t K, bool duo)
 // of the statistics to the host and one synchronisation.  stats: the
 // call's statistics (kStatWords), complete in stream order.
 int choose_slices(const md_opts& o, int m, int64_t K, int T, const int32_t* stats, hipStream_t st, Choice& c,
-                  bool duo)
+                  bool duo, bool defer_cert = false)
 {
     const int Sgiven = o.force_S > 0 ? o.force_S : o.s_hint;
     hipError_t e;
@@ -383,9 +383,11 @@ int choose_slices(const md_opts& o, int m, int64_t K, int T, const int32_t* stat
             return MD_ERANGE;
         if (o.force_S > 0)
             return MD_OK;
+        c.log2_bound = __builtin_nan("");
+        if (defer_cert)
+            return MD_OK;   // the caller certifies once the statistics are made
         if ((e = launch_cert(stats, o.form, K, T, m, c.beta, c.S, o.cert, st)) != hipSuccess)
             return hip_fail(e);
-        c.log2_bound = __builtin_nan("");
         return MD_OK;
     }
     int32_t h[kStatWords];
@@ -470,12 +472,45 @@ int md_choose_params(int form, int64_t K, int T, int G, int* beta, int* S, int* 
     return rc;
 }
 
+// Launch shape of the lane-wise INT8 inner products for S slices, if a lane
+// kernel holds S: containers of SC digits, 64 nw threads per workgroup,
+// depth ranges of `chunk` entries (nch per pair), each within the steps
+// whose int32 sums stay exact, and about 1024 workgroups where the pairs
+// are few.
+struct LanePlan {
+    int SC = 0, nw = 0;
+    int64_t chunk = 0, nch = 0;
+};
+
+bool plan_lane(int form, int m, int S, int64_t batch, int64_t n, LanePlan& p)
+{
+    if (!is_i8(form) || n <= 0)
+        return false;
+    int lo, hi;
+    lane_sc_range(m, lo, hi);
+    const int SC = (S + 7) / 8 * 8;
+    if (lo == 0 || SC < lo || SC > hi)
+        return false;
+    p.SC = SC;
+    p.nw = batch >= 512 ? 2 : 4;
+    const int64_t stepw = 256 * p.nw;
+    const int64_t cap = stepw * lane_steps_limit(SC);
+    const int64_t spread = std::min<int64_t>((1024 + batch - 1) / batch, (n + 4 * stepw - 1) / (4 * stepw));
+    const int64_t nch = std::max<int64_t>({(n + cap - 1) / cap, spread, 1});
+    p.chunk = round_up((n + nch - 1) / nch, stepw);
+    p.nch = (n + p.chunk - 1) / p.chunk;
+    return p.nch <= 65535;
+}
+
 size_t md_dot_workspace_size(int form, int64_t batch, int64_t n, int S)
 {
     // exponents and statistics, the two magnitude slices (slice rule), the
-    // two digit planes and the S x batch diagonal sums
+    // two digit planes (the FP64 form; INT8 cuts digits in registers where a
+    // lane kernel holds S), the S x batch diagonal sums and the per-pair
+    // statistics of whole-pair calls
     return small_bytes(batch, batch) + 2 * digits_bytes(MD_FORM_INT8, batch, n, 1) +
-           2 * digits_bytes(form, batch, n, S) + (size_t)S * batch * sizeof(int64_t) + 4096;
+           2 * digits_bytes(form, batch, n, S) + (size_t)S * batch * sizeof(int64_t) +
+           (size_t)batch * 24 + 4096;
 }
 
 size_t md_gemm_workspace_size(int form, int64_t M, int64_t N, int64_t K, int S)
@@ -889,16 +924,63 @@ int md_dot_ex(int m, int64_t batch, int64_t n, const double* X, int64_t ldx, int
         F = q; q += Ba;
         stats = q;
     }
+    const int eoff = grid_offset(o.form);
+    const bool use_rho = o.force_S == 0 && o.s_rule == MD_S_RHO;
+    const int Sgiven = o.force_S > 0 ? o.force_S : o.s_hint;
+    LanePlan lp;
+
+    // A given S whose lane kernel takes each pair in one workgroup: that
+    // kernel finds the exponents and the statistics itself, and the
+    // certificate follows it.
+    if (Sgiven > 0 && plan_lane(o.form, m, Sgiven, batch, n, lp) && lp.nch == 1) {
+        if ((e = launch_exp_init(hiX, loX, 0, stats, st)) != hipSuccess)
+            return hip_fail(e);
+        Choice ch;
+        int rc = choose_slices(o, m, n, T, stats, st, ch, false, true);
+        if (rc)
+            return rc;
+        void *Dp, *pp;
+        rc = scr.get((size_t)ch.S * batch * sizeof(int64_t), &Dp);
+        if (rc)
+            return rc;
+        rc = scr.get((size_t)batch * (4 * sizeof(int32_t) + sizeof(unsigned long long)), &pp);
+        if (rc)
+            return rc;
+        unsigned long long* pm = (unsigned long long*)pp;
+        int32_t* ph = (int32_t*)(pm + batch);
+        const int ncol = fold_columns(ch.beta, ch.S, round_up(n, kKcI8));
+        if ((size_t)ncol * 256 * sizeof(int64_t) > 160 * 1024)
+            return MD_ERANGE;
+        LaneDotArgs la{opX.p, ldx, plane_stride_X, opY.p, ldy, plane_stride_Y, batch, n, 0, lp.chunk,
+                       E, F, ph, pm, (int64_t*)Dp, ch.S, eoff, 1, use_rho ? 1 : 0, 0};
+        if (o.ev_gemm_begin && (e = hipEventRecord((hipEvent_t)o.ev_gemm_begin, st)) != hipSuccess)
+            return hip_fail(e);
+        if ((e = launch_dot_lane(la, m, lp.SC, o.form == MD_FORM_INT8_BAL, lp.nw, lp.nch, st)) != hipSuccess)
+            return hip_fail(e);
+        if (o.force_S == 0) {
+            if ((e = launch_pair_stats(ph, use_rho ? pm : nullptr, batch, stats, st)) != hipSuccess)
+                return hip_fail(e);
+            if ((e = launch_cert(stats, o.form, n, T, m, ch.beta, ch.S, o.cert, st)) != hipSuccess)
+                return hip_fail(e);
+        }
+        if ((e = launch_dot_final((const int64_t*)Dp, E, F, batch, ch.S, ch.beta, ncol, m, out,
+                                  std::max<int64_t>(plane_stride_out, 1), st)) != hipSuccess)
+            return hip_fail(e);
+        if (o.ev_gemm_end && (e = hipEventRecord((hipEvent_t)o.ev_gemm_end, st)) != hipSuccess)
+            return hip_fail(e);
+        if (o.info)
+            fill_info(o.info, ch, T, o.validate != 0);
+        return MD_OK;
+    }
+
     if ((e = launch_exp_init(hiX, loX, batch, stats, st)) != hipSuccess) return hip_fail(e);
     if ((e = launch_exp_init(hiY, loY, batch, nullptr, st)) != hipSuccess) return hip_fail(e);
     if ((e = launch_exp_partial(opX, hiX, loX, st)) != hipSuccess) return hip_fail(e);
     if ((e = launch_exp_partial(opY, hiY, loY, st)) != hipSuccess) return hip_fail(e);
-    const int eoff = grid_offset(o.form);
     if ((e = launch_exp_final(hiX, loX, batch, E, stats, stats + 4, nullptr, eoff, st)) != hipSuccess) return hip_fail(e);
     if ((e = launch_exp_final(hiY, loY, batch, F, stats + 1, stats + 6, nullptr, eoff, st)) != hipSuccess) return hip_fail(e);
 
     const int64_t nrb = round_up(batch, kTile) / kRowBlock;
-    const bool use_rho = o.force_S == 0 && o.s_rule == MD_S_RHO;
     if (use_rho) {
         // magnitude certificate over the pairs: min_b sum_k qX_bk qY_bk
         const int64_t nkm = (n + kKcI8 - 1) / kKcI8;
@@ -930,52 +1012,65 @@ int md_dot_ex(int m, int64_t batch, int64_t n, const double* X, int64_t ldx, int
     if ((size_t)ncol * 256 * sizeof(int64_t) > 160 * 1024)
         return MD_ERANGE;
 
-    void *dX, *dY, *Dp;
-    int rc = scr.get(digits_bytes(o.form, batch, n, S), &dX);
+    void* Dp;
+    int rc = scr.get((size_t)S * batch * sizeof(int64_t), &Dp);
     if (rc)
         return rc;
-    rc = scr.get(digits_bytes(o.form, batch, n, S), &dY);
-    if (rc)
-        return rc;
-    rc = scr.get((size_t)S * batch * sizeof(int64_t), &Dp);
-    if (rc)
-        return rc;
-    if (is_i8(o.form)) {
-        const bool bal = o.form == MD_FORM_INT8_BAL;
-        if ((e = launch_split_i8(opX, m, E, S, nrb, nkc, (int8_t*)dX, nullptr, bal, st)) != hipSuccess)
+    if (plan_lane(o.form, m, S, batch, n, lp)) {
+        // INT8 digits cut in registers, no digit planes
+        if (lp.nch > 1 && (e = launch_fill_zero_i64((int64_t*)Dp, (int64_t)S * batch, st)) != hipSuccess)
             return hip_fail(e);
-        if ((e = launch_split_i8(opY, m, F, S, nrb, nkc, (int8_t*)dY, nullptr, bal, st)) != hipSuccess)
+        LaneDotArgs la{opX.p, ldx, plane_stride_X, opY.p, ldy, plane_stride_Y, batch, n, 0, lp.chunk,
+                       E, F, nullptr, nullptr, (int64_t*)Dp, S, eoff, 0, 0, lp.nch > 1 ? 1 : 0};
+        if (o.ev_gemm_begin && (e = hipEventRecord((hipEvent_t)o.ev_gemm_begin, st)) != hipSuccess)
+            return hip_fail(e);
+        if ((e = launch_dot_lane(la, m, lp.SC, o.form == MD_FORM_INT8_BAL, lp.nw, lp.nch, st)) != hipSuccess)
             return hip_fail(e);
     } else {
-        if ((e = launch_split_f64(opX, m, E, S, beta, nrb, nkc, (double*)dX, nullptr, st)) != hipSuccess)
+        void *dX, *dY;
+        rc = scr.get(digits_bytes(o.form, batch, n, S), &dX);
+        if (rc)
+            return rc;
+        rc = scr.get(digits_bytes(o.form, batch, n, S), &dY);
+        if (rc)
+            return rc;
+        if (is_i8(o.form)) {
+            const bool bal = o.form == MD_FORM_INT8_BAL;
+            if ((e = launch_split_i8(opX, m, E, S, nrb, nkc, (int8_t*)dX, nullptr, bal, st)) != hipSuccess)
+                return hip_fail(e);
+            if ((e = launch_split_i8(opY, m, F, S, nrb, nkc, (int8_t*)dY, nullptr, bal, st)) != hipSuccess)
+                return hip_fail(e);
+        } else {
+            if ((e = launch_split_f64(opX, m, E, S, beta, nrb, nkc, (double*)dX, nullptr, st)) != hipSuccess)
+                return hip_fail(e);
+            if ((e = launch_split_f64(opY, m, F, S, beta, nrb, nkc, (double*)dY, nullptr, st)) != hipSuccess)
+                return hip_fail(e);
+        }
+        if ((e = launch_fill_zero_i64((int64_t*)Dp, (int64_t)S * batch, st)) != hipSuccess)
             return hip_fail(e);
-        if ((e = launch_split_f64(opY, m, F, S, beta, nrb, nkc, (double*)dY, nullptr, st)) != hipSuccess)
-            return hip_fail(e);
-    }
-    if ((e = launch_fill_zero_i64((int64_t*)Dp, (int64_t)S * batch, st)) != hipSuccess)
-        return hip_fail(e);
 
-    DotArgs da;
-    da.X = dX;
-    da.Y = dY;
-    da.D = (int64_t*)Dp;
-    da.batch = batch;
-    da.nkc = nkc;
-    da.S = S;
-    da.band = band;
-    da.nbands = S / band;
-    // depth fragments per workgroup: within one exactness chunk, and short
-    // enough that about 2048 workgroups share the depth
-    {
-        const int64_t kcc = std::max<int64_t>(kc / kcg, 1);
-        const int64_t units = ((batch + 15) / 16) * da.nbands;
-        const int64_t want = (nkc * units + 2047) / 2048;
-        da.range = std::max<int64_t>(1, std::min<int64_t>(kcc, want));
+        DotArgs da;
+        da.X = dX;
+        da.Y = dY;
+        da.D = (int64_t*)Dp;
+        da.batch = batch;
+        da.nkc = nkc;
+        da.S = S;
+        da.band = band;
+        da.nbands = S / band;
+        // depth fragments per workgroup: within one exactness chunk, and short
+        // enough that about 2048 workgroups share the depth
+        {
+            const int64_t kcc = std::max<int64_t>(kc / kcg, 1);
+            const int64_t units = ((batch + 15) / 16) * da.nbands;
+            const int64_t want = (nkc * units + 2047) / 2048;
+            da.range = std::max<int64_t>(1, std::min<int64_t>(kcc, want));
+        }
+        if (o.ev_gemm_begin && (e = hipEventRecord((hipEvent_t)o.ev_gemm_begin, st)) != hipSuccess)
+            return hip_fail(e);
+        if ((e = launch_dot_diag(da, is_i8(o.form), st)) != hipSuccess)
+            return hip_fail(e);
     }
-    if (o.ev_gemm_begin && (e = hipEventRecord((hipEvent_t)o.ev_gemm_begin, st)) != hipSuccess)
-        return hip_fail(e);
-    if ((e = launch_dot_diag(da, is_i8(o.form), st)) != hipSuccess)
-        return hip_fail(e);
     if ((e = launch_dot_final((const int64_t*)Dp, E, F, batch, S, beta, ncol, m, out,
                               std::max<int64_t>(plane_stride_out, 1), st)) != hipSuccess)
         return hip_fail(e);

@@ -175,6 +175,46 @@ struct DotArgs {
     int S, band, nbands;
 };
 hipError_t launch_dot_diag(const DotArgs& a, int form_int8, hipStream_t st);
+
+// Batched INT8 inner products with the digits cut in registers and
+// multiplied lane-wise (no digit planes): one workgroup of 64 nw threads per
+// pair and depth range [y chunk, (y+1) chunk); containers of SC digits (a
+// multiple of 8, S <= SC, within lane_sc_range(m)).
+struct LaneDotArgs {
+    const double* X;       // pair b, entry k, word w at X[w psx + b ldx + k]
+    int64_t ldx, psx;
+    const double* Y;
+    int64_t ldy, psy;
+    int64_t batch, n;
+    int64_t b0;            // first pair of a launch (set by the launcher)
+    int64_t chunk;         // depth per workgroup
+    int32_t* E;            // grid exponents (shared exponent + eoff): read, or
+    int32_t* F;            //   written in whole-pair mode
+    int32_t* ph;           // whole-pair mode: per pair, the largest and smallest frexp
+                           //   exponent of x's leading words, then of y's (4 planes of
+                           //   batch; INT_MIN / INT_MAX for none), for launch_pair_stats
+    unsigned long long* pm;  // whole-pair mode with mag: per pair, sum_k qx_k qy_k
+    int64_t* D;            // [S][batch] diagonal sums
+    int S, eoff;
+    int full;              // whole-pair mode: chunk >= n, exponents found here
+    int mag;               // whole-pair mode: also the magnitude certificate
+    int atomic;            // add into a zeroed D (several chunks per pair)
+};
+// the call statistics (kStatWords, reset by launch_exp_init) from the
+// per-pair exponents and magnitude products of whole-pair mode (pm may be
+// null: no magnitude certificate)
+hipError_t launch_pair_stats(const int32_t* ph, const unsigned long long* pm, int64_t batch, int32_t* stats,
+                             hipStream_t st);
+// SC range of the lane kernels for m words (0, 0 if none)
+void lane_sc_range(int m, int& lo, int& hi);
+// steps of 4 entries per lane whose int32 diagonal sums stay exact
+int64_t lane_steps_limit(int SC);
+hipError_t launch_dot_lane(const LaneDotArgs& a, int m, int SC, bool balanced, int nw, int64_t nch,
+                           hipStream_t st);
+hipError_t launch_dot_lane_m1(const LaneDotArgs& a, int SC, bool balanced, int nw, int64_t nch, hipStream_t st);
+hipError_t launch_dot_lane_m2(const LaneDotArgs& a, int SC, bool balanced, int nw, int64_t nch, hipStream_t st);
+hipError_t launch_dot_lane_m4(const LaneDotArgs& a, int SC, bool balanced, int nw, int64_t nch, hipStream_t st);
+hipError_t launch_dot_lane_m8(const LaneDotArgs& a, int SC, bool balanced, int nw, int64_t nch, hipStream_t st);
 hipError_t launch_fill_zero_i64(int64_t* p, int64_t n, hipStream_t st);
 // out_b (m words, plane stride pso) from the diagonal sums: exact fold and
 // greedy rounding, ncol 32-bit fold columns per pair

@@ -33,16 +33,6 @@
 namespace mdg {
 namespace {
 
-__device__ __forceinline__ int frexp_exponent(double x)
-{
-    const uint64_t b = (uint64_t)__double_as_longlong(x);
-    const int eb = (int)((b >> 52) & 0x7ff);
-    if (eb)
-        return eb - 1022;
-    const uint64_t f = b & ((1ull << 52) - 1);
-    return (64 - __clzll((long long)f)) - 1074;
-}
-
 __global__ void k_fill_zero(double* C, int m, int64_t M, int64_t N, int64_t ldc, int64_t psc)
 {
     const int64_t n = (int64_t)m * M * N;
