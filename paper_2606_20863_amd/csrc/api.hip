@@ -933,40 +933,27 @@ int md_dot_ex(int m, int64_t batch, int64_t n, const double* X, int64_t ldx, int
     // kernel finds the exponents and the statistics itself, and the
     // certificate follows it.
     if (Sgiven > 0 && plan_lane(o.form, m, Sgiven, batch, n, lp) && lp.nch == 1) {
-        if ((e = launch_exp_init(hiX, loX, 0, stats, st)) != hipSuccess)
-            return hip_fail(e);
         Choice ch;
         int rc = choose_slices(o, m, n, T, stats, st, ch, false, true);
         if (rc)
             return rc;
-        void *Dp, *pp;
-        rc = scr.get((size_t)ch.S * batch * sizeof(int64_t), &Dp);
-        if (rc)
-            return rc;
+        void* pp;
         rc = scr.get((size_t)batch * (4 * sizeof(int32_t) + sizeof(unsigned long long)), &pp);
         if (rc)
             return rc;
         unsigned long long* pm = (unsigned long long*)pp;
         int32_t* ph = (int32_t*)(pm + batch);
-        const int ncol = fold_columns(ch.beta, ch.S, round_up(n, kKcI8));
-        if ((size_t)ncol * 256 * sizeof(int64_t) > 160 * 1024)
-            return MD_ERANGE;
         LaneDotArgs la{opX.p, ldx, plane_stride_X, opY.p, ldy, plane_stride_Y, batch, n, 0, lp.chunk,
-                       E, F, ph, pm, (int64_t*)Dp, ch.S, eoff, 1, use_rho ? 1 : 0, 0};
+                       nullptr, nullptr, ph, pm, nullptr, out, std::max<int64_t>(plane_stride_out, 1),
+                       ch.S, eoff, 1, use_rho ? 1 : 0, 0};
         if (o.ev_gemm_begin && (e = hipEventRecord((hipEvent_t)o.ev_gemm_begin, st)) != hipSuccess)
             return hip_fail(e);
         if ((e = launch_dot_lane(la, m, lp.SC, o.form == MD_FORM_INT8_BAL, lp.nw, lp.nch, st)) != hipSuccess)
             return hip_fail(e);
-        if (o.force_S == 0) {
-            if ((e = launch_pair_stats(ph, use_rho ? pm : nullptr, batch, stats, st)) != hipSuccess)
-                return hip_fail(e);
-            if ((e = launch_cert(stats, o.form, n, T, m, ch.beta, ch.S, o.cert, st)) != hipSuccess)
-                return hip_fail(e);
-        }
-        if ((e = launch_dot_final((const int64_t*)Dp, E, F, batch, ch.S, ch.beta, ncol, m, out,
-                                  std::max<int64_t>(plane_stride_out, 1), st)) != hipSuccess)
-            return hip_fail(e);
         if (o.ev_gemm_end && (e = hipEventRecord((hipEvent_t)o.ev_gemm_end, st)) != hipSuccess)
+            return hip_fail(e);
+        if (o.force_S == 0 && (e = launch_cert(stats, o.form, n, T, m, ch.beta, ch.S, o.cert, st, ph,
+                                               use_rho ? pm : nullptr, batch)) != hipSuccess)
             return hip_fail(e);
         if (o.info)
             fill_info(o.info, ch, T, o.validate != 0);
@@ -1021,11 +1008,20 @@ int md_dot_ex(int m, int64_t batch, int64_t n, const double* X, int64_t ldx, int
         if (lp.nch > 1 && (e = launch_fill_zero_i64((int64_t*)Dp, (int64_t)S * batch, st)) != hipSuccess)
             return hip_fail(e);
         LaneDotArgs la{opX.p, ldx, plane_stride_X, opY.p, ldy, plane_stride_Y, batch, n, 0, lp.chunk,
-                       E, F, nullptr, nullptr, (int64_t*)Dp, S, eoff, 0, 0, lp.nch > 1 ? 1 : 0};
+                       E, F, nullptr, nullptr, (int64_t*)Dp, out, std::max<int64_t>(plane_stride_out, 1),
+                       S, eoff, 0, 0, lp.nch > 1 ? 1 : 0};
         if (o.ev_gemm_begin && (e = hipEventRecord((hipEvent_t)o.ev_gemm_begin, st)) != hipSuccess)
             return hip_fail(e);
         if ((e = launch_dot_lane(la, m, lp.SC, o.form == MD_FORM_INT8_BAL, lp.nw, lp.nch, st)) != hipSuccess)
             return hip_fail(e);
+        if (lp.nch == 1) {
+            // the lane kernel rounded every pair itself
+            if (o.ev_gemm_end && (e = hipEventRecord((hipEvent_t)o.ev_gemm_end, st)) != hipSuccess)
+                return hip_fail(e);
+            if (o.info)
+                fill_info(o.info, ch, T, o.validate != 0);
+            return MD_OK;
+        }
     } else {
         void *dX, *dY;
         rc = scr.get(digits_bytes(o.form, batch, n, S), &dX);

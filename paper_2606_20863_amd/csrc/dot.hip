@@ -361,80 +361,6 @@ hipError_t launch_mag_min_diag(const void* qX, const void* qY, int64_t batch, in
     return hipGetLastError();
 }
 
-namespace {
-
-// one workgroup: span maxima, extreme shared exponents and the smallest
-// magnitude product over the pairs (as launch_exp_final and the magnitude
-// kernels leave them)
-__global__ __launch_bounds__(256) void k_pair_stats(const int32_t* ph, const unsigned long long* pm,
-                                                    int64_t batch, int32_t* stats)
-{
-    __shared__ int32_t xs[4][7];
-    __shared__ unsigned long long xm[4];
-    int v[7] = {0, 0, INT_MIN, INT_MAX, INT_MIN, INT_MAX, 0};   // spans, extremes of x, of y
-    unsigned long long mn = ~0ull;
-    for (int64_t b = threadIdx.x; b < batch; b += 256) {
-        const int hx = ph[b], lx = ph[batch + b], hy = ph[2 * batch + b], ly = ph[3 * batch + b];
-        if (hx != INT_MIN) {
-            v[0] = max(v[0], hx - lx);
-            v[2] = max(v[2], hx);
-            v[3] = min(v[3], hx);
-        }
-        if (hy != INT_MIN) {
-            v[1] = max(v[1], hy - ly);
-            v[4] = max(v[4], hy);
-            v[5] = min(v[5], hy);
-        }
-        if (pm && pm[b] < mn)
-            mn = pm[b];
-    }
-    for (int o = 1; o < 64; o <<= 1) {
-        v[0] = max(v[0], __shfl_xor(v[0], o));
-        v[1] = max(v[1], __shfl_xor(v[1], o));
-        v[2] = max(v[2], __shfl_xor(v[2], o));
-        v[3] = min(v[3], __shfl_xor(v[3], o));
-        v[4] = max(v[4], __shfl_xor(v[4], o));
-        v[5] = min(v[5], __shfl_xor(v[5], o));
-        const unsigned long long u = __shfl_xor(mn, o);
-        mn = u < mn ? u : mn;
-    }
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        for (int i = 0; i < 6; ++i)
-            xs[w][i] = v[i];
-        xm[w] = mn;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int u = 1; u < 4; ++u) {
-            xs[0][0] = max(xs[0][0], xs[u][0]);
-            xs[0][1] = max(xs[0][1], xs[u][1]);
-            xs[0][2] = max(xs[0][2], xs[u][2]);
-            xs[0][3] = min(xs[0][3], xs[u][3]);
-            xs[0][4] = max(xs[0][4], xs[u][4]);
-            xs[0][5] = min(xs[0][5], xs[u][5]);
-            xm[0] = xm[u] < xm[0] ? xm[u] : xm[0];
-        }
-        stats[0] = xs[0][0];
-        stats[1] = xs[0][1];
-        stats[4] = xs[0][2];
-        stats[5] = xs[0][3];
-        stats[6] = xs[0][4];
-        stats[7] = xs[0][5];
-        if (pm)
-            *reinterpret_cast<unsigned long long*>(stats + 2) = xm[0];
-    }
-}
-
-}  // namespace
-
-hipError_t launch_pair_stats(const int32_t* ph, const unsigned long long* pm, int64_t batch, int32_t* stats,
-                             hipStream_t st)
-{
-    hipLaunchKernelGGL(k_pair_stats, dim3(1), dim3(256), 0, st, ph, pm, batch, stats);
-    return hipGetLastError();
-}
-
 void lane_sc_range(int m, int& lo, int& hi)
 {
     switch (m) {

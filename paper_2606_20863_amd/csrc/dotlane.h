@@ -21,14 +21,18 @@
 // nonzero leading words) and writes them with the pair's smallest leading
 // exponents and, with a.mag, its magnitude product of the ratio
 // certificate (sum_k qx_k qy_k, q the leading word's magnitude digit
-// floor(|x^(0)| 2^(7 - E))); launch_pair_stats reduces those to the call
-// statistics (plain stores here: atomics of every pair on the same few
-// words would queue behind each other).  Otherwise the exponents come from the exponent
+// floor(|x^(0)| 2^(7 - E))); the certificate kernel reduces those to the
+// call statistics (plain stores here: atomics of every pair on the same few
+// words would queue behind each other).  With one depth range per pair the
+// workgroup also folds its diagonal sums and rounds the pair's product
+// (lane_round); with several, a zeroed D takes 64-bit atomic adds and
+// launch_dot_final rounds.  Otherwise the exponents come from the exponent
 // pass, and with several depth ranges per pair the sums are added into a
 // zeroed D with 64-bit atomics.
 #pragma once
 
 #include "mdgemm_internal.h"
+#include "renorm.h"
 #include "split.h"
 
 #include <climits>
@@ -157,6 +161,35 @@ __device__ __forceinline__ void pair_exponents(const double* xb, const double* y
     }
 }
 
+// Exact fold X 2^(B (SC - S)) = sum_g D_g 2^(B (SC-1-g)) (D_g = 0 for g >= S:
+// the container's positions, so every column is a compile-time index) into
+// columns of 4 B bits, then greedy rounding of X 2^scale into m words.  A
+// diagonal sum goes in as its low column's worth and the rest (arithmetic),
+// each below 2^56 after its shift, so a column adds at most 8 of them.
+template <int SC, int B>
+__device__ __forceinline__ void lane_round(const int64_t* dsum, int scale, int m, double* out, int64_t pso)
+{
+    constexpr int CW = 4 * B, NC = (SC + 3) / 4 + 2;
+    constexpr int NL = (CW * (NC - 1) + 64 + 31) / 32;
+    int64_t x[NC];
+#pragma unroll
+    for (int j = 0; j < NC; ++j)
+        x[j] = 0;
+#pragma unroll
+    for (int g = 0; g < SC; ++g) {
+        const int e = SC - 1 - g, col = e >> 2;
+        const int64_t w = (int64_t)1 << (B * (e & 3));
+        const int64_t d = dsum[g];
+        x[col] += (int64_t)((uint64_t)d & ((1ull << CW) - 1)) * w;
+        x[col + 1] += (d >> CW) * w;
+    }
+    carry_cols<CW>(x);
+    uint32_t L[NL];
+    double sgn = to_limbs<CW>(x, L) ? -1.0 : 1.0;
+    for (int t = 0; t < m; ++t)
+        out[t * pso] = rn_next(L, sgn, scale);
+}
+
 template <int MW, int SC, bool BAL>
 __global__ __launch_bounds__(256) void k_dot_lane(LaneDotArgs a)
 {
@@ -166,6 +199,7 @@ __global__ __launch_bounds__(256) void k_dot_lane(LaneDotArgs a)
     __shared__ int32_t red[4 * 8 * 64];
     __shared__ int32_t xch[16];
     __shared__ unsigned long long mxch[4];
+    __shared__ int64_t dsum[SC];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, nw = blockDim.x >> 6;
     const int64_t b = a.b0 + blockIdx.x;
     const int64_t c0 = (int64_t)blockIdx.y * a.chunk;
@@ -180,8 +214,6 @@ __global__ __launch_bounds__(256) void k_dot_lane(LaneDotArgs a)
         Ex = (h[0] == INT_MIN ? 0 : h[0]) + a.eoff;
         Ey = (h[2] == INT_MIN ? 0 : h[2]) + a.eoff;
         if (t == 0) {
-            a.E[b] = Ex;
-            a.F[b] = Ey;
 #pragma unroll
             for (int i = 0; i < 4; ++i)
                 a.ph[i * a.batch + b] = h[i];
@@ -218,7 +250,7 @@ __global__ __launch_bounds__(256) void k_dot_lane(LaneDotArgs a)
     // words of the next NB entries of x and of y in flight: entry g (byte
     // g % 4 of step g / 4) lives in buffer g % NB, refilled with entry g + NB
     // as soon as it is cut
-    constexpr int NB = MW <= 4 ? 4 : 2;
+    constexpr int NB = MW <= 4 ? 4 : 1;
     double bx[NB][MW], by[NB][MW];
 #pragma unroll
     for (int g = 0; g < NB; ++g) {
@@ -285,15 +317,19 @@ __global__ __launch_bounds__(256) void k_dot_lane(LaneDotArgs a)
         }
         for (int o = 1; o < parts; o <<= 1)
             s += __shfl_xor(s, o);
-        if (part == 0 && g0 + gl < S) {
-            int64_t* d = a.D + (int64_t)(g0 + gl) * a.batch + b;
-            if (a.atomic)
-                atomicAdd(reinterpret_cast<unsigned long long*>(d), (unsigned long long)s);
-            else
-                *d = s;
+        if (part == 0) {
+            if (a.atomic) {
+                if (g0 + gl < S)
+                    atomicAdd(reinterpret_cast<unsigned long long*>(a.D + (int64_t)(g0 + gl) * a.batch + b),
+                              (unsigned long long)s);
+            } else {
+                dsum[g0 + gl] = g0 + gl < S ? s : 0;
+            }
         }
         __syncthreads();
     });
+    if (!a.atomic && t == 0)
+        lane_round<SC, bits>(dsum, Ex + Ey - bits * (SC + 1), MW, a.out + b, a.pso);
     if (mag) {
         unsigned long long mm = macc;
         for (int o = 1; o < 64; o <<= 1)

@@ -109,9 +109,13 @@ hipError_t launch_exp_final(const int32_t* hi, const int32_t* lo, int64_t R, int
                             int32_t* span_max, int32_t* ext, int32_t* dbgE, int eoff, hipStream_t st);
 // Certificate of a call run on a slice-count hint: from stats (complete on
 // the stream), writes an md_cert record to cert (device).  beta, S, band:
-// the parameters used; T the target, m the words, K the depth.
+// the parameters used; T the target, m the words, K the depth.  With ph,
+// stats are first made from the per-pair exponents and magnitude products
+// of whole-pair inner products (LaneDotArgs::ph, pm; pm null: no magnitude
+// certificate), every word written.
 hipError_t launch_cert(const int32_t* stats, int form, int64_t K, int T, int m, int beta, int S,
-                       void* cert, hipStream_t st);
+                       void* cert, hipStream_t st, const int32_t* ph = nullptr,
+                       const unsigned long long* pm = nullptr, int64_t batch = 0);
 
 // E[r] = Ein[r] + eoff where Ein[r] is at least the shared exponent (E[r] -
 // eoff; -1100 for a row whose leading words are all zero, hi[r] = INT_MIN
@@ -188,23 +192,20 @@ struct LaneDotArgs {
     int64_t batch, n;
     int64_t b0;            // first pair of a launch (set by the launcher)
     int64_t chunk;         // depth per workgroup
-    int32_t* E;            // grid exponents (shared exponent + eoff): read, or
-    int32_t* F;            //   written in whole-pair mode
+    const int32_t* E;      // grid exponents (shared exponent + eoff) of the
+    const int32_t* F;      //   exponent pass, unless whole-pair mode
     int32_t* ph;           // whole-pair mode: per pair, the largest and smallest frexp
                            //   exponent of x's leading words, then of y's (4 planes of
-                           //   batch; INT_MIN / INT_MAX for none), for launch_pair_stats
+                           //   batch; INT_MIN / INT_MAX for none), for launch_cert
     unsigned long long* pm;  // whole-pair mode with mag: per pair, sum_k qx_k qy_k
-    int64_t* D;            // [S][batch] diagonal sums
+    int64_t* D;            // [S][batch] diagonal sums (several chunks per pair)
+    double* out;           // one chunk per pair: out_b, word t at out[t pso + b]
+    int64_t pso;
     int S, eoff;
     int full;              // whole-pair mode: chunk >= n, exponents found here
     int mag;               // whole-pair mode: also the magnitude certificate
-    int atomic;            // add into a zeroed D (several chunks per pair)
+    int atomic;            // several chunks per pair: add into a zeroed D, no rounding
 };
-// the call statistics (kStatWords, reset by launch_exp_init) from the
-// per-pair exponents and magnitude products of whole-pair mode (pm may be
-// null: no magnitude certificate)
-hipError_t launch_pair_stats(const int32_t* ph, const unsigned long long* pm, int64_t batch, int32_t* stats,
-                             hipStream_t st);
 // SC range of the lane kernels for m words (0, 0 if none)
 void lane_sc_range(int m, int& lo, int& hi);
 // steps of 4 entries per lane whose int32 diagonal sums stay exact

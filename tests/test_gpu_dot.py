@@ -1,10 +1,15 @@
 """Batched m-double inner products on the GPU (the paper's experiment,
 Section 3) against the oracle, through the C ABI (needs an MI355X).
 
-* small ragged batches, m = 1, 2, 4, 8, 16, both slice forms, the library's
-  own rule: parameters equal the oracle's rule, every output word equal to
-  the oracle's method (greedy rounding makes the output unique), and every
-  product within 2^-T of sum_k |x_k||y_k| of the exact one;
+* small ragged batches, m = 1, 2, 4, 8, 16, all three slice forms, the
+  library's own rule: parameters within the oracle's budget, every output
+  word equal to the oracle's method (greedy rounding makes the output
+  unique), and every product within 2^-T of sum_k |x_k||y_k| of the exact
+  one;
+* the lane-wise INT8 kernels (digits cut in registers) where each pair's
+  depth is split over several workgroups, and where one workgroup takes a
+  whole pair and finds its exponents and certificate statistics itself
+  (hinted calls equal to the rule's, forced S equal to the oracle);
 * the paper's parameters (FP64 form, beta = 13, S = 4m) on the paper's bit
   pattern, m = 1..16: bit-exact against the oracle;
 * the inner products against the diagonal of the matrix product (a separate
@@ -57,7 +62,7 @@ def check_bound(X, Y, out, T):
 
 
 @pytest.mark.parametrize("m", [1, 2, 4, 8, 16])
-@pytest.mark.parametrize("form", ["int8", "fp64"])
+@pytest.mark.parametrize("form", ["int8bal", "int8", "fp64"])
 def test_dot_small_rule_bitexact(m, form):
     X, Y = random_batch(m, 37, 130, 100 + m)
     X[:, 5, :] = 0.0                      # an all-zero vector: its product is 0
@@ -65,7 +70,7 @@ def test_dot_small_rule_bitexact(m, form):
     out = host(out)
     rulecheck.check_info(info, form, 130, ox.TARGET_BITS[m], ox.dot_G(X, Y))
     beta, S = info["beta"], info["S"]
-    _, ref = ox.method_dot(X, Y, beta, S)
+    _, ref = ox.method_dot(X, Y, beta, S, balanced=form == "int8bal")
     np.testing.assert_array_equal(out, ref)
     assert np.all(out[:, 5] == 0.0)
     check_bound(X, Y, out, ox.TARGET_BITS[m])
@@ -116,6 +121,51 @@ def test_dot_paper_workload_sampled(m, nb, form):
     Cq = np.ascontiguousarray(out[:, pairs].T)
     _, absab, err = coracle.exact_entries(Xs, Ys, idx, idx, Cq)
     assert np.all(np.abs(err) / absab <= 2.0 ** -ox.TARGET_BITS[m])
+
+
+@pytest.mark.parametrize("form", ["int8bal", "int8"])
+@pytest.mark.parametrize("m", [1, 2, 4, 8])
+def test_dot_lane_depth_ranges(m, form):
+    """A few long pairs: the lane-wise INT8 kernels split each pair's depth
+    over several workgroups (64-bit atomic adds into the diagonal sums, then
+    the separate rounding kernel).  Ragged length; bit-exact against the
+    oracle's method at the library's S."""
+    X, Y = random_batch(m, 3, 9037, 700 + m)
+    X[:, 1, 4000:4100] = 0.0
+    out, info = md.dot_ex(dev(X), dev(Y), form=form)
+    _, ref = ox.method_dot(X, Y, info["beta"], info["S"], balanced=form == "int8bal")
+    np.testing.assert_array_equal(host(out), ref)
+
+
+@pytest.mark.parametrize("form", ["int8bal", "int8"])
+@pytest.mark.parametrize("rule", ["span", "rho"])
+@pytest.mark.parametrize("m", [2, 4, 8])
+def test_dot_whole_pair_calls(m, rule, form):
+    """Calls with a given S take each pair in one workgroup that finds the
+    exponents, the statistics and (ratio rule) the magnitude product itself
+    and rounds the pair's product: a hinted call equals the rule's call word
+    for word and certifies what the rule chose (S_min, G, G_span, G_rho); a
+    forced S equals the oracle's method at that S.  A zero vector and a run
+    of zero entries included."""
+    X, Y = random_batch(m, 70, 530, 800 + m)
+    X[:, 3, :] = 0.0
+    Y[:, 7, 100:200] = 0.0
+    out, info = md.dot_ex(dev(X), dev(Y), form=form, rule=rule)
+    cert = md.new_cert()
+    oh, _ = md.dot_ex(dev(X), dev(Y), form=form, rule=rule, s_hint=info["S"], cert=cert)
+    np.testing.assert_array_equal(host(oh), host(out))
+    c = md.read_cert(cert)
+    assert c["flags"] == 0 and c["S_min"] == info["S"]
+    assert (c["G"], c["G_span"], c["G_rho"]) == (info["G"], info["G_span"], info["G_rho"])
+    # a forced S above the rule's: one band up to 32, else the fewest bands
+    # of at most 16 that split it equally
+    S2 = next(c for c in range(info["S"] + 1, info["S"] + 17)
+              if c <= 32 or c % -(-c // 16) == 0)
+    of, i2 = md.dot_ex(dev(X), dev(Y), form=form, force_S=S2, force_beta=info["beta"])
+    assert i2["S"] == S2
+    _, ref = ox.method_dot(X, Y, info["beta"], S2, balanced=form == "int8bal")
+    np.testing.assert_array_equal(host(of), ref)
+    assert np.all(host(out)[:, 3] == 0.0)
 
 
 def test_dot_degenerate_sizes():
