@@ -960,30 +960,46 @@ int md_dot_ex(int m, int64_t batch, int64_t n, const double* X, int64_t ldx, int
         return MD_OK;
     }
 
-    if ((e = launch_exp_init(hiX, loX, batch, stats, st)) != hipSuccess) return hip_fail(e);
-    if ((e = launch_exp_init(hiY, loY, batch, nullptr, st)) != hipSuccess) return hip_fail(e);
-    if ((e = launch_exp_partial(opX, hiX, loX, st)) != hipSuccess) return hip_fail(e);
-    if ((e = launch_exp_partial(opY, hiY, loY, st)) != hipSuccess) return hip_fail(e);
-    if ((e = launch_exp_final(hiX, loX, batch, E, stats, stats + 4, nullptr, eoff, st)) != hipSuccess) return hip_fail(e);
-    if ((e = launch_exp_final(hiY, loY, batch, F, stats + 1, stats + 6, nullptr, eoff, st)) != hipSuccess) return hip_fail(e);
-
     const int64_t nrb = round_up(batch, kTile) / kRowBlock;
-    if (use_rho) {
-        // magnitude certificate over the pairs: min_b sum_k qX_bk qY_bk
-        const int64_t nkm = (n + kKcI8 - 1) / kKcI8;
-        void *qX, *qY;
-        int rc = scr.get(digits_bytes(MD_FORM_INT8, batch, n, 1), &qX);
+    if (is_i8(o.form) && m <= 8 && (batch >= 64 || n <= 16384)) {
+        // INT8 digits: exponents and magnitude products in one pass per pair
+        void* pp;
+        int rc = scr.get((size_t)batch * (4 * sizeof(int32_t) + sizeof(unsigned long long)), &pp);
         if (rc)
             return rc;
-        rc = scr.get(digits_bytes(MD_FORM_INT8, batch, n, 1), &qY);
-        if (rc)
-            return rc;
-        if ((e = launch_split_mag(opX, E, eoff, nrb, nkm, (int8_t*)qX, st)) != hipSuccess)
+        unsigned long long* pm = (unsigned long long*)pp;
+        int32_t* ph = (int32_t*)(pm + batch);
+        if ((e = launch_dot_pre(opX.p, ldx, opY.p, ldy, batch, n, eoff, E, F, ph, use_rho ? pm : nullptr, st)) !=
+            hipSuccess)
             return hip_fail(e);
-        if ((e = launch_split_mag(opY, F, eoff, nrb, nkm, (int8_t*)qY, st)) != hipSuccess)
+        if ((e = launch_cert(stats, o.form, n, T, m, 0, 0, nullptr, st, ph, use_rho ? pm : nullptr, batch)) !=
+            hipSuccess)
             return hip_fail(e);
-        if ((e = launch_mag_min_diag(qX, qY, batch, nkm, (unsigned long long*)(stats + 2), st)) != hipSuccess)
-            return hip_fail(e);
+    } else {
+        if ((e = launch_exp_init(hiX, loX, batch, stats, st)) != hipSuccess) return hip_fail(e);
+        if ((e = launch_exp_init(hiY, loY, batch, nullptr, st)) != hipSuccess) return hip_fail(e);
+        if ((e = launch_exp_partial(opX, hiX, loX, st)) != hipSuccess) return hip_fail(e);
+        if ((e = launch_exp_partial(opY, hiY, loY, st)) != hipSuccess) return hip_fail(e);
+        if ((e = launch_exp_final(hiX, loX, batch, E, stats, stats + 4, nullptr, eoff, st)) != hipSuccess) return hip_fail(e);
+        if ((e = launch_exp_final(hiY, loY, batch, F, stats + 1, stats + 6, nullptr, eoff, st)) != hipSuccess) return hip_fail(e);
+
+        if (use_rho) {
+            // magnitude certificate over the pairs: min_b sum_k qX_bk qY_bk
+            const int64_t nkm = (n + kKcI8 - 1) / kKcI8;
+            void *qX, *qY;
+            int rc = scr.get(digits_bytes(MD_FORM_INT8, batch, n, 1), &qX);
+            if (rc)
+                return rc;
+            rc = scr.get(digits_bytes(MD_FORM_INT8, batch, n, 1), &qY);
+            if (rc)
+                return rc;
+            if ((e = launch_split_mag(opX, E, eoff, nrb, nkm, (int8_t*)qX, st)) != hipSuccess)
+                return hip_fail(e);
+            if ((e = launch_split_mag(opY, F, eoff, nrb, nkm, (int8_t*)qY, st)) != hipSuccess)
+                return hip_fail(e);
+            if ((e = launch_mag_min_diag(qX, qY, batch, nkm, (unsigned long long*)(stats + 2), st)) != hipSuccess)
+                return hip_fail(e);
+        }
     }
     Choice ch;
     {

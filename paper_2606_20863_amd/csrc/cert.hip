@@ -109,7 +109,7 @@ __global__ __launch_bounds__(kCertThreads) void k_cert(int32_t* stats, int form,
         c.fmax = stats[6];
         c.fmin = stats[7];
     }
-    if (threadIdx.x != 0)
+    if (threadIdx.x != 0 || !cert)
         return;
     const int G_span = c.span_a + c.span_b + 2;
     const int G_rho = rule_rho_exponent(c.minP, K);   // -1: not computed or not certifiable

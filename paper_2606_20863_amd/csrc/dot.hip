@@ -361,6 +361,16 @@ hipError_t launch_mag_min_diag(const void* qX, const void* qY, int64_t batch, in
     return hipGetLastError();
 }
 
+hipError_t launch_dot_pre(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t batch, int64_t n,
+                          int eoff, int32_t* E, int32_t* F, int32_t* ph, unsigned long long* pm, hipStream_t st)
+{
+    if (batch > 0x7fffffff)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_dot_pre, dim3((unsigned)batch), dim3(256), 0, st, X, ldx, Y, ldy, batch, n, eoff, E,
+                       F, ph, pm);
+    return hipGetLastError();
+}
+
 void lane_sc_range(int m, int& lo, int& hi)
 {
     switch (m) {

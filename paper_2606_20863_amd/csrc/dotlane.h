@@ -122,7 +122,8 @@ __device__ __forceinline__ void pair_exponents(const double* xb, const double* y
 {
     const int t = threadIdx.x, nw = blockDim.x >> 6;
     int hx = INT_MIN, lx = INT_MAX, hy = INT_MIN, ly = INT_MAX;
-#pragma unroll 16
+    // every workgroup starts here at once: many loads per round trip
+#pragma unroll 32
     for (int64_t k = t; k < n; k += blockDim.x) {
         const double x = xb[k], y = yb[k];
         if (x != 0.0) {
@@ -343,6 +344,49 @@ __global__ __launch_bounds__(256) void k_dot_lane(LaneDotArgs a)
                 tot += mxch[w];
             a.pm[b] = tot;
         }
+    }
+}
+
+// The statistics pass of the slice rule for inner products, one workgroup
+// per pair: the pair's shared exponents (E, F: plus eoff) and its largest
+// and smallest leading exponents (ph, as whole-pair mode writes them), and
+// with pm its magnitude product sum_k qx_k qy_k.
+__global__ __launch_bounds__(256) void k_dot_pre(const double* X, int64_t ldx, const double* Y, int64_t ldy,
+                                                 int64_t batch, int64_t n, int eoff, int32_t* E, int32_t* F,
+                                                 int32_t* ph, unsigned long long* pm)
+{
+    __shared__ int32_t xch[16];
+    __shared__ unsigned long long mxch[4];
+    const int t = threadIdx.x, nw = blockDim.x >> 6;
+    const int64_t b = blockIdx.x;
+    const double* xb = X + b * ldx;
+    const double* yb = Y + b * ldy;
+    int h[4];
+    pair_exponents(xb, yb, n, h, xch);
+    const int Ex = h[0] == INT_MIN ? 0 : h[0], Ey = h[2] == INT_MIN ? 0 : h[2];
+    if (t == 0) {
+        E[b] = Ex + eoff;
+        F[b] = Ey + eoff;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            ph[i * batch + b] = h[i];
+    }
+    if (!pm)
+        return;
+    unsigned long long acc = 0;
+#pragma unroll 8
+    for (int64_t k = t; k < n; k += blockDim.x)
+        acc += (unsigned long long)(mag_digit(xb[k], Ex) * mag_digit(yb[k], Ey));
+    for (int o = 1; o < 64; o <<= 1)
+        acc += __shfl_xor(acc, o);
+    if ((t & 63) == 0)
+        mxch[t >> 6] = acc;
+    __syncthreads();
+    if (t == 0) {
+        unsigned long long tot = 0;
+        for (int w = 0; w < nw; ++w)
+            tot += mxch[w];
+        pm[b] = tot;
     }
 }
 

@@ -112,7 +112,7 @@ hipError_t launch_exp_final(const int32_t* hi, const int32_t* lo, int64_t R, int
 // the parameters used; T the target, m the words, K the depth.  With ph,
 // stats are first made from the per-pair exponents and magnitude products
 // of whole-pair inner products (LaneDotArgs::ph, pm; pm null: no magnitude
-// certificate), every word written.
+// certificate), every word written; a null cert then only makes stats.
 hipError_t launch_cert(const int32_t* stats, int form, int64_t K, int T, int m, int beta, int S,
                        void* cert, hipStream_t st, const int32_t* ph = nullptr,
                        const unsigned long long* pm = nullptr, int64_t batch = 0);
@@ -206,6 +206,12 @@ struct LaneDotArgs {
     int mag;               // whole-pair mode: also the magnitude certificate
     int atomic;            // several chunks per pair: add into a zeroed D, no rounding
 };
+// The slice rule's statistics pass of batched inner products, one
+// workgroup per pair: E, F (shared exponents plus eoff), the per-pair
+// leading exponents ph (as LaneDotArgs::ph) and, with pm, the magnitude
+// products; launch_cert with ph (and no record) reduces them to stats.
+hipError_t launch_dot_pre(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t batch, int64_t n,
+                          int eoff, int32_t* E, int32_t* F, int32_t* ph, unsigned long long* pm, hipStream_t st);
 // SC range of the lane kernels for m words (0, 0 if none)
 void lane_sc_range(int m, int& lo, int& hi);
 // steps of 4 entries per lane whose int32 diagonal sums stay exact

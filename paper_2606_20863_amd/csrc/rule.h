@@ -17,18 +17,21 @@
 
 namespace mdg {
 
+// smallest b with 2^b >= n (0 for n <= 1)
 __host__ __device__ inline int rule_ceil_log2(int64_t n)
 {
-    int b = 0;
-    while (((int64_t)1 << b) < n)
-        ++b;
-    return b;
+    return n <= 1 ? 0 : 64 - __builtin_clzll((unsigned long long)(n - 1));
 }
+
+// The searches below start at a lower bound of the answer (the log term is
+// at least 1), so that they take a few steps: the device runs them in one
+// thread.
 
 // smallest S with beta S >= T + G + ceil(log2(S + 2)) + 1
 __host__ __device__ inline int rule_slice_count(int beta, int T, int G)
 {
-    int S = 1;
+    const int64_t need0 = (int64_t)T + G + 2;
+    int S = need0 > beta ? (int)((need0 - 1) / beta) : 1;
     while ((int64_t)beta * S < (int64_t)T + G + rule_ceil_log2(S + 2) + 1)
         ++S;
     return S;
@@ -37,7 +40,8 @@ __host__ __device__ inline int rule_slice_count(int beta, int T, int G)
 // balanced digits: smallest S with 8 S >= T + G + ceil(log2(S + 3)) + 3
 __host__ __device__ inline int rule_slice_count_balanced(int T, int G)
 {
-    int S = 1;
+    const int64_t need0 = (int64_t)T + G + 5;
+    int S = need0 > 8 ? (int)((need0 - 1) / 8) : 1;
     while ((int64_t)8 * S < (int64_t)T + G + rule_ceil_log2(S + 3) + 3)
         ++S;
     return S;
@@ -66,7 +70,11 @@ __host__ __device__ inline int rule_rho_exponent(uint64_t minP, int64_t K)
     if (minP == 0 || minP == ~0ull)
         return -1;
     const unsigned __int128 target = ((unsigned __int128)K << 14) + 1;
-    int g = 0;
+    // minP 2^g < target for every g below bitlen(target) - bitlen(minP) - 1
+    const int lt = 128 - (int)(target >> 64 ? __builtin_clzll((unsigned long long)(target >> 64))
+                                            : 64 + __builtin_clzll((unsigned long long)target));
+    const int lm = 64 - __builtin_clzll(minP);
+    int g = lt - lm - 1 > 0 ? lt - lm - 1 : 0;
     while (((unsigned __int128)minP << g) < target)
         ++g;
     return g;

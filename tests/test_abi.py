@@ -118,6 +118,20 @@ def test_parameter_rule_against_budget(form, K, T, G):
     rulecheck.check_params(form, K, T, G, beta, S, kc, band)
 
 
+@pytest.mark.parametrize("form", ["int8", "int8bal", "fp64"])
+def test_parameter_rule_sweep(form):
+    """The slice count over a dense grid of targets and ratio exponents (the
+    searches start at a lower bound of the answer): within the budget's
+    rule at every point, equal to its minimum wherever one band holds it."""
+    for T in range(1, 900, 13):
+        for G in range(0, 260, 7):
+            try:
+                beta, S, kc, band = md.choose_params(form, 64, T, G)
+            except md.MDError:
+                continue
+            rulecheck.check_params(form, 64, T, G, beta, S, kc, band)
+
+
 def test_parameter_rule_headline():
     """The benchmark's parameters: quad-double, depth 4096, G = 3 (the
     magnitude certificate of its U(-1,1) inputs)."""

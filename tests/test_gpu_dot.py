@@ -125,12 +125,15 @@ def test_dot_paper_workload_sampled(m, nb, form):
 
 @pytest.mark.parametrize("form", ["int8bal", "int8"])
 @pytest.mark.parametrize("m", [1, 2, 4, 8])
-def test_dot_lane_depth_ranges(m, form):
+@pytest.mark.parametrize("nb,n", [(3, 9037), (2, 20011)])
+def test_dot_lane_depth_ranges(nb, n, m, form):
     """A few long pairs: the lane-wise INT8 kernels split each pair's depth
     over several workgroups (64-bit atomic adds into the diagonal sums, then
-    the separate rounding kernel).  Ragged length; bit-exact against the
+    the separate rounding kernel); the statistics from the per-pair pass
+    (3 pairs) or from the exponent and magnitude kernels over the whole
+    depth (2 pairs of 20,011).  Ragged lengths; bit-exact against the
     oracle's method at the library's S."""
-    X, Y = random_batch(m, 3, 9037, 700 + m)
+    X, Y = random_batch(m, nb, n, 700 + m + n)
     X[:, 1, 4000:4100] = 0.0
     out, info = md.dot_ex(dev(X), dev(Y), form=form)
     _, ref = ox.method_dot(X, Y, info["beta"], info["S"], balanced=form == "int8bal")
