@@ -56,15 +56,28 @@ PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 matrix peak, TFLOP/s
 
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_tri2_i8_qd4096_traffic.md")
-KERNEL_SOURCES = ("csrc/tri.h", "csrc/slice_common.h", "csrc/renorm.h", "csrc/mdgemm_internal.h",
-                  "csrc/tri8_s23_28.hip", "build.py")
+KERNEL_SOURCES = ("csrc/tri.h", "csrc/slice_common.h", "csrc/renorm.h", "csrc/tri8_s23_28.hip", "build.py")
 
 
 def kernel_fingerprint():
-    """sha256 over the sources of the slice contraction kernels, first 16 hex digits."""
+    """sha256 over the sources of the whole-triangle INT8 kernels, first 16
+    hex digits: their headers and unit, the build flags, and of the shared
+    internal header only what they take from it (its constants and the
+    kernel argument block), so that unrelated declarations added there keep
+    the stored counter readings valid."""
     import hashlib
     pkg = os.path.join(ROOT, "paper_2606_20863_amd")
     blob = b"".join(open(os.path.join(pkg, f), "rb").read() for f in KERNEL_SOURCES)
+    lines = open(os.path.join(pkg, "csrc/mdgemm_internal.h")).read().split("\n")
+    keep, inside = [], False
+    for ln in lines:
+        if ln.startswith("constexpr ") or ln.startswith("struct GemmArgs"):
+            keep.append(ln)
+            inside = ln.startswith("struct GemmArgs")
+        elif inside:
+            keep.append(ln)
+            inside = ln != "};"
+    blob += "\n".join(keep).encode()
     return hashlib.sha256(blob).hexdigest()[:16]
 
 
@@ -285,7 +298,7 @@ def paper_inner_products(md, torch, steps=5):
             "target_bits": "50 m", "results": rows}
 
 
-def other_configs(md, torch, steps=3):
+def other_configs(md, torch, steps=3, only=None):
     """The scope's other workloads, each timed as whole steps (inputs
     resident): double-double 64^3 (per-call microseconds, eager and as a
     HIP graph replay); quad-double 1024^3 forward; double-double 2048^3 and
@@ -295,7 +308,8 @@ def other_configs(md, torch, steps=3):
     (2 M N K per product), the slice contractions with their folds from HIP
     events, their fraction of the matrix-core peak (algorithmic work
     2 M N K S(S+1)/2 per product), and the largest error of 64 sampled
-    forward entries against the exact product (checked by the CPU leg)."""
+    entries against the exact product (checked by the CPU leg), of the
+    forward product and, with the adjoint, of both gradients."""
     import numpy as np
     import mdinputs
     hip, _ = hip_events(1)
@@ -312,9 +326,13 @@ def other_configs(md, torch, steps=3):
                   mdinputs.mdouble(r16, 16, (1024, 1024), ("log2uniform", 6.0)), None),
          False, ("int8bal", "int8", "fp64")),
     ]
-    res = {"dd64": small_case(md, torch)}
-    progress("workload dd64 done")
+    res = {}
+    if only is None or "dd64" in only:
+        res["dd64"] = small_case(md, torch)
+        progress("workload dd64 done")
     for name, label, make, adjoint, forms in cases:
+        if only is not None and name not in only:
+            continue
         Ah, Bh, Wh = make()
         A = torch.from_numpy(Ah).cuda()
         B = torch.from_numpy(Bh).cuda()
@@ -341,6 +359,10 @@ def other_configs(md, torch, steps=3):
                                           events=evs[st * len(calls) + q])
                     if q == 0:
                         C = Cq
+                    elif q == 1:
+                        dA = Cq
+                    else:
+                        dB = Cq
                     infos.append(info)
             torch.cuda.synchronize()
             ms = (time.perf_counter() - t0) * 1e3 / steps
@@ -355,9 +377,17 @@ def other_configs(md, torch, steps=3):
                          "contraction_fold_ms": round(kern, 4),
                          "frac_peak": round(ops / (kern * 1e-3) / 1e12 / peak, 4)}
             defer_error(row[form], "max_log2_err_sampled", Ah, Bh, C)
+            if adjoint:
+                # the gradients: dA = W B^T and dB = A^T W on 8 x 8 grids each
+                defer_error(row[form], "max_log2_err_dA_sampled", Wh,
+                            np.ascontiguousarray(np.transpose(Bh, (0, 2, 1))), dA)
+                defer_error(row[form], "max_log2_err_dB_sampled",
+                            np.ascontiguousarray(np.transpose(Ah, (0, 2, 1))), Wh, dB)
         res[name] = row
         progress(f"workload {name} done")
         del A, B, W, calls, C
+        if adjoint:
+            del dA, dB
         torch.cuda.empty_cache()
     return res
 
@@ -531,6 +561,8 @@ def main():
                     help="skip the paper's inner-product workload (m = 1..16)")
     ap.add_argument("--no-split", action="store_true",
                     help="skip the fixed-point depth split of the benchmark product")
+    ap.add_argument("--configs", default="",
+                    help="comma-separated subset of the other workloads (dd64, qd1024, dd2048, od1024, hd1024)")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the other workloads (qd1024, dd2048 and od1024 with the adjoint, hd1024)")
     ap.add_argument("--forms", default="int8bal,int8,fp64",
@@ -574,6 +606,11 @@ def main():
         out = {"metric": f"QD-GEMM 4096^3 effective GFLOP/s ({head} form only)",
                "ms_per_call": round(ms8, 4), "gemm_kernel_ms": round(kern8, 4), "S": info8["S"],
                "kernel": int8_kernel_name(info8, K)}
+        if args.configs:
+            # profiling runs of chosen workloads beside the one headline form
+            del A, B, C8
+            torch.cuda.empty_cache()
+            out["configs"] = other_configs(md, torch, only=args.configs.split(","))
         print(json.dumps(out))
         return
     sm = None
@@ -686,7 +723,7 @@ def main():
         if args.no_dot:
             del A, B, C8, C64
             torch.cuda.empty_cache()
-        out["configs"] = other_configs(md, torch)
+        out["configs"] = other_configs(md, torch, only=args.configs.split(",") if args.configs else None)
     # the CPU leg: every use of the oracle, after all GPU work
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(Ah, Bh, K)
