@@ -55,8 +55,9 @@ PEAK_INT8_TOPS = 5000.0      # MI355X dense INT8 matrix peak, TOP/s
 PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 matrix peak, TFLOP/s
 
 
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_tri2_i8_qd4096_traffic.md")
-KERNEL_SOURCES = ("csrc/tri.h", "csrc/slice_common.h", "csrc/renorm.h", "csrc/tri8_s23_28.hip", "build.py")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_tri2d_i8_qd4096_traffic.md")
+KERNEL_SOURCES = ("csrc/tri.h", "csrc/trid.h", "csrc/trid.hip", "csrc/slice_common.h", "csrc/renorm.h",
+                  "csrc/tri8_s23_28.hip", "build.py")
 
 
 def kernel_fingerprint():
@@ -84,11 +85,16 @@ def kernel_fingerprint():
 def int8_kernel_name(info, K):
     """The INT8 slice contraction kernel the library dispatches for these
     parameters (digit width beta = 7 or 8): the whole triangle (S <= 32)
-    with two row blocks per wave when the depth is one exactness chunk, else
-    one row block; bands of two row blocks per wave otherwise."""
+    with two row blocks per wave when the depth is one exactness chunk (for
+    balanced S = 27 the variant that shares A through LDS), else one row
+    block; two bands over the whole depth for S = 36..64; bands of two row
+    blocks per wave otherwise."""
     S, band, b = info["S"], info["band"], info["beta"]
     if band == S and S <= 32:
-        return f"k_tri2_i8<{S}, {b}>" if info["kc"] >= K else f"k_tri_i8<{S}, false, {b}>"
+        if info["kc"] < K:
+            return f"k_tri_i8<{S}, false, {b}>"
+        # the balanced headline slice count shares A through LDS (trid_shape)
+        return "k_tri2d_i8<27, 8, 9>" if (S, b) == (27, 8) else f"k_tri2_i8<{S}, {b}>"
     if 2 * band == S and S % 4 == 0 and 36 <= S <= 64:
         return f"k_duo_i8<{S}, {b}>"
     return f"k_band2_i8<{band}>"

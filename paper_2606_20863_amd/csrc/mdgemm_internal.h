@@ -154,6 +154,11 @@ hipError_t launch_tri_s29_32(const GemmArgs& a, hipStream_t st);
 hipError_t launch_tri8_s1_22(const GemmArgs& a, hipStream_t st);
 hipError_t launch_tri8_s23_28(const GemmArgs& a, hipStream_t st);
 hipError_t launch_tri8_s29_32(const GemmArgs& a, hipStream_t st);
+// whole-triangle kernels with the A fragments shared through LDS (one
+// exactness chunk, no debug dump or fixed-point output), for the (S, beta)
+// of trid_shape
+bool trid_shape(int S, int beta);
+hipError_t launch_trid(const GemmArgs& a, hipStream_t st);
 // two-band kernels (duo_shape, one exactness chunk, no debug dump or
 // fixed-point output), by digit width and range of S
 hipError_t launch_duo_s36_48(const GemmArgs& a, hipStream_t st);

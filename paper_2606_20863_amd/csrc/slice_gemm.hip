@@ -267,6 +267,8 @@ hipError_t launch_gemm_i8(const GemmArgs& a, hipStream_t st)
                 return hipErrorInvalidValue;
             return a.S <= 22 ? launch_trifix_s1_22(a, st) : launch_trifix_s23_32(a, st);
         }
+        if (a.kcc >= a.nkc && !a.dbgD && trid_shape(a.S, a.beta))
+            return launch_trid(a, st);
         if (a.beta == 8) {
             if (a.S <= 22)
                 return launch_tri8_s1_22(a, st);
