@@ -63,16 +63,16 @@ KERNEL_SOURCES = ("csrc/tri.h", "csrc/trid.h", "csrc/trid.hip", "csrc/slice_comm
 def kernel_fingerprint():
     """sha256 over the sources of the whole-triangle INT8 kernels, first 16
     hex digits: their headers and unit, the build flags, and of the shared
-    internal header only what they take from it (its constants and the
-    kernel argument block), so that unrelated declarations added there keep
-    the stored counter readings valid."""
+    internal header only what they take from it (its integer tiling
+    constants and the kernel argument block), so that unrelated
+    declarations added there keep the stored counter readings valid."""
     import hashlib
     pkg = os.path.join(ROOT, "paper_2606_20863_amd")
     blob = b"".join(open(os.path.join(pkg, f), "rb").read() for f in KERNEL_SOURCES)
     lines = open(os.path.join(pkg, "csrc/mdgemm_internal.h")).read().split("\n")
     keep, inside = [], False
     for ln in lines:
-        if ln.startswith("constexpr ") or ln.startswith("struct GemmArgs"):
+        if ln.startswith("constexpr int ") or ln.startswith("struct GemmArgs"):
             keep.append(ln)
             inside = ln.startswith("struct GemmArgs")
         elif inside:

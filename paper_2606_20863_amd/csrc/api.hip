@@ -492,7 +492,9 @@ bool plan_lane(int form, int m, int S, int64_t batch, int64_t n, LanePlan& p)
     if (lo == 0 || SC < lo || SC > hi)
         return false;
     p.SC = SC;
-    p.nw = batch >= 512 ? 2 : 4;
+    // many pairs: two waves per pair, else (and for single words, whose
+    // light steps leave the exponent scan more exposed) four
+    p.nw = batch >= 512 && m > 1 ? 2 : 4;
     const int64_t stepw = 256 * p.nw;
     const int64_t cap = stepw * lane_steps_limit(SC);
     const int64_t spread = std::min<int64_t>((1024 + batch - 1) / batch, (n + 4 * stepw - 1) / (4 * stepw));

@@ -62,29 +62,6 @@ __device__ __forceinline__ void lane_load(double (&w)[MW], const double* p, int6
     }
 }
 
-// magnitude digit of the ratio certificate: floor(|x| 2^(7 - Er)) in [0, 127]
-__device__ __forceinline__ uint32_t mag_digit(double x, int Er)
-{
-    uint64_t mant;
-    int ex;
-    decode(x, mant, ex);
-    return (uint32_t)field(mant, ex + 7 - Er, 127);
-}
-
-// The words in registers at this point of the program: an empty volatile
-// statement that takes and gives back every one.  Volatile statements and
-// loads keep their order, so a cut pinned this way is done before the loads
-// that follow it are issued (else the cuts may sink below every load of
-// the step, and all their words are live at once).
-template <int SC>
-__device__ __forceinline__ void pin(uint32_t (&xs)[SC], uint32_t& mx)
-{
-#pragma unroll
-    for (int s = 0; s < SC; ++s)
-        asm volatile("" : "+v"(xs[s]));
-    asm volatile("" : "+v"(mx));
-}
-
 // An entry's limbs in LDS: a lane's column of its wave's limb array (limb
 // i of lane l at [i][l]: 64 lanes' 8-byte limbs side by side, so the reads,
 // the clears and the adds of one limb index meet no bank twice; the adds

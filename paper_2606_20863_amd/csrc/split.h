@@ -65,6 +65,37 @@ __device__ __forceinline__ void limb_pair(const uint64_t (&mant)[MW], const int 
     }
 }
 
+// magnitude digit of the ratio certificate: floor(|x| 2^(7 - Er)) in [0, 127]
+// (|x| < 2^Er); branch-free, from the same decoding as place_word, which the
+// compiler shares with the word's placement
+__device__ __forceinline__ uint32_t mag_digit(double x, int Er)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, x);
+    const uint32_t bh = (uint32_t)(b >> 32);
+    const int eb = (int)(bh >> 20) & 0x7ff;
+    const uint32_t hid = eb < 1 ? 0u : 1u;
+    const uint64_t mant = ((uint64_t)((bh & 0xfffffu) | (hid << 20)) << 32) | (uint32_t)b;
+    const int e1 = eb > 1 ? eb : 1;                 // |x| = mant 2^(e1 - 1075)
+    const int t = Er + 1068 - e1;                   // floor(|x| 2^(7 - Er)) = mant >> t
+    const uint64_t down = mant >> (t > 63 ? 63 : (t < 0 ? 0 : t));
+    const uint64_t up = mant << (t < -63 ? 63 : (t > 0 ? 0 : -t));   // t < 0: tiny Er, subnormal x
+    return (uint32_t)(t >= 0 ? down : up) & 127u;
+}
+
+// The words in registers at this point of the program: an empty volatile
+// statement that takes and gives back every one.  Volatile statements and
+// loads keep their order, so a cut pinned this way is done before the loads
+// that follow it are issued (else the cuts may sink below every load of
+// the step, and all their words are live at once).
+template <int SC>
+__device__ __forceinline__ void pin(uint32_t (&xs)[SC], uint32_t& mx)
+{
+#pragma unroll
+    for (int s = 0; s < SC; ++s)
+        asm volatile("" : "+v"(xs[s]));
+    asm volatile("" : "+v"(mx));
+}
+
 // ---------------------------------------------------------------------------
 // Digits by word placement.
 //
