@@ -480,10 +480,39 @@ int md_choose_params(int form, int64_t K, int T, int G, int* beta, int* S, int* 
 struct LanePlan {
     int SC = 0, nw = 0;
     int64_t chunk = 0, nch = 0;
+    bool mma = false;   // the matrix-core kernel (digit positions on the tile rows)
 };
+
+// Batched inner products on the matrix cores for m = 16 (the lane kernels
+// stop at 8 words, and at S > 64 their S (S+1) / 2 byte products per four
+// entries outweigh the cut): two-wave workgroups of 256 entries per round,
+// about 1024 workgroups or one per pair, at most mma_depth_limit() entries
+// each.
+bool plan_mma(int form, int m, int S, int64_t batch, int64_t n, LanePlan& p)
+{
+    if (!is_i8(form) || n <= 0 || m != 16)
+        return false;
+    int lo, hi;
+    mma_sc_range(m, lo, hi);
+    const int SC = (S + 15) / 16 * 16;
+    if (lo == 0 || SC < lo || SC > hi)
+        return false;
+    p.SC = SC;
+    p.nw = 2;
+    p.mma = true;
+    constexpr int64_t round = 256;
+    const int64_t cap = mma_depth_limit();
+    const int64_t spread = std::min<int64_t>((1024 + batch - 1) / batch, (n + 4 * round - 1) / (4 * round));
+    const int64_t nch = std::max<int64_t>({(n + cap - 1) / cap, spread, 1});
+    p.chunk = round_up((n + nch - 1) / nch, round);
+    p.nch = (n + p.chunk - 1) / p.chunk;
+    return p.nch <= 65535;
+}
 
 bool plan_lane(int form, int m, int S, int64_t batch, int64_t n, LanePlan& p)
 {
+    if (plan_mma(form, m, S, batch, n, p))
+        return true;
     if (!is_i8(form) || n <= 0)
         return false;
     int lo, hi;
@@ -502,6 +531,13 @@ bool plan_lane(int form, int m, int S, int64_t batch, int64_t n, LanePlan& p)
     p.chunk = round_up((n + nch - 1) / nch, stepw);
     p.nch = (n + p.chunk - 1) / p.chunk;
     return p.nch <= 65535;
+}
+
+hipError_t launch_planned_dot(const LaneDotArgs& la, int m, const LanePlan& lp, bool balanced, hipStream_t st)
+{
+    if (lp.mma)
+        return launch_dot_mma(la, m, lp.SC, balanced, lp.nch, st);
+    return launch_dot_lane(la, m, lp.SC, balanced, lp.nw, lp.nch, st);
 }
 
 size_t md_dot_workspace_size(int form, int64_t batch, int64_t n, int S)
@@ -950,7 +986,7 @@ int md_dot_ex(int m, int64_t batch, int64_t n, const double* X, int64_t ldx, int
                        ch.S, eoff, 1, use_rho ? 1 : 0, 0};
         if (o.ev_gemm_begin && (e = hipEventRecord((hipEvent_t)o.ev_gemm_begin, st)) != hipSuccess)
             return hip_fail(e);
-        if ((e = launch_dot_lane(la, m, lp.SC, o.form == MD_FORM_INT8_BAL, lp.nw, lp.nch, st)) != hipSuccess)
+        if ((e = launch_planned_dot(la, m, lp, o.form == MD_FORM_INT8_BAL, st)) != hipSuccess)
             return hip_fail(e);
         if (o.ev_gemm_end && (e = hipEventRecord((hipEvent_t)o.ev_gemm_end, st)) != hipSuccess)
             return hip_fail(e);
@@ -963,7 +999,7 @@ int md_dot_ex(int m, int64_t batch, int64_t n, const double* X, int64_t ldx, int
     }
 
     const int64_t nrb = round_up(batch, kTile) / kRowBlock;
-    if (is_i8(o.form) && m <= 8 && (batch >= 64 || n <= 16384)) {
+    if (is_i8(o.form) && (m <= 8 || m == 16) && (batch >= 64 || n <= 16384)) {
         // INT8 digits: exponents and magnitude products in one pass per pair
         void* pp;
         int rc = scr.get((size_t)batch * (4 * sizeof(int32_t) + sizeof(unsigned long long)), &pp);
@@ -1030,7 +1066,7 @@ int md_dot_ex(int m, int64_t batch, int64_t n, const double* X, int64_t ldx, int
                        S, eoff, 0, 0, lp.nch > 1 ? 1 : 0};
         if (o.ev_gemm_begin && (e = hipEventRecord((hipEvent_t)o.ev_gemm_begin, st)) != hipSuccess)
             return hip_fail(e);
-        if ((e = launch_dot_lane(la, m, lp.SC, o.form == MD_FORM_INT8_BAL, lp.nw, lp.nch, st)) != hipSuccess)
+        if ((e = launch_planned_dot(la, m, lp, o.form == MD_FORM_INT8_BAL, st)) != hipSuccess)
             return hip_fail(e);
         if (lp.nch == 1) {
             // the lane kernel rounded every pair itself

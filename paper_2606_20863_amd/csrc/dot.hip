@@ -3,6 +3,7 @@
 // inner-product contraction and fold.
 #include "slice_common.h"
 #include "dotlane.h"
+#include "dotmma.h"
 
 #include <climits>
 
@@ -379,6 +380,31 @@ void lane_sc_range(int m, int& lo, int& hi)
     case 4: lo = 8; hi = 48; return;
     case 8: lo = 24; hi = 64; return;
     default: lo = hi = 0; return;
+    }
+}
+
+void mma_sc_range(int m, int& lo, int& hi)
+{
+    switch (m) {
+    case 4: lo = 16; hi = 48; return;
+    case 8: lo = 32; hi = 64; return;
+    case 16: lo = 80; hi = 128; return;
+    default: lo = hi = 0; return;
+    }
+}
+
+int64_t mma_depth_limit()
+{
+    return kMmaMaxDepth;
+}
+
+hipError_t launch_dot_mma(const LaneDotArgs& a, int m, int SC, bool balanced, int64_t nch, hipStream_t st)
+{
+    switch (m) {
+    case 4: return launch_dot_mma_m4(a, SC, balanced, nch, st);
+    case 8: return launch_dot_mma_m8(a, SC, balanced, nch, st);
+    case 16: return launch_dot_mma_m16(a, SC, balanced, nch, st);
+    default: return hipErrorInvalidValue;
     }
 }
 

@@ -6,10 +6,11 @@ Section 3) against the oracle, through the C ABI (needs an MI355X).
   word equal to the oracle's method (greedy rounding makes the output
   unique), and every product within 2^-T of sum_k |x_k||y_k| of the exact
   one;
-* the lane-wise INT8 kernels (digits cut in registers) where each pair's
-  depth is split over several workgroups, and where one workgroup takes a
-  whole pair and finds its exponents and certificate statistics itself
-  (hinted calls equal to the rule's, forced S equal to the oracle);
+* the lane-wise INT8 kernels (digits cut in registers, m <= 8) and the
+  matrix-core kernel (digits through LDS, m = 16) where each pair's depth
+  is split over several workgroups, and where one workgroup takes a whole
+  pair and finds its exponents and certificate statistics itself (hinted
+  calls equal to the rule's, forced S equal to the oracle);
 * the paper's parameters (FP64 form, beta = 13, S = 4m) on the paper's bit
   pattern, m = 1..16: bit-exact against the oracle;
 * the inner products against the diagonal of the matrix product (a separate
@@ -124,15 +125,16 @@ def test_dot_paper_workload_sampled(m, nb, form):
 
 
 @pytest.mark.parametrize("form", ["int8bal", "int8"])
-@pytest.mark.parametrize("m", [1, 2, 4, 8])
+@pytest.mark.parametrize("m", [1, 2, 4, 8, 16])
 @pytest.mark.parametrize("nb,n", [(3, 9037), (2, 20011)])
 def test_dot_lane_depth_ranges(nb, n, m, form):
-    """A few long pairs: the lane-wise INT8 kernels split each pair's depth
-    over several workgroups (64-bit atomic adds into the diagonal sums, then
-    the separate rounding kernel); the statistics from the per-pair pass
-    (3 pairs) or from the exponent and magnitude kernels over the whole
-    depth (2 pairs of 20,011).  Ragged lengths; bit-exact against the
-    oracle's method at the library's S."""
+    """A few long pairs: the lane-wise INT8 kernels (m <= 8) and the
+    matrix-core kernel (m = 16) split each pair's depth over several
+    workgroups (64-bit atomic adds into the diagonal sums, then the separate
+    rounding kernel); the statistics from the per-pair pass (3 pairs) or from
+    the exponent and magnitude kernels over the whole depth (2 pairs of
+    20,011).  Ragged lengths; bit-exact against the oracle's method at the
+    library's S."""
     X, Y = random_batch(m, nb, n, 700 + m + n)
     X[:, 1, 4000:4100] = 0.0
     out, info = md.dot_ex(dev(X), dev(Y), form=form)
@@ -142,7 +144,7 @@ def test_dot_lane_depth_ranges(nb, n, m, form):
 
 @pytest.mark.parametrize("form", ["int8bal", "int8"])
 @pytest.mark.parametrize("rule", ["span", "rho"])
-@pytest.mark.parametrize("m", [2, 4, 8])
+@pytest.mark.parametrize("m", [2, 4, 8, 16])
 def test_dot_whole_pair_calls(m, rule, form):
     """Calls with a given S take each pair in one workgroup that finds the
     exponents, the statistics and (ratio rule) the magnitude product itself
