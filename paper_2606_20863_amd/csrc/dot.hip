@@ -385,12 +385,8 @@ void lane_sc_range(int m, int& lo, int& hi)
 
 void mma_sc_range(int m, int& lo, int& hi)
 {
-    switch (m) {
-    case 4: lo = 16; hi = 48; return;
-    case 8: lo = 32; hi = 64; return;
-    case 16: lo = 80; hi = 128; return;
-    default: lo = hi = 0; return;
-    }
+    lo = m == 16 ? 80 : 0;
+    hi = m == 16 ? 128 : 0;
 }
 
 int64_t mma_depth_limit()
@@ -400,12 +396,9 @@ int64_t mma_depth_limit()
 
 hipError_t launch_dot_mma(const LaneDotArgs& a, int m, int SC, bool balanced, int64_t nch, hipStream_t st)
 {
-    switch (m) {
-    case 4: return launch_dot_mma_m4(a, SC, balanced, nch, st);
-    case 8: return launch_dot_mma_m8(a, SC, balanced, nch, st);
-    case 16: return launch_dot_mma_m16(a, SC, balanced, nch, st);
-    default: return hipErrorInvalidValue;
-    }
+    if (m != 16)
+        return hipErrorInvalidValue;
+    return launch_dot_mma_m16(a, SC, balanced, nch, st);
 }
 
 int64_t lane_steps_limit(int SC)
