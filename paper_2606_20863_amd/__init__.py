@@ -212,6 +212,44 @@ def read_cert(cert: torch.Tensor) -> dict:
     return MDCert.from_buffer_copy(raw).as_dict()
 
 
+# S of the last call per shape and options (keys below), for sizing the
+# scratch of the next one before the slice rule has run
+_S_SEEN: dict = {}
+
+
+def _auto_workspace(key, size_of_S, S, device, stream):
+    """Scratch for a call from torch's caching allocator: with it the library
+    allocates nothing and a call only queues kernels (its own pool's
+    stream-ordered allocation and release put work on the GPU's queue in
+    every call, 10-70 us of it measured per call).  Sized for S, else for
+    the S this shape and these options took last time; None when neither is
+    known (the library's pool serves that call)."""
+    if S <= 0:
+        S = _S_SEEN.get(key, 0)
+    if S <= 0:
+        return None
+    ws = torch.empty(int(size_of_S(S)), dtype=torch.uint8, device=device)
+    if stream is not None:
+        ws.record_stream(stream)
+    return ws
+
+
+def _run_with_scratch(call, opts: "MDOpts", ws, key, info: "MDInfo"):
+    """call() with ws as the workspace; a call whose slice rule chose a larger
+    S than ws holds stops with MD_ENOMEM before it writes any output, and
+    runs again on the library's pool.  Records the S taken under key."""
+    if ws is not None:
+        opts.workspace, opts.workspace_bytes = ctypes.c_void_p(ws.data_ptr()), ws.numel()
+    rc = call()
+    if rc == 5 and ws is not None:
+        opts.workspace, opts.workspace_bytes = None, 0
+        rc = call()
+    _check(rc, info)
+    if key is not None:
+        _S_SEEN[key] = info.S
+    return rc
+
+
 def _slice_opts(opts: "MDOpts", device, force_S, force_beta, s_hint, cert, workspace):
     opts.force_S = force_S
     opts.force_beta = force_beta
@@ -227,7 +265,7 @@ def _slice_opts(opts: "MDOpts", device, force_S, force_beta, s_hint, cert, works
 def gemm_ex(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None, *, transA=False,
             transB=False, form="fp64", rule="rho", target_bits=0, force_S=0, force_beta=0,
             debug=None, workspace: torch.Tensor | None = None, events=None, stream=None,
-            validate=False, s_hint=0, cert: torch.Tensor | None = None, noalloc=False):
+            validate=False, s_hint=0, cert: torch.Tensor | None = None, noalloc=False, pool=False):
     """C = op(A) op(B) in m-double arithmetic.
 
     A is (m, M, K) (or (m, K, M) with transA), B is (m, K, N) (or (m, N, K)
@@ -243,6 +281,8 @@ def gemm_ex(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None, *, 
     ``md_gemm_workspace_size`` bytes (the call then allocates nothing).
     ``noalloc``: call md_gemm_ex_noalloc (the library's own fixed scratch
     array, no workspace; C must then be given to allocate nothing at all).
+    Without a workspace the scratch comes from torch's caching allocator
+    (``_auto_workspace``); ``pool=True`` leaves it to the library's pool.
     """
     _check_planes(A, "A")
     _check_planes(B, "B")
@@ -292,10 +332,19 @@ def gemm_ex(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None, *, 
     if noalloc and workspace is not None:
         raise ValueError("md_gemm_ex_noalloc takes no workspace")
     fn = lib().md_gemm_ex_noalloc if noalloc else lib().md_gemm_ex
-    rc = fn(m, int(transA), int(transB), M, N, K, _ptr(A), lda, A.shape[1] * A.shape[2],
-            _ptr(B), ldb, B.shape[1] * B.shape[2], _ptr(C), N, M * N,
-            ctypes.byref(opts), _stream_handle(stream))
-    _check(rc, info)
+    sh = _stream_handle(stream)
+
+    def call():
+        return fn(m, int(transA), int(transB), M, N, K, _ptr(A), lda, A.shape[1] * A.shape[2],
+                  _ptr(B), ldb, B.shape[1] * B.shape[2], _ptr(C), N, M * N, ctypes.byref(opts), sh)
+
+    if workspace is None and not noalloc and not debug and not pool:
+        key = ("gemm", form, rule, target_bits, force_beta, m, M, N, K, bool(transA), bool(transB))
+        ws = _auto_workspace(key, lambda S: lib().md_gemm_workspace_size(_FORMS[form], M, N, K, S),
+                             force_S or s_hint, A.device, stream)
+        _run_with_scratch(call, opts, ws, key, info)
+    else:
+        _check(call(), info)
     return C, info.as_dict()
 
 
@@ -319,7 +368,7 @@ def gemm(A: torch.Tensor, B: torch.Tensor, form: str = "fp64", stream=None) -> t
 def dot_ex(X: torch.Tensor, Y: torch.Tensor, out: torch.Tensor | None = None, *, form="fp64",
            rule="rho", target_bits=0, force_S=0, force_beta=0, events=None, stream=None,
            validate=False, workspace: torch.Tensor | None = None, s_hint=0,
-           cert: torch.Tensor | None = None):
+           cert: torch.Tensor | None = None, pool=False):
     """Batched m-double inner products out_b = sum_k X[:, b, k] Y[:, b, k].
 
     X and Y are (m, batch, n) float64 planes on the HIP device (m = 1, 2, 4,
@@ -327,7 +376,7 @@ def dot_ex(X: torch.Tensor, Y: torch.Tensor, out: torch.Tensor | None = None, *,
     ``validate`` as in ``gemm_ex`` (events recorded around the contraction
     and the fold).  ``workspace``: a device byte buffer of at least
     ``md_dot_workspace_size`` bytes (the library then allocates nothing);
-    ``s_hint`` and ``cert`` as in ``gemm_ex``.
+    ``s_hint``, ``cert`` and ``pool`` as in ``gemm_ex``.
     """
     _check_planes(X, "X")
     _check_planes(Y, "Y")
@@ -351,9 +400,19 @@ def dot_ex(X: torch.Tensor, Y: torch.Tensor, out: torch.Tensor | None = None, *,
     if events is not None:
         opts.ev_gemm_begin = ctypes.c_void_p(events[0])
         opts.ev_gemm_end = ctypes.c_void_p(events[1])
-    rc = lib().md_dot_ex(m, batch, n, _ptr(X), n, batch * n, _ptr(Y), n, batch * n, _ptr(out), batch,
-                         ctypes.byref(opts), _stream_handle(stream))
-    _check(rc, info)
+    sh = _stream_handle(stream)
+
+    def call():
+        return lib().md_dot_ex(m, batch, n, _ptr(X), n, batch * n, _ptr(Y), n, batch * n, _ptr(out), batch,
+                               ctypes.byref(opts), sh)
+
+    if workspace is None and not pool:
+        key = ("dot", form, rule, target_bits, force_beta, m, batch, n)
+        ws = _auto_workspace(key, lambda S: lib().md_dot_workspace_size(_FORMS[form], batch, n, S),
+                             force_S or s_hint, X.device, stream)
+        _run_with_scratch(call, opts, ws, key, info)
+    else:
+        _check(call(), info)
     return out, info.as_dict()
 
 

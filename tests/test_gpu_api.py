@@ -106,3 +106,62 @@ def test_dot_caller_workspace(form):
     assert e.value.code == 5
     torch.cuda.synchronize()
     assert bool((keep == 3.0).all())
+
+
+@pytest.mark.parametrize("form", ["int8bal", "fp64"])
+def test_scratch_from_torch_equals_pool(form):
+    """Calls without a workspace take their scratch from torch's caching
+    allocator once the shape's S is known (a hint, or the S the same shape
+    and options took last time): the same words as calls on the library's
+    pool, for products and inner products, with the rule and on a hint.
+    When the rule then picks a larger S on the same shape (wider exponent
+    spans), the workspace sized for the last S is too small: the call stops
+    with MD_ENOMEM before writing an output and runs again on the pool, with
+    the pool's words."""
+    A, B = mdinputs.workload("qd1024", M=40, N=56, K=130)
+    ref, i1 = md.gemm_ex(dev(A), dev(B), form=form, pool=True)
+    ref = host(ref)
+    for _ in range(2):   # the first call records S, the second runs on torch's scratch
+        C, i2 = md.gemm_ex(dev(A), dev(B), form=form)
+        np.testing.assert_array_equal(host(C), ref)
+        assert i2["S"] == i1["S"]
+    cert = md.new_cert()
+    fb = i1["beta"] if form == "fp64" else 0   # the FP64 form's hint names its beta
+    Ch, _ = md.gemm_ex(dev(A), dev(B), form=form, s_hint=i1["S"], force_beta=fb, cert=cert)
+    np.testing.assert_array_equal(host(Ch), ref)
+    assert md.read_cert(cert)["flags"] == 0
+    # the span rule (S follows the exponent spans) on the same shape: the
+    # last S recorded, then wider spans in the rows of A
+    _, i1s = md.gemm_ex(dev(A), dev(B), form=form, rule="span")
+    A2 = A.copy()
+    A2[:, :, ::5] *= 2.0 ** -90
+    ref2, i3 = md.gemm_ex(dev(A2), dev(B), form=form, rule="span", pool=True)
+    assert i3["S"] > i1s["S"]
+    size = lambda S: md.lib().md_gemm_workspace_size(md._FORMS[form], 40, 56, 130, S)
+    assert size(i3["S"]) > size(i1s["S"])
+    C2, i4 = md.gemm_ex(dev(A2), dev(B), form=form, rule="span")
+    np.testing.assert_array_equal(host(C2), host(ref2))
+    assert i4["S"] == i3["S"]
+
+    r = np.random.Generator(np.random.PCG64(77))
+    X = mdinputs.mdouble(r, 4, (33, 700), ("log2uniform", 6.0))
+    Y = mdinputs.mdouble(r, 4, (33, 700), ("log2uniform", 6.0))
+    oref, j1 = md.dot_ex(dev(X), dev(Y), form=form, pool=True)
+    oref = host(oref)
+    for _ in range(2):
+        o, j2 = md.dot_ex(dev(X), dev(Y), form=form)
+        np.testing.assert_array_equal(host(o), oref)
+        assert j2["S"] == j1["S"]
+    oh, _ = md.dot_ex(dev(X), dev(Y), form=form, s_hint=j1["S"], force_beta=j1["beta"] if form == "fp64" else 0,
+                      cert=cert)
+    np.testing.assert_array_equal(host(oh), oref)
+    _, j1s = md.dot_ex(dev(X), dev(Y), form=form, rule="span")
+    X2 = X.copy()
+    X2[:, :, ::5] *= 2.0 ** -90
+    oref2, j3 = md.dot_ex(dev(X2), dev(Y), form=form, rule="span", pool=True)
+    assert j3["S"] > j1s["S"]
+    size = lambda S: md.lib().md_dot_workspace_size(md._FORMS[form], 33, 700, S)
+    assert size(j3["S"]) > size(j1s["S"])
+    o2, j4 = md.dot_ex(dev(X2), dev(Y), form=form, rule="span")
+    np.testing.assert_array_equal(host(o2), host(oref2))
+    assert j4["S"] == j3["S"]
