@@ -9,20 +9,23 @@
 // of a matrix instruction's outputs kept when the pairs are put on the tile
 // rows), and the digits never leave the workgroup.
 //
-// A workgroup of two waves takes one pair and a range of its depth, 256
-// entries per round: wave 0 cuts four entries of x per lane, wave 1 four of
-// y (word placement, four entries per 32-bit word, one per byte; the entry
-// of byte q of lane l is 64 q + l of the round), and each writes its digit
-// words to LDS, row s holding digit s of the round's entries.  After a
-// barrier each wave multiplies its half of the needed tiles over the four
-// 64-entry sub-blocks of the round: the fragment of tile row I in sub-block
-// j is, for lane L, the 16 bytes at words 16 j + 4 (L / 16) .. +3 of row
-// 16 I + L % 16, for x and for y alike, so the instruction pairs entry with
-// entry (whatever its order of the 64 entries inside).  Tile sums stay in
-// int32: each adds at most 2^14 per entry, and the host caps the depth per
-// workgroup at 65536 entries.  At the end the tiles go to an SC x SC int32
-// matrix in LDS (the digit rows' space), and thread g adds its anti-diagonal
-// in int64.  The rest is the lane kernel's: whole-pair mode (exponents found
+// A workgroup of two waves takes one pair and a range of its depth, 128
+// entries per round: wave 0 cuts two entries of x per lane, wave 1 two of y
+// (word placement, one entry per byte), and each writes its digits to LDS,
+// row s holding digit s of the round's entries, 32 words of four: lanes l
+// and l + 32 fill the low and the high half of word l % 32, so byte 2 h + q
+// of word c holds entry 64 q + 32 h + c.  After a barrier each wave
+// multiplies its half of the needed tiles over the round's two 64-entry
+// sub-blocks: the fragment of tile row I in sub-block j is, for lane L, the
+// 16 bytes at words 16 j + 4 (L / 16) .. +3 of row 16 I + L % 16, for x and
+// for y alike, so the instruction pairs entry with entry (whatever its order
+// of the 64 entries inside).  A wave's limb store lives in its own digit
+// rows (cleared at the start of a round, overwritten by the digits once the
+// cut has left it zero), so a workgroup holds about 34 KB of LDS and a CU
+// four workgroups.  Tile sums stay in int32: each adds at most 2^14 per
+// entry, and the host caps the depth per workgroup at 65536 entries.  At the
+// end every tile element goes into the int64 sum of its diagonal by an LDS
+// atomic.  The rest is the lane kernel's: whole-pair mode (exponents found
 // here, in-kernel rounding) or several depth ranges added into a zeroed D.
 #pragma once
 
@@ -33,8 +36,8 @@ namespace {
 
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kMmaRound = 256;   // entries per round
-constexpr int kMmaRow = 68;      // 32-bit words per digit row (64 and 4 of padding)
+constexpr int kMmaRound = 128;   // entries per round: two per lane
+constexpr int kMmaRow = 36;      // 32-bit words per digit row (32 and 4 of padding)
 constexpr int64_t kMmaMaxDepth = 65536;
 
 // the needed tiles (I, J), I + J <= NT - 1, by anti-diagonal, dealt
@@ -61,14 +64,14 @@ struct MmaTiles {
     }
 };
 
-// Wave W's tiles over the four sub-blocks of a round (xa, ya: this lane's
+// Wave W's tiles over the 64-entry sub-blocks of a round (xa, ya: this lane's
 // fragment bytes in row 0 of the x and y digit rows; every offset from
 // there a compile-time constant)
 template <int NT, int W>
 __device__ __forceinline__ void mma_round(i32x4 (&acc)[MmaTiles<NT>::SLOTS], const uint32_t* xa, const uint32_t* ya)
 {
     constexpr MmaTiles<NT> kT{};
-    unroll<4>([&](auto JJ) {
+    unroll<kMmaRound / 64>([&](auto JJ) {
         constexpr int j = decltype(JJ)::value;
         unroll<MmaTiles<NT>::SLOTS>([&](auto KK) {
             constexpr int k = decltype(KK)::value, I = kT.I[2 * k + W], J = kT.J[2 * k + W];
@@ -81,20 +84,22 @@ __device__ __forceinline__ void mma_round(i32x4 (&acc)[MmaTiles<NT>::SLOTS], con
     });
 }
 
-// wave W's tiles into the SC x SC matrix: tile (I, J) of the product, lane L
-// holds rows 16 I + 4 (L / 16) + r, column 16 J + L % 16
+// wave W's tile sums added into the diagonal sums dsum[g], g < S
 template <int NT, int W>
-__device__ __forceinline__ void mma_store(const i32x4 (&acc)[MmaTiles<NT>::SLOTS], int32_t* mat, int lane)
+__device__ __forceinline__ void mma_fold(const i32x4 (&acc)[MmaTiles<NT>::SLOTS], int64_t* dsum, int S, int lane)
 {
     constexpr MmaTiles<NT> kT{};
-    constexpr int SC = 16 * NT;
-    int32_t* m0 = mat + 4 * (lane >> 4) * SC + (lane & 15);
+    const int g0 = 4 * (lane >> 4) + (lane & 15);
     unroll<MmaTiles<NT>::SLOTS>([&](auto KK) {
         constexpr int k = decltype(KK)::value, I = kT.I[2 * k + W], J = kT.J[2 * k + W];
         if constexpr (I >= 0) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                m0[(16 * I + r) * SC + 16 * J] = acc[k][r];
+            for (int r = 0; r < 4; ++r) {
+                const int g = 16 * (I + J) + g0 + r;
+                if (g < S)
+                    atomicAdd(reinterpret_cast<unsigned long long*>(dsum + g),
+                              (unsigned long long)(int64_t)acc[k][r]);
+            }
         }
     });
 }
@@ -102,13 +107,12 @@ __device__ __forceinline__ void mma_store(const i32x4 (&acc)[MmaTiles<NT>::SLOTS
 template <int MW, int SC, bool BAL>
 __global__ __launch_bounds__(128) void k_dot_mma(LaneDotArgs a)
 {
-    static_assert(SC % 16 == 0 && SC >= 16 && SC <= 128, "whole tiles; one thread per anti-diagonal");
-    static_assert(SC * SC <= 2 * SC * kMmaRow, "the fold matrix fits in the digit rows");
+    static_assert(SC % 16 == 0 && SC >= 16 && SC <= 128, "whole tiles; one thread per diagonal");
     constexpr int NT = SC / 16;
     constexpr int SLOTS = MmaTiles<NT>::SLOTS;
     constexpr int NS = store_limbs<SC, BAL>();
+    static_assert(NS * 64 * 2 <= SC * kMmaRow, "a wave's limb store fits in its operand's digit rows");
     __shared__ __attribute__((aligned(16))) uint32_t dig[2][SC][kMmaRow];
-    __shared__ uint64_t limbs[2][NS][64];
     __shared__ uint32_t magw[2][64];
     __shared__ int32_t xch[16];
     __shared__ int64_t dsum[SC];
@@ -118,6 +122,8 @@ __global__ __launch_bounds__(128) void k_dot_mma(LaneDotArgs a)
     const int64_t c1 = c0 + a.chunk < a.n ? c0 + a.chunk : a.n;
     const double* xb = a.X + b * a.ldx;
     const double* yb = a.Y + b * a.ldy;
+    if (t < SC)
+        dsum[t] = 0;
 
     int Ex, Ey;
     if (a.full) {
@@ -145,10 +151,10 @@ __global__ __launch_bounds__(128) void k_dot_mma(LaneDotArgs a)
     const bool mag = a.mag != 0;
     const int64_t ps = wave == 0 ? a.psx : a.psy;
 
-    LdsLimbs L{&limbs[wave][0][lane]};
-#pragma unroll
-    for (int i = 0; i < NS; ++i)
-        L.col[i * 64] = 0;
+    // the wave's limb store inside its operand's digit rows: its limbs are
+    // zero again once the round's entries are cut, the digit words then
+    // overwrite them, and the next round clears them first
+    LdsLimbs L{reinterpret_cast<uint64_t*>(&dig[wave][0][0]) + lane};
     i32x4 acc[SLOTS];
 #pragma unroll
     for (int k = 0; k < SLOTS; ++k)
@@ -160,26 +166,32 @@ __global__ __launch_bounds__(128) void k_dot_mma(LaneDotArgs a)
     const int64_t lim = c1 - off;
     const int64_t elast = c1 - 1 - off;
     const double* p = (wave == 0 ? xb : yb) + off;
-    // the next NB entries' words in flight (entry g of the sequence: byte
-    // g % 4 of round g / 4, in buffer g % NB)
-    constexpr int NB = MW <= 4 ? 4 : (MW <= 8 ? 2 : 1);
+    // the next NB entries' words in flight (entry g of the lane's sequence:
+    // byte g % 2 of round g / 2, in buffer g % NB)
+    constexpr int NB = MW <= 4 ? 2 : 1;
     double bw[NB][MW];
 #pragma unroll
     for (int g = 0; g < NB; ++g)
-        lane_load(bw[g], p, ps, (int64_t)(g / 4) * kMmaRound + 64 * (g % 4), lim, elast);
+        lane_load(bw[g], p, ps, (int64_t)(g / 2) * kMmaRound + 64 * (g % 2), lim, elast);
 
-    // this lane's fragment words in the first row of each operand's digits
+    // this lane's fragment words in the first row of each operand's digits,
+    // and where its two digit bytes go: half lane / 32 of word lane % 32
     const uint32_t* xa = &dig[0][lane & 15][4 * (lane >> 4)];
     const uint32_t* ya = &dig[1][lane & 15][4 * (lane >> 4)];
+    uint16_t* own = reinterpret_cast<uint16_t*>(&dig[wave][0][lane & 31]) + (lane >> 5);
+    uint16_t* ownm = reinterpret_cast<uint16_t*>(&magw[wave][lane & 31]) + (lane >> 5);
     for (int64_t it = 0; it < nrounds; ++it) {
+#pragma unroll
+        for (int i = 0; i < NS; ++i)
+            L.col[i * 64] = 0;
         uint32_t xs[SC], mx = 0;
 #pragma unroll
         for (int s = 0; s < SC; ++s)
             xs[s] = 0;
         const int64_t e0 = it * kMmaRound;
-        unroll<4>([&](auto QQ) {
+        unroll<2>([&](auto QQ) {
             constexpr int q = decltype(QQ)::value, slot = q % NB;
-            const int64_t en = e0 + ((q + NB) / 4) * kMmaRound + 64 * ((q + NB) % 4);
+            const int64_t en = e0 + ((q + NB) / 2) * kMmaRound + 64 * ((q + NB) % 2);
             if (mag)
                 mx = byte_insert<q, 0>(mx, mag_digit(bw[slot][0], Er));
             lane_digits<q, MW, SC, BAL>(bw[slot], kn, pad, xs, L);
@@ -188,10 +200,10 @@ __global__ __launch_bounds__(128) void k_dot_mma(LaneDotArgs a)
         });
 #pragma unroll
         for (int s = 0; s < SC; ++s)
-            dig[wave][s][lane] = BAL ? xs[s] ^ 0x80808080u : xs[s];
-        magw[wave][lane] = mx;
+            own[2 * s * kMmaRow] = (uint16_t)(BAL ? xs[s] ^ 0x8080u : xs[s]);
+        *ownm = (uint16_t)mx;
         __syncthreads();
-        if (mag && wave == 0)
+        if (mag && wave == 0 && lane < 32)
             macc = __builtin_amdgcn_udot4(magw[0][lane], magw[1][lane], macc, false);
         if (wave == 0)
             mma_round<NT, 0>(acc, xa, ya);
@@ -200,32 +212,21 @@ __global__ __launch_bounds__(128) void k_dot_mma(LaneDotArgs a)
         __syncthreads();
     }
 
-    // the tiles into an SC x SC int32 matrix in the digit rows' space
-    int32_t* mat = reinterpret_cast<int32_t*>(&dig[0][0][0]);
+    // tile (I, J): lane L holds rows 16 I + 4 (L / 16) + r, column 16 J + L % 16,
+    // on diagonal 16 (I + J) + 4 (L / 16) + r + L % 16; sums of one
+    // diagonal meet in int64 by LDS atomics
     if (wave == 0)
-        mma_store<NT, 0>(acc, mat, lane);
+        mma_fold<NT, 0>(acc, dsum, S, lane);
     else
-        mma_store<NT, 1>(acc, mat, lane);
+        mma_fold<NT, 1>(acc, dsum, S, lane);
     __syncthreads();
-    // anti-diagonal g = s + u of the needed part (every element with
-    // s + u <= SC - 1 lies in a computed tile)
-    if (t < SC) {
-        const int g = t;
-        int64_t sum = 0;
-        if (g < S)
-            for (int s = 0; s <= g; ++s)
-                sum += mat[s * SC + g - s];
-        if (a.atomic) {
-            if (g < S)
-                atomicAdd(reinterpret_cast<unsigned long long*>(a.D + (int64_t)g * a.batch + b),
-                          (unsigned long long)sum);
-        } else {
-            dsum[g] = sum;
-        }
-    }
-    __syncthreads();
-    if (!a.atomic && t == 0)
+    if (a.atomic) {
+        if (t < S)
+            atomicAdd(reinterpret_cast<unsigned long long*>(a.D + (int64_t)t * a.batch + b),
+                      (unsigned long long)dsum[t]);
+    } else if (t == 0) {
         lane_round<SC, bits>(dsum, Ex + Ey - bits * (SC + 1), MW, a.out + b, a.pso);
+    }
     if (mag && wave == 0) {
         unsigned long long mm = macc;
         for (int o = 1; o < 64; o <<= 1)
