@@ -99,20 +99,35 @@ __device__ __forceinline__ void pair_exponents(const double* xb, const double* y
 {
     const int t = threadIdx.x, nw = blockDim.x >> 6;
     int hx = INT_MIN, lx = INT_MAX, hy = INT_MIN, ly = INT_MAX;
-    // every workgroup starts here at once: many loads per round trip
-#pragma unroll 32
-    for (int64_t k = t; k < n; k += blockDim.x) {
-        const double x = xb[k], y = yb[k];
-        if (x != 0.0) {
-            const int e = frexp_exponent(x);
-            hx = max(hx, e);
-            lx = min(lx, e);
+    auto take = [](double v, int& h, int& l) {
+        if (v != 0.0) {
+            const int e = frexp_exponent(v);
+            h = max(h, e);
+            l = min(l, e);
         }
-        if (y != 0.0) {
-            const int e = frexp_exponent(y);
-            hy = max(hy, e);
-            ly = min(ly, e);
+    };
+    // every workgroup starts here at once: many loads per round trip, two
+    // entries per 16-byte load where both vectors are 16-byte aligned (the
+    // odd last entry, or everything otherwise, one at a time)
+    int64_t k0 = 0;
+    if (((reinterpret_cast<uintptr_t>(xb) | reinterpret_cast<uintptr_t>(yb)) & 15) == 0) {
+        const int64_t n2 = n >> 1;
+        const double2* x2 = reinterpret_cast<const double2*>(xb);
+        const double2* y2 = reinterpret_cast<const double2*>(yb);
+#pragma unroll 16
+        for (int64_t i = t; i < n2; i += blockDim.x) {
+            const double2 xv = x2[i], yv = y2[i];
+            take(xv.x, hx, lx);
+            take(xv.y, hx, lx);
+            take(yv.x, hy, ly);
+            take(yv.y, hy, ly);
         }
+        k0 = 2 * n2;
+    }
+#pragma unroll 8
+    for (int64_t k = k0 + t; k < n; k += blockDim.x) {
+        take(xb[k], hx, lx);
+        take(yb[k], hy, ly);
     }
     for (int o = 1; o < 64; o <<= 1) {
         hx = max(hx, __shfl_xor(hx, o));
