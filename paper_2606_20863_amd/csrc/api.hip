@@ -483,14 +483,14 @@ struct LanePlan {
     bool mma = false;   // the matrix-core kernel (digit positions on the tile rows)
 };
 
-// Batched inner products on the matrix cores for m = 16 (the lane kernels
-// stop at 8 words, and at S > 64 their S (S+1) / 2 byte products per four
-// entries outweigh the cut): two-wave workgroups of 256 entries per round,
-// about 1024 workgroups or one per pair, at most mma_depth_limit() entries
-// each.
+// Batched inner products on the matrix cores for m = 8 and 16 (the lane
+// kernels' S (S+1) / 2 byte products per four entries outweigh the cut
+// there; at m <= 4 the lane kernels are faster): two-wave workgroups of 128
+// entries per round, about 1024 workgroups or one per pair, at most
+// mma_depth_limit() entries each.
 bool plan_mma(int form, int m, int S, int64_t batch, int64_t n, LanePlan& p)
 {
-    if (!is_i8(form) || n <= 0 || m != 16)
+    if (!is_i8(form) || n <= 0 || (m != 8 && m != 16))
         return false;
     int lo, hi;
     mma_sc_range(m, lo, hi);
@@ -500,7 +500,7 @@ bool plan_mma(int form, int m, int S, int64_t batch, int64_t n, LanePlan& p)
     p.SC = SC;
     p.nw = 2;
     p.mma = true;
-    constexpr int64_t round = 256;
+    constexpr int64_t round = 128;
     const int64_t cap = mma_depth_limit();
     const int64_t spread = std::min<int64_t>((1024 + batch - 1) / batch, (n + 4 * round - 1) / (4 * round));
     const int64_t nch = std::max<int64_t>({(n + cap - 1) / cap, spread, 1});

@@ -378,15 +378,14 @@ void lane_sc_range(int m, int& lo, int& hi)
     case 1: lo = 8; hi = 24; return;
     case 2: lo = 8; hi = 32; return;
     case 4: lo = 8; hi = 48; return;
-    case 8: lo = 24; hi = 64; return;
     default: lo = hi = 0; return;
     }
 }
 
 void mma_sc_range(int m, int& lo, int& hi)
 {
-    lo = m == 16 ? 80 : 0;
-    hi = m == 16 ? 128 : 0;
+    lo = m == 16 ? 80 : m == 8 ? 32 : 0;
+    hi = m == 16 ? 128 : m == 8 ? 64 : 0;
 }
 
 int64_t mma_depth_limit()
@@ -396,9 +395,11 @@ int64_t mma_depth_limit()
 
 hipError_t launch_dot_mma(const LaneDotArgs& a, int m, int SC, bool balanced, int64_t nch, hipStream_t st)
 {
-    if (m != 16)
-        return hipErrorInvalidValue;
-    return launch_dot_mma_m16(a, SC, balanced, nch, st);
+    switch (m) {
+    case 8: return launch_dot_mma_m8(a, SC, balanced, nch, st);
+    case 16: return launch_dot_mma_m16(a, SC, balanced, nch, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 int64_t lane_steps_limit(int SC)
@@ -413,7 +414,6 @@ hipError_t launch_dot_lane(const LaneDotArgs& a, int m, int SC, bool balanced, i
     case 1: return launch_dot_lane_m1(a, SC, balanced, nw, nch, st);
     case 2: return launch_dot_lane_m2(a, SC, balanced, nw, nch, st);
     case 4: return launch_dot_lane_m4(a, SC, balanced, nw, nch, st);
-    case 8: return launch_dot_lane_m8(a, SC, balanced, nw, nch, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -111,8 +111,12 @@ __global__ __launch_bounds__(128) void k_dot_mma(LaneDotArgs a)
     constexpr int NT = SC / 16;
     constexpr int SLOTS = MmaTiles<NT>::SLOTS;
     constexpr int NS = store_limbs<SC, BAL>();
-    static_assert(NS * 64 * 2 <= SC * kMmaRow, "a wave's limb store fits in its operand's digit rows");
+    // a wave's limb store inside its operand's digit rows where it fits
+    // (decided at compile time: the balanced containers of 32 digits or more,
+    // the sign-magnitude ones of 64 or more), else beside them
+    constexpr bool kInRows = NS * 64 * 2 <= SC * kMmaRow;
     __shared__ __attribute__((aligned(16))) uint32_t dig[2][SC][kMmaRow];
+    __shared__ uint64_t beside[2][kInRows ? 1 : NS][kInRows ? 1 : 64];
     __shared__ uint32_t magw[2][64];
     __shared__ int32_t xch[16];
     __shared__ int64_t dsum[SC];
@@ -154,7 +158,7 @@ __global__ __launch_bounds__(128) void k_dot_mma(LaneDotArgs a)
     // the wave's limb store inside its operand's digit rows: its limbs are
     // zero again once the round's entries are cut, the digit words then
     // overwrite them, and the next round clears them first
-    LdsLimbs L{reinterpret_cast<uint64_t*>(&dig[wave][0][0]) + lane};
+    LdsLimbs L{kInRows ? reinterpret_cast<uint64_t*>(&dig[wave][0][0]) + lane : &beside[wave][0][0] + lane};
     i32x4 acc[SLOTS];
 #pragma unroll
     for (int k = 0; k < SLOTS; ++k)

@@ -226,14 +226,14 @@ hipError_t launch_dot_lane(const LaneDotArgs& a, int m, int SC, bool balanced, i
 hipError_t launch_dot_lane_m1(const LaneDotArgs& a, int SC, bool balanced, int nw, int64_t nch, hipStream_t st);
 hipError_t launch_dot_lane_m2(const LaneDotArgs& a, int SC, bool balanced, int nw, int64_t nch, hipStream_t st);
 hipError_t launch_dot_lane_m4(const LaneDotArgs& a, int SC, bool balanced, int nw, int64_t nch, hipStream_t st);
-hipError_t launch_dot_lane_m8(const LaneDotArgs& a, int SC, bool balanced, int nw, int64_t nch, hipStream_t st);
 // The matrix-core kernels of batched inner products (digit positions on
-// the tile rows, entries on the depth; m = 16): SC range for m words (0, 0
+// the tile rows, entries on the depth; m = 8 and 16): SC range for m words (0, 0
 // if none), the depth a workgroup may take, and the launch (grid batch x
 // nch of two-wave workgroups; LaneDotArgs as for the lane kernels).
 void mma_sc_range(int m, int& lo, int& hi);
 int64_t mma_depth_limit();
 hipError_t launch_dot_mma(const LaneDotArgs& a, int m, int SC, bool balanced, int64_t nch, hipStream_t st);
+hipError_t launch_dot_mma_m8(const LaneDotArgs& a, int SC, bool balanced, int64_t nch, hipStream_t st);
 hipError_t launch_dot_mma_m16(const LaneDotArgs& a, int SC, bool balanced, int64_t nch, hipStream_t st);
 hipError_t launch_fill_zero_i64(int64_t* p, int64_t n, hipStream_t st);
 // out_b (m words, plane stride pso) from the diagonal sums: exact fold and

@@ -6,8 +6,8 @@ Section 3) against the oracle, through the C ABI (needs an MI355X).
   word equal to the oracle's method (greedy rounding makes the output
   unique), and every product within 2^-T of sum_k |x_k||y_k| of the exact
   one;
-* the lane-wise INT8 kernels (digits cut in registers, m <= 8) and the
-  matrix-core kernel (digits through LDS, m = 16) where each pair's depth
+* the lane-wise INT8 kernels (digits cut in registers, m <= 4) and the
+  matrix-core kernel (digits through LDS, m = 8 and 16) where each pair's depth
   is split over several workgroups, and where one workgroup takes a whole
   pair and finds its exponents and certificate statistics itself (hinted
   calls equal to the rule's, forced S equal to the oracle);
@@ -128,8 +128,8 @@ def test_dot_paper_workload_sampled(m, nb, form):
 @pytest.mark.parametrize("m", [1, 2, 4, 8, 16])
 @pytest.mark.parametrize("nb,n", [(3, 9037), (2, 20011)])
 def test_dot_lane_depth_ranges(nb, n, m, form):
-    """A few long pairs: the lane-wise INT8 kernels (m <= 8) and the
-    matrix-core kernel (m = 16) split each pair's depth over several
+    """A few long pairs: the lane-wise INT8 kernels (m <= 4) and the
+    matrix-core kernel (m = 8, 16) split each pair's depth over several
     workgroups (64-bit atomic adds into the diagonal sums, then the separate
     rounding kernel); the statistics from the per-pair pass (3 pairs) or from
     the exponent and magnitude kernels over the whole depth (2 pairs of
