@@ -246,6 +246,8 @@ def _run_with_scratch(call, opts: "MDOpts", ws, key, info: "MDInfo"):
         rc = call()
     _check(rc, info)
     if key is not None:
+        if len(_S_SEEN) >= 4096 and key not in _S_SEEN:
+            _S_SEEN.clear()   # bounded: a process that meets many shapes starts over
         _S_SEEN[key] = info.S
     return rc
 
