@@ -1,5 +1,6 @@
 // Batched INT8 inner products with the split in registers (the paper's
-// experiment, Section 3): a workgroup takes one pair and a range of its
+// experiment, Section 3; m = 1, 2, 4 words, the matrix-core kernel of
+// dotmma.h taking m = 8 and 16): a workgroup takes one pair and a range of its
 // depth; each lane cuts four entries of x and four of y into digits (four
 // entries per 32-bit word, one per byte, by word placement) and multiplies
 // them lane-wise with 4-way byte dot products, every pair of slices (s, t)
@@ -10,7 +11,7 @@
 // A lane's entries in step `it`: offsets it * 4 T + 256 w + 64 q + lane of
 // the workgroup's range (T threads, wave w, byte q), so every load of a
 // word is 512 contiguous bytes per wave.  The words of the next four
-// entries (two for m = 8) of x and of y are in flight while one is cut.  Diagonal sums
+// entries of x and of y are in flight while one is cut.  Diagonal sums
 // stay in int32 per lane: a step adds at most S 4-way products of digits
 // of magnitude <= 128, S 2^16, and the host caps the steps per lane so the
 // sums stay below 2^31 (lane_max_steps); the workgroup then adds its lanes
@@ -187,6 +188,7 @@ template <int MW, int SC, bool BAL>
 __global__ __launch_bounds__(256) void k_dot_lane(LaneDotArgs a)
 {
     static_assert(SC % 8 == 0 && SC <= 64, "diagonals reduced eight at a time, 8 per thread group");
+    static_assert(MW <= 4, "four entries' words in flight per operand");
     constexpr int NS = store_limbs<SC, BAL>();
     __shared__ uint64_t limbs[4][NS][64];
     __shared__ int32_t red[4 * 8 * 64];
@@ -243,7 +245,7 @@ __global__ __launch_bounds__(256) void k_dot_lane(LaneDotArgs a)
     // words of the next NB entries of x and of y in flight: entry g (byte
     // g % 4 of step g / 4) lives in buffer g % NB, refilled with entry g + NB
     // as soon as it is cut
-    constexpr int NB = MW <= 4 ? 4 : 1;
+    constexpr int NB = 4;
     double bx[NB][MW], by[NB][MW];
 #pragma unroll
     for (int g = 0; g < NB; ++g) {
