@@ -35,6 +35,7 @@
 #include "mdgemm_internal.h"
 #include "renorm.h"
 #include "split.h"
+#include "ldslimbs.h"
 
 #include <climits>
 
@@ -62,26 +63,6 @@ __device__ __forceinline__ void lane_load(double (&w)[MW], const double* p, int6
         w[i] = ok ? v : 0.0;
     }
 }
-
-// An entry's limbs in LDS: a lane's column of its wave's limb array (limb
-// i of lane l at [i][l]: 64 lanes' 8-byte limbs side by side, so the reads,
-// the clears and the adds of one limb index meet no bank twice; the adds
-// land on limbs that differ from lane to lane).  Only the lane itself
-// touches its column, so no barrier is needed; LDS operations of a wave
-// complete in order.
-struct LdsLimbs {
-    uint64_t* col;
-    __device__ __forceinline__ void add(int i, uint64_t v)
-    {
-        atomicAdd(reinterpret_cast<unsigned long long*>(col + i * 64), (unsigned long long)v);
-    }
-    __device__ __forceinline__ uint64_t take(int i)
-    {
-        const uint64_t v = col[i * 64];
-        col[i * 64] = 0;
-        return v;
-    }
-};
 
 template <int Q, int MW, int SC, bool BAL>
 __device__ __forceinline__ void lane_digits(const double (&w)[MW], int kn, int pad, uint32_t (&xs)[SC],

@@ -27,6 +27,7 @@
 // what S such digits reach.
 #include "mdgemm_internal.h"
 #include "split.h"
+#include "ldslimbs.h"
 
 #include <climits>
 
@@ -543,6 +544,89 @@ hipError_t launch_exp_set(const int32_t* Ein, const int32_t* hi, int64_t R, int 
 }
 
 // Entries per thread of the splits: fewer when an entry has more words.
+// INT8 split by word placement (the digits of split.h), m <= 4: the same
+// threads, entries and stores as k_split_i8 / k_split_i8bal with four
+// entries per thread, the four entries of a thread being the four bytes of
+// each digit word.  Each word's truncated significand is placed at its bit
+// position in the entry's integer (two LDS adds into at most two limbs)
+// instead of being cut at every limb, about 40% fewer instructions per
+// entry.  Digits in a container of SC >= S (the low SC - S zero); digit s
+// of the entry is container digit s, most significant first.
+template <int MW, int SC, bool BAL, bool DBG>
+__global__ __launch_bounds__(256) void k_split_place(Operand op, const int32_t* E, int S, int64_t nkc,
+                                                     int8_t* out, int32_t* dbg, int64_t rb0)
+{
+    constexpr int bits = BAL ? 8 : 7;
+    constexpr int NS = store_limbs<SC, BAL>();
+    __shared__ uint64_t limbs[4][NS][64];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int64_t rb = rb0 + blockIdx.y, kc = blockIdx.x;
+    const int byte0 = 4 * t;
+    const int L = byte0 >> 4;                 // fragment lane
+    const int64_t r = rb * kRowBlock + (L & 15);
+    const int64_t kbase = kc * kKcI8 + 16 * (L >> 4) + (byte0 & 15);
+    const bool row_ok = r < op.R;
+    const int Er = row_ok ? E[r] : 0;
+    const int kn = Er + 1075 - bits * S, pad = bits * (SC - S);
+
+    double x[4][MW];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t k = kbase + q;
+        const bool ok = row_ok && k < op.K;
+#pragma unroll
+        for (int w = 0; w < MW; ++w)
+            x[q][w] = ok ? op.p[w * op.ps + r * op.sr + k * op.sk] : 0.0;
+    }
+    LdsLimbs Ls{&limbs[wave][0][lane]};
+#pragma unroll
+    for (int i = 0; i < NS; ++i)
+        Ls.col[i * 64] = 0;
+    uint32_t xs[SC];
+#pragma unroll
+    for (int s = 0; s < SC; ++s)
+        xs[s] = 0;
+    unroll<4>([&](auto QQ) {
+        constexpr int q = decltype(QQ)::value;
+        if constexpr (BAL)
+            digits_bal<q, MW, SC>(x[q], kn, pad, xs, Ls);
+        else
+            digits_sm<q, MW, SC>(x[q], kn, pad, xs, Ls);
+    });
+    uint32_t* o = reinterpret_cast<uint32_t*>(out + ((rb * nkc + kc) * (int64_t)S) * 1024 + byte0);
+#pragma unroll
+    for (int s = 0; s < SC; ++s) {
+        if (s < S) {
+            const uint32_t v = BAL ? xs[s] ^ 0x80808080u : xs[s];
+            o[(int64_t)s * 256] = v;
+            if (DBG && row_ok) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (kbase + q < op.K)
+                        dbg[((int64_t)s * op.R + r) * op.K + kbase + q] = (int)(int8_t)(v >> (8 * q));
+            }
+        }
+    }
+}
+
+// the container for S: the smallest multiple of 8 from 8 to 48 holding it
+template <int MW, int SC, bool BAL>
+hipError_t split_place_sc(const Operand& op, const int32_t* E, int S, int64_t nkc, int8_t* out, int32_t* dbg,
+                          dim3 grid, int64_t y0, hipStream_t st)
+{
+    if constexpr (SC <= 48) {
+        if (S > SC)
+            return split_place_sc<MW, SC + 8, BAL>(op, E, S, nkc, out, dbg, grid, y0, st);
+        if (dbg)
+            hipLaunchKernelGGL((k_split_place<MW, SC, BAL, true>), grid, dim3(256), 0, st, op, E, S, nkc, out, dbg, y0);
+        else
+            hipLaunchKernelGGL((k_split_place<MW, SC, BAL, false>), grid, dim3(256), 0, st, op, E, S, nkc, out, dbg, y0);
+        return hipGetLastError();
+    } else {
+        return hipErrorInvalidValue;
+    }
+}
+
 constexpr int split_ept(int m) { return m <= 4 ? 4 : (m == 8 ? 2 : 1); }
 
 template <int MW>
@@ -552,9 +636,18 @@ hipError_t split_i8_m(const Operand& op, const int32_t* E, int S, int64_t nrb, i
     constexpr int EPT = split_ept(MW);
     if (nkc * (4 / EPT) > 0x7fffffff)
         return hipErrorInvalidValue;
+    // word placement where a container holds S (m <= 4, S <= 48)
+    constexpr bool kPlace = MW <= 4;
     // row blocks on the grid's second dimension, at most kMaxGridY per launch
     for (int64_t y0 = 0; y0 < nrb; y0 += kMaxGridY) {
         const dim3 grid((unsigned)(nkc * (4 / EPT)), (unsigned)std::min<int64_t>(nrb - y0, kMaxGridY));
+        if (kPlace && S >= 1 && S <= 48) {
+            const hipError_t e = balanced ? split_place_sc<MW, 8, true>(op, E, S, nkc, out, dbg, grid, y0, st)
+                                          : split_place_sc<MW, 8, false>(op, E, S, nkc, out, dbg, grid, y0, st);
+            if (e != hipSuccess)
+                return e;
+            continue;
+        }
         if (balanced) {
             if (dbg)
                 hipLaunchKernelGGL((k_split_i8bal<MW, EPT, true>), grid, dim3(256), 0, st, op, E, S, nkc, out, dbg, y0);
