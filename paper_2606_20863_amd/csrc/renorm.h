@@ -156,12 +156,45 @@ __device__ __forceinline__ double rn_step_aligned(uint32_t (&L)[NL], double& sgn
     return w;
 }
 
-// Greedy step on any limbs: aligned, then the fixed-place step, or the
-// general one where the unit would fall below 2^-1074.
+// Shift the limbs left by 53 bits (one limb and 21 bits, fixed places);
+// the caller has checked that no set bit lies above bit 32 NL - 54.
 template <int NL>
+__device__ __forceinline__ void shift_left_53(uint32_t (&L)[NL])
+{
+#pragma unroll
+    for (int k = NL - 1; k >= 0; --k)
+        L[k] = k >= 2 ? (L[k - 1] << 21) | (L[k - 2] >> 11) : (k == 1 ? L[0] << 21 : 0u);
+}
+
+// Greedy step on any limbs: aligned, then the fixed-place step, or the
+// general one where the unit would fall below 2^-1074.  A remainder left
+// by a step has no set bit above bit 32 NL - 54 (the step cleared its unit
+// and everything above), so it is first moved up by those 53 bits at fixed
+// places, and where its top bit then lies in the top limb, a shift by that
+// limb's leading zeros finishes the alignment without the limb network:
+// the same total shift as align_left's, so the same word.  FAST = false
+// keeps the limb network for every word (fewer live registers: for kernels
+// that round many outputs at once with little room left).
+template <int NL, bool FAST = true>
 __device__ __forceinline__ double rn_next(uint32_t (&L)[NL], double& sgn, int& scale)
 {
-    if (!align_left(L, scale))
+    static_assert(NL >= 3, "at least three limbs");
+    bool aligned = false;
+    if (FAST && L[NL - 1] == 0 && (L[NL - 2] >> 11) == 0) {
+        shift_left_53(L);
+        scale -= 53;
+        if (L[NL - 1] != 0) {
+            const int z = __builtin_clz(L[NL - 1]);
+#pragma unroll
+            for (int k = NL - 1; k >= 0; --k) {
+                const uint32_t lo = k ? L[k - 1] : 0u;
+                L[k] = z ? (L[k] << z) | (lo >> (32 - z)) : L[k];
+            }
+            scale -= z;
+            aligned = true;
+        }
+    }
+    if (!aligned && !align_left(L, scale))
         return 0.0;
     if (32 * NL - 53 + scale >= -1074)
         return rn_step_aligned(L, sgn, scale);

@@ -128,8 +128,9 @@ __device__ __forceinline__ void tri_fold(const v4i (&acc)[R][S], int64_t (&x)[4 
 // Greedy renormalisation of the lane's 4 R outputs, their steps interleaved.
 // FIX: instead, the exact integers as two's complement limb planes
 // (a.fixX[k * M N + i N + j], limbs past the register ones filled with the
-// sign) and their scales (a.fixScale[i N + j]).
-template <int S, int R, int B, bool FIX = false>
+// sign) and their scales (a.fixScale[i N + j]).  FAST: rn_next's fixed-place
+// alignment of the remainders (off where the kernel has no registers left).
+template <int S, int R, int B, bool FIX = false, bool FAST = true>
 __device__ __forceinline__ void tri_outputs(int64_t (&x)[4 * R][(Tri<S, B>::kCols)], const GemmArgs& a,
                                             int64_t rb0, int64_t cb, int lane)
 {
@@ -175,7 +176,7 @@ __device__ __forceinline__ void tri_outputs(int64_t (&x)[4 * R][(Tri<S, B>::kCol
     for (int t = 0; t < a.m; ++t) {
 #pragma unroll
         for (int n = 0; n < NO; ++n) {
-            const double wv = rn_next(L[n], sgn[n], scale[n]);
+            const double wv = rn_next<NL, FAST>(L[n], sgn[n], scale[n]);
             if (ok[n])
                 out[n][t * a.psc] = wv;
         }

@@ -29,8 +29,10 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2606_20863_amd", "csrc")
 
 # (S, digit bits) whose register layouts differ: (columns, limbs) =
-# (2, 3), (5, 6), (9, 9) for 28-bit columns, (3, 4), (8, 9) for 32-bit ones
-LAYOUTS = ((4, 7), (16, 7), (30, 7), (5, 8), (27, 8))
+# (2, 3), (5, 6), (9, 9), (16, 16) for 28-bit columns, (3, 4), (8, 9),
+# (15, 17) for 32-bit ones (the last two of each: octo-double widths, where
+# seven of eight words take the fixed-place alignment of a remainder)
+LAYOUTS = ((4, 7), (16, 7), (30, 7), (60, 7), (5, 8), (27, 8), (56, 8))
 
 DRIVER = r"""
 #define __device__
@@ -65,11 +67,13 @@ extern "C" int layout(int S, int B, int which)
         case 4: return lay<4, 7>(which);
         case 16: return lay<16, 7>(which);
         case 30: return lay<30, 7>(which);
+        case 60: return lay<60, 7>(which);
         }
     if (B == 8)
         switch (S) {
         case 5: return lay<5, 8>(which);
         case 27: return lay<27, 8>(which);
+        case 56: return lay<56, 8>(which);
         }
     return -1;
 }
@@ -81,11 +85,13 @@ extern "C" void renorm(int S, int B, const int64_t* cols, int scale, int m, doub
         case 4: run<4, 7>(cols, scale, m, out); break;
         case 16: run<16, 7>(cols, scale, m, out); break;
         case 30: run<30, 7>(cols, scale, m, out); break;
+        case 60: run<60, 7>(cols, scale, m, out); break;
         }
     if (B == 8)
         switch (S) {
         case 5: run<5, 8>(cols, scale, m, out); break;
         case 27: run<27, 8>(cols, scale, m, out); break;
+        case 56: run<56, 8>(cols, scale, m, out); break;
         }
 }
 """
