@@ -266,9 +266,10 @@ __global__ __launch_bounds__(256, 1) void k_duo_i8(GemmArgs a)
 #pragma unroll
     for (int n = 0; n < 8; ++n)
         carry_cols<Tri<S, B>::kCW>(x[n]);
-    // the register-file-bound two-band kernel keeps the limb network for
-    // every word (the remainders' fixed-place alignment spills here)
-    tri_outputs<S, 2, B, false, false>(x, a, w.rb, w.cb, w.lane);
+    // the register file is full here: the outputs' rounding steps
+    // interleave in groups of four (balanced digits) or two, so that the
+    // remainders' fixed-place alignment fits without spilling
+    tri_outputs<S, 2, B, false, true, B == 8 ? 4 : 2>(x, a, w.rb, w.cb, w.lane);
 }
 
 // Launch the two-band kernel for a.S in {LO, LO+4, ..., S}, B-bit digits.

@@ -173,8 +173,7 @@ __device__ __forceinline__ void shift_left_53(uint32_t (&L)[NL])
 // places, and where its top bit then lies in the top limb, a shift by that
 // limb's leading zeros finishes the alignment without the limb network:
 // the same total shift as align_left's, so the same word.  FAST = false
-// keeps the limb network for every word (fewer live registers: for kernels
-// that round many outputs at once with little room left).
+// keeps the limb network for every word (fewer live registers).
 template <int NL, bool FAST = true>
 __device__ __forceinline__ double rn_next(uint32_t (&L)[NL], double& sgn, int& scale)
 {

@@ -130,7 +130,8 @@ __device__ __forceinline__ void tri_fold(const v4i (&acc)[R][S], int64_t (&x)[4 
 // (a.fixX[k * M N + i N + j], limbs past the register ones filled with the
 // sign) and their scales (a.fixScale[i N + j]).  FAST: rn_next's fixed-place
 // alignment of the remainders (off where the kernel has no registers left).
-template <int S, int R, int B, bool FIX = false, bool FAST = true>
+// G: outputs whose steps interleave (groups of G one after the other).
+template <int S, int R, int B, bool FIX = false, bool FAST = true, int G = 4 * R>
 __device__ __forceinline__ void tri_outputs(int64_t (&x)[4 * R][(Tri<S, B>::kCols)], const GemmArgs& a,
                                             int64_t rb0, int64_t cb, int lane)
 {
@@ -173,14 +174,17 @@ __device__ __forceinline__ void tri_outputs(int64_t (&x)[4 * R][(Tri<S, B>::kCol
         }
         return;
     }
-    for (int t = 0; t < a.m; ++t) {
+    static_assert(NO % G == 0, "whole groups of outputs");
 #pragma unroll
-        for (int n = 0; n < NO; ++n) {
-            const double wv = rn_next<NL, FAST>(L[n], sgn[n], scale[n]);
-            if (ok[n])
-                out[n][t * a.psc] = wv;
+    for (int g0 = 0; g0 < NO; g0 += G)
+        for (int t = 0; t < a.m; ++t) {
+#pragma unroll
+            for (int n = g0; n < g0 + G; ++n) {
+                const double wv = rn_next<NL, FAST>(L[n], sgn[n], scale[n]);
+                if (ok[n])
+                    out[n][t * a.psc] = wv;
+            }
         }
-    }
 }
 
 // Load lead of the triangle kernels' A fragments, in matrix instructions.
