@@ -189,3 +189,22 @@ def test_dot_degenerate_sizes():
             out, info = md.dot_ex(dev(X), dev(Y), form=form)
             _, ref = ox.method_dot(X, Y, info["beta"], info["S"])
             np.testing.assert_array_equal(host(out), ref)
+
+
+@pytest.mark.parametrize("form", ["int8bal", "int8"])
+@pytest.mark.parametrize("m,S", [(8, 20), (8, 36), (8, 48), (8, 64), (16, 70), (16, 90), (16, 112), (16, 128)])
+def test_dot_matrix_core_containers(m, S, form):
+    """The matrix-core inner-product kernel in every container it is built
+    for (m = 8: 32, 48, 64 digits; m = 16: 80, 96, 112, 128), both digit
+    forms (the sign-magnitude limb store sits beside the digit rows in the
+    containers of 32 and 48), with S forced (one band up to 32, else equal
+    bands of at most 16), a ragged depth over several rounds and a zero
+    vector: every word equal to the oracle's method at that S."""
+    X, Y = random_batch(m, 5, 301, 900 + m + S)
+    X[:, 2, :] = 0.0
+    beta = 8 if form == "int8bal" else 7
+    out, info = md.dot_ex(dev(X), dev(Y), form=form, force_S=S, force_beta=beta)
+    assert info["S"] == S
+    _, ref = ox.method_dot(X, Y, beta, S, balanced=form == "int8bal")
+    np.testing.assert_array_equal(host(out), ref)
+    assert np.all(host(out)[:, 2] == 0.0)
