@@ -325,19 +325,77 @@ __global__ __launch_bounds__(256) void k_dot_lane(LaneDotArgs a)
 // The statistics pass of the slice rule for inner products, one workgroup
 // per pair: the pair's shared exponents (E, F: plus eoff) and its largest
 // and smallest leading exponents (ph, as whole-pair mode writes them), and
-// with pm its magnitude product sum_k qx_k qy_k.
+// with pm its magnitude product sum_k qx_k qy_k.  One read of the leading
+// words serves both (for the first kPreCache values of each thread and
+// operand): a value's frexp exponent e and top seven bits t = floor(|x|
+// 2^(7 - e)) stay in a register, and once the vector's exponent E is known
+// its magnitude digit floor(|x| 2^(7 - E)) is t >> (E - e) (a floor of a
+// floor by a power of two); values past the cache are read again.
+constexpr int kPreCache = 32;
+
+// (e + 2048) 2^8 + t, or 0 for a zero word; h, l: running largest and
+// smallest frexp exponent
+__device__ __forceinline__ uint32_t pre_pack(double x, int& h, int& l)
+{
+    if (x == 0.0)
+        return 0u;
+    const int e = frexp_exponent(x);
+    h = max(h, e);
+    l = min(l, e);
+    return ((uint32_t)(e + 2048) << 8) | mag_digit(x, e);
+}
+
+__device__ __forceinline__ uint32_t pre_digit(uint32_t c, int E)
+{
+    const int d = E - ((int)(c >> 8) - 2048);
+    return c == 0u || d > 7 ? 0u : (c & 255u) >> d;
+}
+
 __global__ __launch_bounds__(256) void k_dot_pre(const double* X, int64_t ldx, const double* Y, int64_t ldy,
                                                  int64_t batch, int64_t n, int eoff, int32_t* E, int32_t* F,
                                                  int32_t* ph, unsigned long long* pm)
 {
     __shared__ int32_t xch[16];
     __shared__ unsigned long long mxch[4];
-    const int t = threadIdx.x, nw = blockDim.x >> 6;
+    const int t = threadIdx.x;
     const int64_t b = blockIdx.x;
     const double* xb = X + b * ldx;
     const double* yb = Y + b * ldy;
-    int h[4];
-    pair_exponents(xb, yb, n, h, xch);
+    int hx = INT_MIN, lx = INT_MAX, hy = INT_MIN, ly = INT_MAX;
+    uint32_t cx[kPreCache], cy[kPreCache];
+#pragma unroll
+    for (int i = 0; i < kPreCache; ++i) {
+        const int64_t k = t + (int64_t)i * 256;
+        const bool ok = k < n;
+        const double x = ok ? xb[k] : 0.0, y = ok ? yb[k] : 0.0;
+        cx[i] = pre_pack(x, hx, lx);
+        cy[i] = pre_pack(y, hy, ly);
+    }
+    const int64_t k1 = (int64_t)kPreCache * 256;
+    for (int64_t k = k1 + t; k < n; k += 256) {
+        pre_pack(xb[k], hx, lx);
+        pre_pack(yb[k], hy, ly);
+    }
+    for (int o = 1; o < 64; o <<= 1) {
+        hx = max(hx, __shfl_xor(hx, o));
+        lx = min(lx, __shfl_xor(lx, o));
+        hy = max(hy, __shfl_xor(hy, o));
+        ly = min(ly, __shfl_xor(ly, o));
+    }
+    if ((t & 63) == 0) {
+        xch[4 * (t >> 6) + 0] = hx;
+        xch[4 * (t >> 6) + 1] = lx;
+        xch[4 * (t >> 6) + 2] = hy;
+        xch[4 * (t >> 6) + 3] = ly;
+    }
+    __syncthreads();
+    int h[4] = {INT_MIN, INT_MAX, INT_MIN, INT_MAX};
+    for (int w = 0; w < 4; ++w) {
+        h[0] = max(h[0], xch[4 * w + 0]);
+        h[1] = min(h[1], xch[4 * w + 1]);
+        h[2] = max(h[2], xch[4 * w + 2]);
+        h[3] = min(h[3], xch[4 * w + 3]);
+    }
     const int Ex = h[0] == INT_MIN ? 0 : h[0], Ey = h[2] == INT_MIN ? 0 : h[2];
     if (t == 0) {
         E[b] = Ex + eoff;
@@ -349,20 +407,18 @@ __global__ __launch_bounds__(256) void k_dot_pre(const double* X, int64_t ldx, c
     if (!pm)
         return;
     unsigned long long acc = 0;
-#pragma unroll 8
-    for (int64_t k = t; k < n; k += blockDim.x)
+#pragma unroll
+    for (int i = 0; i < kPreCache; ++i)
+        acc += (unsigned long long)(pre_digit(cx[i], Ex) * pre_digit(cy[i], Ey));
+    for (int64_t k = k1 + t; k < n; k += 256)
         acc += (unsigned long long)(mag_digit(xb[k], Ex) * mag_digit(yb[k], Ey));
     for (int o = 1; o < 64; o <<= 1)
         acc += __shfl_xor(acc, o);
     if ((t & 63) == 0)
         mxch[t >> 6] = acc;
     __syncthreads();
-    if (t == 0) {
-        unsigned long long tot = 0;
-        for (int w = 0; w < nw; ++w)
-            tot += mxch[w];
-        pm[b] = tot;
-    }
+    if (t == 0)
+        pm[b] = mxch[0] + mxch[1] + mxch[2] + mxch[3];
 }
 
 // SC in [LO, HI], a multiple of 8
