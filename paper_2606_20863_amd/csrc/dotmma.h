@@ -1,5 +1,5 @@
 // Batched INT8 inner products for many slices (the paper's experiment,
-// Section 3, at large m): the digits of x and of y as two matrices whose
+// Section 3, at m = 8 and 16): the digits of x and of y as two matrices whose
 // rows are the digit positions and whose columns are the entries, so that
 // one matrix product over the entries gives every sum of slice products
 // sum_k x_s[k] y_t[k] at once; the diagonal sums D_g of the method are the
@@ -20,9 +20,10 @@
 // 16 bytes at words 16 j + 4 (L / 16) .. +3 of row 16 I + L % 16, for x and
 // for y alike, so the instruction pairs entry with entry (whatever its order
 // of the 64 entries inside).  A wave's limb store lives in its own digit
-// rows (cleared at the start of a round, overwritten by the digits once the
-// cut has left it zero), so a workgroup holds about 34 KB of LDS and a CU
-// four workgroups.  Tile sums stay in int32: each adds at most 2^14 per
+// rows where they hold it (cleared at the start of a round, overwritten by
+// the digits once the cut has left it zero), else beside them: at SC = 112 a
+// workgroup holds about 34 KB of LDS and a CU four workgroups.  Tile sums
+// stay in int32: each adds at most 2^14 per
 // entry, and the host caps the depth per workgroup at 65536 entries.  At the
 // end every tile element goes into the int64 sum of its diagonal by an LDS
 // atomic.  The rest is the lane kernel's: whole-pair mode (exponents found
