@@ -699,13 +699,14 @@ int gemm_impl(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, co
     }
     md_debug* dbg = o.dbg;
     hipError_t e;
-    if ((e = launch_exp_init(hiA, loA, M, stats, st)) != hipSuccess) return hip_fail(e);
-    if ((e = launch_exp_init(hiB, loB, N, nullptr, st)) != hipSuccess) return hip_fail(e);
-    if ((e = launch_exp_partial(opA, hiA, loA, st)) != hipSuccess) return hip_fail(e);
-    if ((e = launch_exp_partial(opB, hiB, loB, st)) != hipSuccess) return hip_fail(e);
     const int eoff = grid_offset(o.form);
-    if ((e = launch_exp_final(hiA, loA, M, E, stats, stats + 4, dbg ? dbg->E : nullptr, eoff, st)) != hipSuccess) return hip_fail(e);
-    if ((e = launch_exp_final(hiB, loB, N, F, stats + 1, stats + 6, dbg ? dbg->F : nullptr, eoff, st)) != hipSuccess) return hip_fail(e);
+    // the exponent pass of both operands, one launch per step
+    ExpSide sa{opA, hiA, loA, E, dbg ? dbg->E : nullptr, stats, stats + 4, (opA.sr == 1 && opA.sk != 1) ? 1 : 0,
+               round_up(M, kTile) / kRowBlock, nullptr};
+    ExpSide sb{opB, hiB, loB, F, dbg ? dbg->F : nullptr, stats + 1, stats + 6, (opB.sr == 1 && opB.sk != 1) ? 1 : 0,
+               round_up(N, kTile) / kRowBlock, nullptr};
+    if ((e = launch_exp_pass2(sa, sb, stats, eoff, st)) != hipSuccess)
+        return hip_fail(e);
     if (E_in && (e = launch_exp_set(E_in, hiA, M, eoff, E, exp_flags, st)) != hipSuccess) return hip_fail(e);
     if (F_in && (e = launch_exp_set(F_in, hiB, N, eoff, F, exp_flags, st)) != hipSuccess) return hip_fail(e);
 
@@ -721,9 +722,9 @@ int gemm_impl(int m, int transA, int transB, int64_t M, int64_t N, int64_t K, co
         rc = scr.get(digits_bytes(MD_FORM_INT8, N, K, 1), &qB);
         if (rc)
             return rc;
-        if ((e = launch_split_mag(opA, E, eoff, round_up(M, kTile) / kRowBlock, nkm, (int8_t*)qA, st)) != hipSuccess)
-            return hip_fail(e);
-        if ((e = launch_split_mag(opB, F, eoff, round_up(N, kTile) / kRowBlock, nkm, (int8_t*)qB, st)) != hipSuccess)
+        sa.q = (int8_t*)qA;
+        sb.q = (int8_t*)qB;
+        if ((e = launch_split_mag2(sa, sb, eoff, nkm, st)) != hipSuccess)
             return hip_fail(e);
         if ((e = launch_mag_min(qA, qB, M, N, nkm, (unsigned long long*)(stats + 2), st)) != hipSuccess)
             return hip_fail(e);
@@ -1014,12 +1015,10 @@ int md_dot_ex(int m, int64_t batch, int64_t n, const double* X, int64_t ldx, int
             hipSuccess)
             return hip_fail(e);
     } else {
-        if ((e = launch_exp_init(hiX, loX, batch, stats, st)) != hipSuccess) return hip_fail(e);
-        if ((e = launch_exp_init(hiY, loY, batch, nullptr, st)) != hipSuccess) return hip_fail(e);
-        if ((e = launch_exp_partial(opX, hiX, loX, st)) != hipSuccess) return hip_fail(e);
-        if ((e = launch_exp_partial(opY, hiY, loY, st)) != hipSuccess) return hip_fail(e);
-        if ((e = launch_exp_final(hiX, loX, batch, E, stats, stats + 4, nullptr, eoff, st)) != hipSuccess) return hip_fail(e);
-        if ((e = launch_exp_final(hiY, loY, batch, F, stats + 1, stats + 6, nullptr, eoff, st)) != hipSuccess) return hip_fail(e);
+        ExpSide sx{opX, hiX, loX, E, nullptr, stats, stats + 4, (opX.sr == 1 && opX.sk != 1) ? 1 : 0, nrb, nullptr};
+        ExpSide sy{opY, hiY, loY, F, nullptr, stats + 1, stats + 6, (opY.sr == 1 && opY.sk != 1) ? 1 : 0, nrb, nullptr};
+        if ((e = launch_exp_pass2(sx, sy, stats, eoff, st)) != hipSuccess)
+            return hip_fail(e);
 
         if (use_rho) {
             // magnitude certificate over the pairs: min_b sum_k qX_bk qY_bk
@@ -1031,9 +1030,9 @@ int md_dot_ex(int m, int64_t batch, int64_t n, const double* X, int64_t ldx, int
             rc = scr.get(digits_bytes(MD_FORM_INT8, batch, n, 1), &qY);
             if (rc)
                 return rc;
-            if ((e = launch_split_mag(opX, E, eoff, nrb, nkm, (int8_t*)qX, st)) != hipSuccess)
-                return hip_fail(e);
-            if ((e = launch_split_mag(opY, F, eoff, nrb, nkm, (int8_t*)qY, st)) != hipSuccess)
+            sx.q = (int8_t*)qX;
+            sy.q = (int8_t*)qY;
+            if ((e = launch_split_mag2(sx, sy, eoff, nkm, st)) != hipSuccess)
                 return hip_fail(e);
             if ((e = launch_mag_min_diag(qX, qY, batch, nkm, (unsigned long long*)(stats + 2), st)) != hipSuccess)
                 return hip_fail(e);

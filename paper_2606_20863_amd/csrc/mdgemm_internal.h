@@ -102,6 +102,24 @@ hipError_t launch_fill_zero(double* C, int m, int64_t M, int64_t N, int64_t ldc,
 constexpr int kStatWords = 8;
 hipError_t launch_exp_init(int32_t* hi, int32_t* lo, int64_t R, int32_t* stats, hipStream_t st);
 hipError_t launch_exp_partial(const Operand& op, int32_t* hi, int32_t* lo, hipStream_t st);
+// Both operands of a product at once: the exponent pass (as launch_exp_init,
+// launch_exp_partial and launch_exp_final on each, stats laid out as they
+// fill it: span maxima in words 0 and 1, extreme shared exponents of A in 4
+// and 5, of B in 6 and 7) and the magnitude split (one INT8 slice of
+// leading-word magnitudes on the shared-exponent grids, the ratio
+// certificate's), in half the launches.
+struct ExpSide {
+    Operand op;
+    int32_t *hi, *lo;        // working maxima and minima, op.R each
+    int32_t* E;              // shared exponent + eoff per row
+    int32_t* dbgE;           // optional
+    int32_t *span_max, *ext;
+    int rows_fast;           // rows contiguous (op.sr == 1 and op.sk != 1)
+    int64_t nrb;             // row blocks of the magnitude split
+    int8_t* q;               // magnitude digits
+};
+hipError_t launch_exp_pass2(const ExpSide& a, const ExpSide& b, int32_t* stats, int eoff, hipStream_t st);
+hipError_t launch_split_mag2(const ExpSide& a, const ExpSide& b, int eoff, int64_t nkc, hipStream_t st);
 // E[r] = shared exponent + eoff (2 for the balanced INT8 digits, else 0);
 // dbgE gets the shared exponent itself; ext (optional) the largest and
 // smallest shared exponent of the rows with a nonzero leading word
@@ -131,16 +149,12 @@ hipError_t launch_split_i8(const Operand& op, int m, const int32_t* E, int S, in
 // OR of the input-precondition flags of every entry of op into *flags
 // (1 not finite, 2 not weakly nonoverlapping, 4 leading word out of range)
 hipError_t launch_validate(const Operand& op, int m, int32_t* flags, hipStream_t st);
-// one INT8 slice of leading-word magnitudes (ratio certificate); E holds
-// the shared exponent + eoff
-hipError_t launch_split_mag(const Operand& op, const int32_t* E, int eoff, int64_t nrb, int64_t nkc,
-                            int8_t* out, hipStream_t st);
 hipError_t launch_split_f64(const Operand& op, int m, const int32_t* E, int S, int beta,
                             int64_t nrb, int64_t nkc, double* out, int32_t* dbg, hipStream_t st);
 
 hipError_t launch_gemm_i8(const GemmArgs& a, hipStream_t st);
 // minP[0] = min over (i < M, j < N) of sum_k qA_ik qB_kj (must start at
-// UINT64_MAX); qA, qB from launch_split_mag, nkc depth fragments each.
+// UINT64_MAX); qA, qB from launch_split_mag2, nkc depth fragments each.
 hipError_t launch_mag_min(const void* qA, const void* qB, int64_t M, int64_t N, int64_t nkc,
                           unsigned long long* minP, hipStream_t st);
 hipError_t launch_gemm_f64(const GemmArgs& a, hipStream_t st);

@@ -72,14 +72,14 @@ __global__ void k_exp_init(int32_t* hi, int32_t* lo, int64_t R, int32_t* stats)
 constexpr int kExpRows = 16, kExpDepth = 256;
 constexpr int64_t kMaxGridY = 65535;   // blocks on a launch's second grid dimension
 
-__global__ __launch_bounds__(256) void k_exp_partial(Operand op, int32_t* hi, int32_t* lo,
-                                                     int rows_fast, int64_t depth)
+__device__ __forceinline__ void exp_partial_block(const Operand& op, int32_t* hi, int32_t* lo, int rows_fast,
+                                                  int64_t depth, int64_t bx, int64_t by)
 {
     const int t = threadIdx.x;
     const int tr = rows_fast ? (t & 15) : (t >> 4);
     const int tk = rows_fast ? (t >> 4) : (t & 15);
-    const int64_t r = (int64_t)blockIdx.x * kExpRows + tr;
-    const int64_t k0 = (int64_t)blockIdx.y * depth;
+    const int64_t r = bx * kExpRows + tr;
+    const int64_t k0 = by * depth;
     int h = INT_MIN, l = INT_MAX;
     if (r < op.R) {
         const double* p = op.p + r * op.sr;
@@ -114,15 +114,21 @@ __global__ __launch_bounds__(256) void k_exp_partial(Operand op, int32_t* hi, in
     }
 }
 
+__global__ __launch_bounds__(256) void k_exp_partial(Operand op, int32_t* hi, int32_t* lo,
+                                                     int rows_fast, int64_t depth)
+{
+    exp_partial_block(op, hi, lo, rows_fast, depth, blockIdx.x, blockIdx.y);
+}
+
 // E[r] = the shared exponent plus eoff (the digit grid's start); the debug
 // dump and the spans take the shared exponent itself.  ext (optional):
 // ext[0] and ext[1] take the largest and smallest shared exponent of the
 // rows with a nonzero leading word (wavefront-reduced, one atomic pair per
 // wave).
-__global__ void k_exp_final(const int32_t* hi, const int32_t* lo, int64_t R, int32_t* E,
-                            int32_t* span_max, int32_t* ext, int32_t* dbgE, int eoff)
+__device__ __forceinline__ void exp_final_rows(const int32_t* hi, const int32_t* lo, int64_t R, int32_t* E,
+                                               int32_t* span_max, int32_t* ext, int32_t* dbgE, int eoff,
+                                               int64_t r)
 {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int h = r < R ? hi[r] : INT_MIN;
     const int e = h == INT_MIN ? 0 : h;
     int span = h == INT_MIN ? 0 : h - lo[r];
@@ -144,6 +150,12 @@ __global__ void k_exp_final(const int32_t* hi, const int32_t* lo, int64_t R, int
             atomicMin(ext + 1, emin);
         }
     }
+}
+
+__global__ void k_exp_final(const int32_t* hi, const int32_t* lo, int64_t R, int32_t* E,
+                            int32_t* span_max, int32_t* ext, int32_t* dbgE, int eoff)
+{
+    exp_final_rows(hi, lo, R, E, span_max, ext, dbgE, eoff, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // Input preconditions of one entry (flags: 1 a word not finite, 2 not
@@ -354,11 +366,10 @@ __global__ __launch_bounds__(256) void k_split_i8bal(Operand op, const int32_t* 
 // in [0, 127] because |a^(0)| < 2^E_r; one slice in INT8 fragment order.
 // Nonoverlapping words give |a| >= |a^(0)| (1 - 2^-52) >= q 2^(E_r - 7) (1 - 2^-52).
 // E holds E_r + eoff.
-__global__ __launch_bounds__(256) void k_split_mag(Operand op, const int32_t* E, int eoff,
-                                                   int64_t nkc, int8_t* out, int64_t rb0)
+__device__ __forceinline__ void split_mag_block(const Operand& op, const int32_t* E, int eoff, int64_t nkc,
+                                                int8_t* out, int64_t rb, int64_t kc)
 {
     const int T = threadIdx.x;
-    const int64_t rb = rb0 + blockIdx.y, kc = blockIdx.x;
     const int L = T >> 2;
     const int64_t r = rb * kRowBlock + (L & 15);
     const int64_t kbase = kc * kKcI8 + 16 * (L >> 4) + 4 * (T & 3);
@@ -376,6 +387,57 @@ __global__ __launch_bounds__(256) void k_split_mag(Operand op, const int32_t* E,
         packed |= (uint32_t)v << (8 * q);
     }
     reinterpret_cast<uint32_t*>(out)[(rb * nkc + kc) * 256 + T] = packed;
+}
+
+
+// The exponent pass and the magnitude split of both operands of a product,
+// one launch per step instead of two (blockIdx.z: 0 for A, 1 for B; the
+// grid covers the larger operand, and each side's blocks past its own rows
+// do nothing): small products are bound by their launches.
+__global__ void k_exp_init2(ExpSide a, ExpSide b, int32_t* stats)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < a.op.R) {
+        a.hi[r] = INT_MIN;
+        a.lo[r] = INT_MAX;
+    } else if (r < a.op.R + b.op.R) {
+        b.hi[r - a.op.R] = INT_MIN;
+        b.lo[r - a.op.R] = INT_MAX;
+    }
+    if (r < 2)
+        stats[r] = 0;
+    if (r == 0)
+        *reinterpret_cast<unsigned long long*>(stats + 2) = ~0ull;
+    if (r < 4)   // largest and smallest shared exponents of A, then B
+        stats[4 + r] = (r & 1) ? INT_MAX : INT_MIN;
+}
+
+__global__ __launch_bounds__(256) void k_exp_partial2(ExpSide a, ExpSide b, int64_t depth)
+{
+    if (blockIdx.z == 0)
+        exp_partial_block(a.op, a.hi, a.lo, a.rows_fast, depth, blockIdx.x, blockIdx.y);
+    else
+        exp_partial_block(b.op, b.hi, b.lo, b.rows_fast, depth, blockIdx.x, blockIdx.y);
+}
+
+__global__ void k_exp_final2(ExpSide a, ExpSide b, int eoff)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (blockIdx.z == 0)
+        exp_final_rows(a.hi, a.lo, a.op.R, a.E, a.span_max, a.ext, a.dbgE, eoff, r);
+    else
+        exp_final_rows(b.hi, b.lo, b.op.R, b.E, b.span_max, b.ext, b.dbgE, eoff, r);
+}
+
+__global__ __launch_bounds__(256) void k_split_mag2(ExpSide a, ExpSide b, int eoff, int64_t nkc, int64_t rb0)
+{
+    const int64_t rb = rb0 + blockIdx.y;
+    if (blockIdx.z == 0) {
+        if (rb < a.nrb)
+            split_mag_block(a.op, a.E, eoff, nkc, a.q, rb, blockIdx.x);
+    } else if (rb < b.nrb) {
+        split_mag_block(b.op, b.E, eoff, nkc, b.q, rb, blockIdx.x);
+    }
 }
 
 // Store of EPT consecutive digit doubles.
@@ -510,6 +572,48 @@ hipError_t launch_exp_final(const int32_t* hi, const int32_t* lo, int64_t R, int
     hipLaunchKernelGGL(k_exp_final, dim3((unsigned)blocks), dim3(256), 0, st, hi, lo, R, E,
                        span_max, ext, dbgE, eoff);
     return hipGetLastError();
+}
+
+hipError_t launch_exp_pass2(const ExpSide& a, const ExpSide& b, int32_t* stats, int eoff, hipStream_t st)
+{
+    if (a.op.K != b.op.K)
+        return hipErrorInvalidValue;
+    const int64_t R = std::max(a.op.R, b.op.R);
+    hipLaunchKernelGGL(k_exp_init2, dim3((unsigned)std::max<int64_t>((a.op.R + b.op.R + 255) / 256, 1)), dim3(256),
+                       0, st, a, b, stats);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    if (a.op.K > 0) {
+        int64_t depth = kExpDepth;
+        while ((a.op.K + depth - 1) / depth > kMaxGridY)
+            depth *= 2;
+        const int64_t gx = std::max<int64_t>((R + kExpRows - 1) / kExpRows, 1);
+        if (gx > 0x7fffffff)
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_exp_partial2, dim3((unsigned)gx, (unsigned)((a.op.K + depth - 1) / depth), 2),
+                           dim3(256), 0, st, a, b, depth);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
+    }
+    hipLaunchKernelGGL(k_exp_final2, dim3((unsigned)std::max<int64_t>((R + 255) / 256, 1), 1, 2), dim3(256), 0, st,
+                       a, b, eoff);
+    return hipGetLastError();
+}
+
+hipError_t launch_split_mag2(const ExpSide& a, const ExpSide& b, int eoff, int64_t nkc, hipStream_t st)
+{
+    if (nkc > 0x7fffffff)
+        return hipErrorInvalidValue;
+    const int64_t nrb = std::max(a.nrb, b.nrb);
+    for (int64_t y0 = 0; y0 < nrb; y0 += kMaxGridY) {
+        const dim3 grid((unsigned)nkc, (unsigned)std::min<int64_t>(nrb - y0, kMaxGridY), 2);
+        hipLaunchKernelGGL(k_split_mag2, grid, dim3(256), 0, st, a, b, eoff, nkc, y0);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
 }
 
 // Caller-given shared exponents: E[r] (the data's own + eoff) becomes
@@ -698,21 +802,6 @@ hipError_t launch_validate(const Operand& op, int m, int32_t* flags, hipStream_t
     case 16: return validate_m<16>(op, flags, st);
     default: return hipErrorInvalidValue;
     }
-}
-
-hipError_t launch_split_mag(const Operand& op, const int32_t* E, int eoff, int64_t nrb, int64_t nkc,
-                            int8_t* out, hipStream_t st)
-{
-    if (nkc > 0x7fffffff)
-        return hipErrorInvalidValue;
-    for (int64_t y0 = 0; y0 < nrb; y0 += kMaxGridY) {
-        dim3 grid((unsigned)nkc, (unsigned)std::min<int64_t>(nrb - y0, kMaxGridY));
-        hipLaunchKernelGGL(k_split_mag, grid, dim3(256), 0, st, op, E, eoff, nkc, out, y0);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess)
-            return e;
-    }
-    return hipSuccess;
 }
 
 template <int MW>
