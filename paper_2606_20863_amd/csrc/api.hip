@@ -390,11 +390,19 @@ int choose_slices(const md_opts& o, int m, int64_t K, int T, const int32_t* stat
             return hip_fail(e);
         return MD_OK;
     }
-    int32_t h[kStatWords];
-    if ((e = hipMemcpyAsync(h, stats, sizeof(h), hipMemcpyDeviceToHost, st)) != hipSuccess)
+    // the statistics into pinned host memory (one small buffer per host
+    // thread, kept for the thread's life): no staging copy on the way
+    static thread_local int32_t* pinned = nullptr;
+    if (!pinned && (e = hipHostMalloc((void**)&pinned, kStatWords * sizeof(int32_t), hipHostMallocDefault)) != hipSuccess) {
+        pinned = nullptr;
+        return hip_fail(e);
+    }
+    if ((e = hipMemcpyAsync(pinned, stats, kStatWords * sizeof(int32_t), hipMemcpyDeviceToHost, st)) != hipSuccess)
         return hip_fail(e);
     if ((e = hipStreamSynchronize(st)) != hipSuccess)
         return hip_fail(e);
+    int32_t h[kStatWords];
+    memcpy(h, pinned, sizeof(h));
     c.span_A = h[0];
     c.span_B = h[1];
     c.G_span = h[0] + h[1] + 2;
