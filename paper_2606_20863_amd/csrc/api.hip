@@ -391,9 +391,10 @@ int choose_slices(const md_opts& o, int m, int64_t K, int T, const int32_t* stat
         return MD_OK;
     }
     // the statistics into pinned host memory (one small buffer per host
-    // thread, kept for the thread's life): no staging copy on the way
+    // thread, portable across devices, allocated at its first rule call and
+    // never released): no staging copy on the way
     static thread_local int32_t* pinned = nullptr;
-    if (!pinned && (e = hipHostMalloc((void**)&pinned, kStatWords * sizeof(int32_t), hipHostMallocDefault)) != hipSuccess) {
+    if (!pinned && (e = hipHostMalloc((void**)&pinned, kStatWords * sizeof(int32_t), hipHostMallocPortable)) != hipSuccess) {
         pinned = nullptr;
         return hip_fail(e);
     }
