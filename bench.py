@@ -306,7 +306,8 @@ def paper_inner_products(md, torch, steps=5):
 
 def other_configs(md, torch, steps=3, only=None):
     """The scope's other workloads, each timed as whole steps (inputs
-    resident): double-double 64^3 (per-call microseconds, eager and as a
+    resident; per form one warm-up step, then at least ``steps`` steps and
+    about 20 ms of them, at most 50): double-double 64^3 (per-call microseconds, eager and as a
     HIP graph replay); quad-double 1024^3 forward; double-double 2048^3 and
     octo-double 1024^3 forward + adjoint (C = A B, dA = W B^T, dB = A^T W:
     three products per step); hexa-double 1024^3 forward (leading words
@@ -355,10 +356,15 @@ def other_configs(md, torch, steps=3, only=None):
                 C, _ = md.gemm_ex(c["A"], c["B"], transA=c.get("transA", False),
                                   transB=c.get("transB", False), form=form)
             torch.cuda.synchronize()
-            _, evs = hip_events(steps * len(calls))
+            # at least `steps` steps and about 20 ms of them, at most 50 (the
+            # slice rule's read-back keeps the host in step with the device)
+            _, evs = hip_events(50 * len(calls))
             t0 = time.perf_counter()
             infos = []
-            for st in range(steps):
+            nst = 0
+            while nst < 50 and (nst < steps or time.perf_counter() - t0 < 0.02):
+                st = nst
+                nst += 1
                 for q, c in enumerate(calls):
                     Cq, info = md.gemm_ex(c["A"], c["B"], transA=c.get("transA", False),
                                           transB=c.get("transB", False), form=form,
@@ -371,15 +377,16 @@ def other_configs(md, torch, steps=3, only=None):
                         dB = Cq
                     infos.append(info)
             torch.cuda.synchronize()
-            ms = (time.perf_counter() - t0) * 1e3 / steps
-            kern = sum(elapsed_ms(hip, e) for e in evs) / steps
+            ms = (time.perf_counter() - t0) * 1e3 / nst
+            kern = sum(elapsed_ms(hip, e) for e in evs[:nst * len(calls)]) / nst
             for a, b in evs:
                 hip.hipEventDestroy(ctypes.c_void_p(a))
                 hip.hipEventDestroy(ctypes.c_void_p(b))
             ops = sum(2.0 * M * N * K * i["S"] * (i["S"] + 1) / 2 for i in infos[:len(calls)])
             peak = PEAK_FP64_TFLOPS if form == "fp64" else PEAK_INT8_TOPS
             row[form] = {"S": [i["S"] for i in infos[:len(calls)]], "beta": infos[0]["beta"],
-                         "ms_per_step": round(ms, 4), "effective_gflops": round(flop / (ms * 1e-3) / 1e9, 2),
+                         "steps": nst, "ms_per_step": round(ms, 4),
+                         "effective_gflops": round(flop / (ms * 1e-3) / 1e9, 2),
                          "contraction_fold_ms": round(kern, 4),
                          "frac_peak": round(ops / (kern * 1e-3) / 1e12 / peak, 4)}
             defer_error(row[form], "max_log2_err_sampled", Ah, Bh, C)
