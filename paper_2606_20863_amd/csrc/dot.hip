@@ -12,12 +12,14 @@ namespace {
 
 // min over the outputs of P_ij = sum_k qA_ik qB_kj, depth up to 2^11 depth
 // fragments (INT32 exact: one fragment adds below 64 * 127^2 < 2^20): a wave
-// computes a 64 x 64 block (4 x 4 fragments), a workgroup 128 x 128.  The
-// fragments of the next kMagDepth depth steps are in flight while the
-// current one multiplies.  Row or column blocks past the padded arrays read
-// through empty descriptors (zeros; those outputs are not counted).
-constexpr int kMagDepth = 4;
-
+// computes RX x CY fragments (16 RX x 16 CY outputs), a workgroup of four
+// waves 32 RX x 32 CY.  The fragments of the next D depth steps are in
+// flight while the current one multiplies.  A wave issues RX + CY fragment
+// loads for RX CY matrix instructions per step, so wider tiles relieve the
+// texture path once there are enough of them to fill the chip.  Row or
+// column blocks past the padded arrays read through empty descriptors
+// (zeros; those outputs are not counted).
+template <int RX, int CY, int D>
 __global__ __launch_bounds__(256) void k_mag_min_short(const v4i* __restrict__ qA,
                                                        const v4i* __restrict__ qB, int64_t M,
                                                        int64_t N, int64_t nkc,
@@ -25,52 +27,56 @@ __global__ __launch_bounds__(256) void k_mag_min_short(const v4i* __restrict__ q
 {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t rb0 = ((y0 + blockIdx.y) * 2 + (wave >> 1)) * 4;
-    const int64_t cb0 = ((int64_t)blockIdx.x * 2 + (wave & 1)) * 4;
+    const int64_t rb0 = ((y0 + blockIdx.y) * 2 + (wave >> 1)) * RX;
+    const int64_t cb0 = ((int64_t)blockIdx.x * 2 + (wave & 1)) * CY;
     const int64_t nrb = 2 * ((M + kTile - 1) / kTile), ncb = 2 * ((N + kTile - 1) / kTile);
     const uint64_t bytes = (uint64_t)nkc * 1024;
-    FragStream SA[4], SB[4];
+    FragStream SA[RX], SB[CY];
 #pragma unroll
-    for (int x = 0; x < 4; ++x) {
+    for (int x = 0; x < RX; ++x)
         SA[x] = frag_stream((const char*)qA + (rb0 + x) * bytes, rb0 + x < nrb ? bytes : 0, lane);
-        SB[x] = frag_stream((const char*)qB + (cb0 + x) * bytes, cb0 + x < ncb ? bytes : 0, lane);
-    }
-    v4i acc[4][4], pa[kMagDepth][4], pb[kMagDepth][4];
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
+    for (int y = 0; y < CY; ++y)
+        SB[y] = frag_stream((const char*)qB + (cb0 + y) * bytes, cb0 + y < ncb ? bytes : 0, lane);
+    v4i acc[RX][CY], pa[D][RX], pb[D][CY];
 #pragma unroll
-        for (int y = 0; y < 4; ++y)
+    for (int x = 0; x < RX; ++x)
+#pragma unroll
+        for (int y = 0; y < CY; ++y)
             acc[x][y] = v4i{0, 0, 0, 0};
 #pragma unroll
-    for (int d = 0; d < kMagDepth; ++d)
+    for (int d = 0; d < D; ++d) {
 #pragma unroll
-        for (int x = 0; x < 4; ++x) {
+        for (int x = 0; x < RX; ++x)
             pa[d][x] = SA[x](d * 1024u);
-            pb[d][x] = SB[x](d * 1024u);
-        }
-    for (int64_t kc = 0; kc < nkc; kc += kMagDepth) {
 #pragma unroll
-        for (int d = 0; d < kMagDepth; ++d) {
+        for (int y = 0; y < CY; ++y)
+            pb[d][y] = SB[y](d * 1024u);
+    }
+    for (int64_t kc = 0; kc < nkc; kc += D) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
             // depth steps past nkc read zeros and add nothing
 #pragma unroll
-            for (int x = 0; x < 4; ++x)
+            for (int x = 0; x < RX; ++x)
 #pragma unroll
-                for (int y = 0; y < 4; ++y)
+                for (int y = 0; y < CY; ++y)
                     acc[x][y] = __builtin_amdgcn_mfma_i32_16x16x64_i8(pa[d][x], pb[d][y], acc[x][y],
                                                                       0, 0, 0);
-            const uint32_t nxt = (uint32_t)(kc + d + kMagDepth) * 1024u;
+            const uint32_t nxt = (uint32_t)(kc + d + D) * 1024u;
 #pragma unroll
-            for (int x = 0; x < 4; ++x) {
+            for (int x = 0; x < RX; ++x)
                 pa[d][x] = SA[x](nxt);
-                pb[d][x] = SB[x](nxt);
-            }
+#pragma unroll
+            for (int y = 0; y < CY; ++y)
+                pb[d][y] = SB[y](nxt);
         }
     }
     unsigned long long best = ~0ull;
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
+    for (int x = 0; x < RX; ++x)
 #pragma unroll
-        for (int y = 0; y < 4; ++y)
+        for (int y = 0; y < CY; ++y)
 #pragma unroll
             for (int o = 0; o < 4; ++o) {
                 const int64_t i = (rb0 + x) * 16 + FormI8::row(lane, o);
@@ -306,14 +312,21 @@ struct DispatchDot<Form, 0> {
 hipError_t launch_mag_min(const void* qA, const void* qB, int64_t M, int64_t N, int64_t nkc,
                           unsigned long long* minP, hipStream_t st)
 {
-    const int64_t gx = (N + 127) / 128, ny = (M + 127) / 128;
+    // 256 x 256 outputs per workgroup where that still gives every compute
+    // unit one (4096^2 outputs and up), else 128 x 128
+    const bool wide = nkc <= 2048 && ((N + 255) / 256) * ((M + 255) / 256) >= 256;
+    const int64_t tile = wide ? 256 : 128;
+    const int64_t gx = (N + tile - 1) / tile, ny = (M + tile - 1) / tile;
     if (gx > 0x7fffffff)
         return hipErrorInvalidValue;
     for (int64_t y0 = 0; y0 < ny; y0 += 65535) {
         dim3 grid((unsigned)gx, (unsigned)std::min<int64_t>(ny - y0, 65535));
-        if (nkc <= 2048)
-            hipLaunchKernelGGL(k_mag_min_short, grid, dim3(256), 0, st, (const v4i*)qA, (const v4i*)qB,
-                               M, N, nkc, minP, y0);
+        if (wide)
+            hipLaunchKernelGGL((k_mag_min_short<8, 8, 2>), grid, dim3(256), 0, st, (const v4i*)qA,
+                               (const v4i*)qB, M, N, nkc, minP, y0);
+        else if (nkc <= 2048)
+            hipLaunchKernelGGL((k_mag_min_short<4, 4, 4>), grid, dim3(256), 0, st, (const v4i*)qA,
+                               (const v4i*)qB, M, N, nkc, minP, y0);
         else
             hipLaunchKernelGGL(k_mag_min, grid, dim3(256), 0, st, (const v4i*)qA, (const v4i*)qB, M, N,
                                nkc, minP, y0);
