@@ -183,7 +183,8 @@ def qd_mul(c: Counter, x, y):
 
 
 # ---------------------------------------------------------------------------
-# octo-double operations (m = 8): floating-point expansion arithmetic in the
+# octo-double operations (m = 8, and hexa-double, m = 16, the same algorithms
+# on 16 words): floating-point expansion arithmetic in the
 # manner of CAMPARY (Joldes, Muller, Popescu and Tucker; the paper's
 # reference for multiple double arithmetic of any length), built from the
 # same error-free transformations:
@@ -305,6 +306,17 @@ def od_mul(c: Counter, x, y):
     return md_mul_expansion(c, x, y, 8)
 
 
+def hd_add(c: Counter, x, y):
+    """Hexa-double addition (m = 16): the octo-double algorithm on 16 words,
+    merge of 32 words, then renormalise to 16."""
+    return renormalize(c, merge_by_magnitude(x, y), 16)
+
+
+def hd_mul(c: Counter, x, y):
+    """Hexa-double multiplication: the expansion product truncated at order 16."""
+    return md_mul_expansion(c, x, y, 16)
+
+
 def d_add(c: Counter, x, y):
     """Ordinary 1-double addition: one IEEE rounding."""
     return (c.add(x[0], y[0]),)
@@ -315,11 +327,12 @@ def d_mul(c: Counter, x, y):
     return (c.mul(x[0], y[0]),)
 
 
-ORDINARY = {1: (d_add, d_mul), 2: (dd_add, dd_mul), 4: (qd_add, qd_mul), 8: (od_add, od_mul)}
+ORDINARY = {1: (d_add, d_mul), 2: (dd_add, dd_mul), 4: (qd_add, qd_mul), 8: (od_add, od_mul),
+            16: (hd_add, hd_mul)}
 
 
 def ordinary_dot(c: Counter, xs, ys, m: int):
-    """sum_k x_k * y_k in ordinary m-double arithmetic (m = 1, 2, 4, 8): the
+    """sum_k x_k * y_k in ordinary m-double arithmetic (m = 1, 2, 4, 8, 16): the
     accumulator starts at zero and takes add(acc, mul(x_k, y_k)) for k in
     increasing order, each operation renormalised."""
     add, mul = ORDINARY[m]

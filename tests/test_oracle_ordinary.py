@@ -15,12 +15,16 @@ baseline, Section 1, Table 1) against exact arithmetic.
   (every 0/1 input with sorted halves, and random ones); dropping the
   TwoProd errors of the order-6 products (terms of order 7) would cost
   about 2^-370;
+* hexa-double addition and multiplication (the same expansion algorithms
+  on 16 words) stay within 2^-824 of the exact sum and product, carry
+  octo-doubles to octo-double accuracy, and the merge network of 16 sorts;
 * the lane-order inner product (the batched GPU kernel's order) with one
   lane is the sequential one, and with 64 lanes meets the same bound;
 * operation counts beside Table 1: double-double addition 20 (pinned in
   test_oracle.py); quad-double addition 85 and multiplication 194 against
   the table's 89 and 336, octo-double 135 and 1769 against 269 and 1742,
-  whose algorithms the paper does not name (reported, parity unpinned).
+  hexa-double 279 and 10901 against 925 and 11499, whose algorithms the
+  paper does not name (reported, parity unpinned).
 """
 from fractions import Fraction
 
@@ -91,7 +95,7 @@ def test_qd_ops_on_double_doubles():
         assert abs(val(p) - val(q)) <= Fraction(2) ** -100 * ref
 
 
-@pytest.mark.parametrize("m", [1, 2, 4, 8])
+@pytest.mark.parametrize("m", [1, 2, 4, 8, 16])
 def test_ordinary_dot_bound(m):
     r = rng(10 + m)
     K = 64
@@ -144,6 +148,9 @@ def test_op_counts_beside_table1():
     # octo-double expansion arithmetic beside the table's 269 and 1742
     assert ma.op_count(ma.od_add, 8) == 135
     assert ma.op_count(ma.od_mul, 8) == 1769
+    # hexa-double, beside the table's 925 and 11499
+    assert ma.op_count(ma.hd_add, 16) == 279
+    assert ma.op_count(ma.hd_mul, 16) == 10901
 
 
 def od_samples(n, seed, lead=("log2uniform", 20.0)):
@@ -213,7 +220,7 @@ def test_od_ops_on_quad_doubles():
         assert val(ma.od_add(ma.Counter(), x, (0.0,) * 8)) == val(x)
 
 
-@pytest.mark.parametrize("m", [1, 2, 4, 8])
+@pytest.mark.parametrize("m", [1, 2, 4, 8, 16])
 def test_lane_order_dot(m):
     r = rng(50 + m)
     K = 200
@@ -232,3 +239,67 @@ def test_lane_order_dot(m):
     acc = [ma.ordinary_dot(c, xs[l::4], ys[l::4], m) for l in range(4)]
     want = add(c, add(c, acc[0], acc[2]), add(c, acc[1], acc[3]))
     assert ma.ordinary_dot_lanes(ma.Counter(), xs, ys, m, lanes=4) == want
+
+
+def hd_samples(n, seed, lead=("log2uniform", 20.0)):
+    return mdinputs.mdouble(rng(seed), 16, (n,), lead)
+
+
+def test_merge_network_sorts_sixteen():
+    """The merge of two sorted runs of 16 (the hexa-double addition): every
+    0/1 input whose halves are sorted."""
+    pairs = ma.odd_even_merge(16)
+    for a in range(17):
+        for b in range(17):
+            z = [1] * a + [0] * (16 - a) + [1] * b + [0] * (16 - b)
+            for i, j in pairs:
+                if z[i] < z[j]:
+                    z[i], z[j] = z[j], z[i]
+            assert z == sorted(z, reverse=True)
+
+
+def test_hd_add_accuracy():
+    X = hd_samples(120, 61)
+    Y = hd_samples(120, 62)
+    Y[0, :40] = -X[0, :40]                # the leading words cancel
+    Y[:, 40:60] = 0.0                     # a zero operand
+    worst = Fraction(0)
+    for i in range(120):
+        x, y = tuple(X[:, i]), tuple(Y[:, i])
+        s = ma.hd_add(ma.Counter(), x, y)
+        assert ox.is_nonoverlapping(s, strong=False)
+        err = abs(val(s) - (val(x) + val(y)))
+        worst = max(worst, err / (abs(val(x)) + abs(val(y))))
+    assert worst <= Fraction(2) ** -824, float(worst)
+
+
+def test_hd_mul_accuracy():
+    X = hd_samples(120, 63)
+    Y = hd_samples(120, 64)
+    worst = Fraction(0)
+    for i in range(120):
+        x, y = tuple(X[:, i]), tuple(Y[:, i])
+        p = ma.hd_mul(ma.Counter(), x, y)
+        assert ox.is_nonoverlapping(p, strong=False)
+        err = abs(val(p) - val(x) * val(y))
+        worst = max(worst, err / abs(val(x) * val(y)))
+    assert worst <= Fraction(2) ** -824, float(worst)
+
+
+def test_hd_ops_on_octo_doubles():
+    """Hexa-doubles whose eight trailing words are zero: sums and products
+    agree with the octo-double operations to octo-double accuracy, and a zero
+    hexa-double added changes nothing."""
+    X = hd_samples(40, 65)
+    Y = hd_samples(40, 66)
+    X[8:] = 0.0
+    Y[8:] = 0.0
+    for i in range(40):
+        x, y = tuple(X[:, i]), tuple(Y[:, i])
+        ref = abs(val(x)) + abs(val(y))
+        assert abs(val(ma.hd_add(ma.Counter(), x, y)) - val(ma.od_add(ma.Counter(), x[:8], y[:8]))) <= \
+            Fraction(2) ** -412 * ref
+        ref = abs(val(x) * val(y))
+        assert abs(val(ma.hd_mul(ma.Counter(), x, y)) - val(ma.od_mul(ma.Counter(), x[:8], y[:8]))) <= \
+            Fraction(2) ** -412 * ref
+        assert val(ma.hd_add(ma.Counter(), x, (0.0,) * 16)) == val(x)
