@@ -282,7 +282,8 @@ int md_gemm_ordinary(int m, int64_t M, int64_t N, int64_t K, const double *A, co
 /*
  * Batched inner products in ordinary m-double arithmetic (the "ordinary"
  * side of the paper's experiment, Section 3, Table 2): out_b = sum_k
- * x_bk y_bk with md_gemm_ordinary's operations, m = 1, 2, 4 or 8.  Order:
+ * x_bk y_bk with md_gemm_ordinary's operations, m = 1, 2, 4 or 8, and
+ * m = 16 (the octo-double expansion arithmetic on 16 words).  Order:
  * 64 partial sums per pair, sum l accumulating add(acc, mul(x_k, y_k)) over
  * k = l, l + 64, l + 128, .. from zero, then pairwise, sum l < h taking
  * add(sum_l, sum_(l+h)) for h = 32, 16, .., 1.  Dense planes as md_dot (X

@@ -441,8 +441,8 @@ def gemm_ordinary(A: torch.Tensor, B: torch.Tensor, stream=None) -> torch.Tensor
 
 def dot_ordinary(X: torch.Tensor, Y: torch.Tensor, stream=None) -> torch.Tensor:
     """Batched inner products in ordinary m-double arithmetic (m = 1, 2, 4,
-    8) of (m, batch, n) planes, 64 partial sums per pair met pairwise: the
-    comparison baseline of ``dot``, not error-free."""
+    8, 16) of (m, batch, n) planes, 64 partial sums per pair met pairwise:
+    the comparison baseline of ``dot``, not error-free."""
     _check_planes(X, "X")
     _check_planes(Y, "Y")
     X = X.contiguous()

@@ -1173,7 +1173,7 @@ int md_dot_ordinary(int m, int64_t batch, int64_t n, const double* X, const doub
                     void* stream)
 {
     g_last_hip = 0;
-    if (m != 1 && m != 2 && m != 4 && m != 8)
+    if (m != 1 && m != 2 && m != 4 && m != 8 && m != 16)
         return MD_EINVAL_M;
     if (batch < 0 || n < 0 || batch > (INT64_C(1) << 40) || n > (INT64_C(1) << 40) || !mul_ok(batch, n))
         return MD_EINVAL_DIM;

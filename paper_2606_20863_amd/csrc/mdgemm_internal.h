@@ -272,10 +272,13 @@ hipError_t launch_fixed_round(int m, int64_t count, int nlimb, const int32_t* X,
 // ordinary m-double product (m = 1, 2, 4, 8) of dense planes
 hipError_t launch_ordinary(int m, const double* A, const double* B, double* C, int64_t M,
                            int64_t N, int64_t K, hipStream_t st);
-// batched ordinary inner products (m = 1, 2, 4, 8): dense planes X, Y of
-// batch x n, out with plane stride pso; one wave per pair
+// batched ordinary inner products (m = 1, 2, 4, 8, 16): dense planes X, Y
+// of batch x n, out with plane stride pso; one wave per pair
 hipError_t launch_ordinary_dot(int m, const double* X, const double* Y, double* out, int64_t pso,
                                int64_t batch, int64_t n, hipStream_t st);
+// the same for m = 16 (a unit of its own)
+hipError_t launch_ordinary_dot16(const double* X, const double* Y, double* out, int64_t pso, int64_t batch,
+                                 int64_t n, hipStream_t st);
 // min over pairs of sum_k qX_bk qY_bk into *minP (atomic min)
 hipError_t launch_mag_min_diag(const void* qX, const void* qY, int64_t batch, int64_t nkc,
                                unsigned long long* minP, hipStream_t st);
